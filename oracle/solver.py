@@ -1,0 +1,276 @@
+"""Oracle: M-IHS for ridge regression, step by step, in float64 on the CPU.
+
+TEST INFRASTRUCTURE ONLY.  Only tests, the smoke check and the benchmark's CPU
+baseline call this module; the GPU library shares no code with it.
+
+Problem (Section 1, eq. (intro)):  x* = argmin 1/2 ||Ax - b||^2 + lambda/2 ||x||^2,
+whose plain definition is x* = (A^T A + lambda I)^{-1} A^T b.
+
+M-IHS (Section 3, eq. (mihs1) and Algorithm 1), with one sketch S for all
+iterations:
+    g^i      = A^T (b - A x^i) - lambda x^i
+    dx^i     = argmin ||S A z||^2 + lambda ||z||^2 - 2 <g^i, z>
+             = ((SA)^T SA + lambda I)^{-1} g^i            (solved inexactly)
+    x^{i+1}  = x^i + alpha dx^i + beta (x^i - x^{i-1}),   x^0 = x^1.
+(eq. (mihs1) writes the linear term with grad f = -g; the minimiser above is
+the same step.)  Momentum: Corollary 4 (beta = sd/m, alpha = (1-beta)^2) or
+Theorem 1 (beta*, alpha* from the embedding accuracy epsilon).
+
+Inner solvers: exact (Cholesky of the d x d sketched Hessian), conjugate
+gradients stopped on the relative residual eps_sub (Section 3.1's constant
+forcing term), and AAb_Solver (Algorithm 6, Section 3.5).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, List, Optional, Tuple
+
+import numpy as np
+import scipy.linalg as sla
+
+
+# ----------------------------------------------------------------------------
+# Closed forms
+# ----------------------------------------------------------------------------
+def ridge_cholesky(A: np.ndarray, b: np.ndarray, lam: float) -> np.ndarray:
+    """x* = (A^T A + lambda I)^{-1} A^T b by a dense Cholesky factorisation."""
+    A64 = A.astype(np.float64, copy=False)
+    H = A64.T @ A64 + lam * np.eye(A.shape[1])
+    c = sla.cho_factor(H, lower=True)
+    return sla.cho_solve(c, A64.T @ b)
+
+
+def ridge_lstsq(A: np.ndarray, b: np.ndarray, lam: float) -> np.ndarray:
+    """x* as the least-squares solution of [A; sqrt(lambda) I] x = [b; 0]
+    (Householder QR via LAPACK; avoids squaring the condition number)."""
+    n, d = A.shape
+    M = np.vstack([A.astype(np.float64), math.sqrt(lam) * np.eye(d)])
+    rhs = np.concatenate([b, np.zeros((d,) + b.shape[1:])])
+    return np.linalg.lstsq(M, rhs, rcond=None)[0]
+
+
+def statistical_dimension(A: np.ndarray, lam: float) -> float:
+    """sd_lambda(A) = tr(A (A^T A + lambda I)^{-1} A^T) = sum sigma_i^2/(sigma_i^2+lambda) (Section 1)."""
+    s = np.linalg.svd(A.astype(np.float64), compute_uv=False)
+    return float(np.sum(s * s / (s * s + lam)))
+
+
+# ----------------------------------------------------------------------------
+# Momentum parameters
+# ----------------------------------------------------------------------------
+def momentum_cor4(sd: float, m: int) -> Tuple[float, float]:
+    """Corollary 4: beta = sd/m, alpha = (1 - beta)^2; rate sqrt(beta)."""
+    beta = sd / m
+    if not 0.0 < beta < 1.0:
+        raise ValueError("need 0 < sd < m")
+    return (1.0 - beta) ** 2, beta
+
+
+def momentum_thm1(eps: float) -> Tuple[float, float]:
+    """Theorem 1: beta* = (eps / (1 + sqrt(1-eps^2)))^2, alpha* = (1 - beta*) sqrt(1 - eps^2)."""
+    if not 0.0 < eps < 1.0:
+        raise ValueError("need 0 < eps < 1")
+    beta = (eps / (1.0 + math.sqrt(1.0 - eps * eps))) ** 2
+    return (1.0 - beta) * math.sqrt(1.0 - eps * eps), beta
+
+
+def heavy_ball_rate(mu: np.ndarray, alpha: float, beta: float) -> float:
+    """Spectral radius of the two-term recursion for eigenvalues mu of
+    (sketched Hessian)^{-1} (Hessian): largest root modulus of
+    u^2 - (1 + beta - alpha mu) u + beta = 0 (eq. (characteristic))."""
+    worst = 0.0
+    for m_ in np.atleast_1d(mu):
+        roots = np.roots([1.0, -(1.0 + beta - alpha * m_), beta])
+        worst = max(worst, float(np.max(np.abs(roots))))
+    return worst
+
+
+def iterations_cor4(eta: float, beta: float) -> int:
+    """Corollary 4: at most log(eta) / log(sqrt(beta)) iterations."""
+    return int(math.ceil(math.log(eta) / math.log(math.sqrt(beta))))
+
+
+# ----------------------------------------------------------------------------
+# Gradient (Algorithm 1, the per-iteration pass over A)
+# ----------------------------------------------------------------------------
+def gradient(A: np.ndarray, b: np.ndarray, lam: float, x: np.ndarray) -> np.ndarray:
+    """g = A^T (b - A x) - lambda x, FP32 A upcast exactly to FP64."""
+    A64 = A.astype(np.float64, copy=False)
+    return A64.T @ (b - A64 @ x) - lam * x
+
+
+def gradient_rhs(A: np.ndarray, rhs: np.ndarray, lam: float, w: np.ndarray) -> np.ndarray:
+    """Gradient of the adjoint system (A^T A + lambda I) w = rhs: rhs - A^T A w - lambda w."""
+    A64 = A.astype(np.float64, copy=False)
+    return rhs - A64.T @ (A64 @ w) - lam * w
+
+
+# ----------------------------------------------------------------------------
+# Inner solvers for ((SA)^T SA + lambda I) z = g
+# ----------------------------------------------------------------------------
+def inner_exact_factory(SA: np.ndarray, lam: float) -> Callable[[np.ndarray], Tuple[np.ndarray, int]]:
+    SA64 = SA.astype(np.float64, copy=False)
+    c = sla.cho_factor(SA64.T @ SA64 + lam * np.eye(SA.shape[1]), lower=True)
+    return lambda g: (sla.cho_solve(c, g), 0)
+
+
+def inner_cg(SA: np.ndarray, g: np.ndarray, lam: float, eps: float,
+             max_iter: Optional[int] = None) -> Tuple[np.ndarray, int]:
+    """Conjugate gradients from z = 0 on (SA^T SA + lambda I) z = g, the operator
+    applied as SA^T (SA p) + lambda p; stops once ||r|| <= eps ||g||."""
+    SA64 = SA.astype(np.float64, copy=False)
+    d = g.shape[0]
+    max_iter = max_iter if max_iter is not None else 10 * d
+    z = np.zeros_like(g)
+    r = g.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    stop = (eps * eps) * rr
+    k = 0
+    while rr > stop and k < max_iter:
+        q = SA64.T @ (SA64 @ p) + lam * p
+        a = rr / float(p @ q)
+        z += a * p
+        r -= a * q
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        k += 1
+    return z, k
+
+
+def aab_solver(M: np.ndarray, b: np.ndarray, lam: float, eps: float,
+               max_iter: Optional[int] = None, trace: Optional[list] = None) -> Tuple[np.ndarray, int]:
+    """AAb_Solver (Algorithm 6) for (M^T M + lambda I) x = b.
+
+    Upper bidiagonalisation started from theta_1 v = b; the sqrt(lambda) block is
+    folded in by Givens rotations (Section 3.5): c = rho/rhobar,
+    s = lambdabar/rhobar, thetabar = c theta, lambdabar^2 = lambda + (s theta)^2,
+    rhobar = sqrt(rho^2 + lambdabar^2), starting from lambdabar_1 = sqrt(lambda).
+    The first-step sine is therefore sqrt(lambda)/rhobar (the listing's
+    sqrt(lambda/rhobar) contradicts the recurrence it implements; the text's
+    recurrence is followed).  Stops on |phi rhobar| / theta_1 < eps, the
+    relative residual norm of the previous iterate.  If `trace` is a list, it
+    receives (x, t) after every step (the initial iterate with t = inf first).
+    """
+    M64 = M.astype(np.float64, copy=False)
+    max_iter = max_iter if max_iter is not None else 10 * M.shape[1]
+    theta1 = float(np.linalg.norm(b))
+    if theta1 == 0.0:
+        return np.zeros_like(b), 0
+    v = b / theta1
+    pv = M64 @ v
+    rho = float(np.linalg.norm(pv))
+    p = pv / rho
+    rhobar = math.sqrt(rho * rho + lam)
+    c = rho / rhobar
+    s = math.sqrt(lam) / rhobar
+    phi = theta1 / rhobar
+    dvec = v / rhobar
+    x = phi * dvec
+    t = math.inf
+    k = 0
+    if trace is not None:
+        trace.append((x.copy(), t))
+    while t >= eps and k < max_iter:
+        w = M64.T @ p - rho * v
+        theta = float(np.linalg.norm(w))
+        v = w / theta
+        w2 = M64 @ v - theta * p
+        rho = float(np.linalg.norm(w2))
+        p = w2 / rho
+        lbar = math.sqrt(lam + (s * theta) ** 2)
+        thetabar = c * theta
+        rhobar = math.sqrt(rho * rho + lbar * lbar)
+        c = rho / rhobar
+        s = lbar / rhobar
+        dvec = (v - thetabar * dvec) / rhobar
+        phi = -phi * thetabar / rhobar
+        x = x + phi * dvec
+        t = abs(phi * rhobar) / theta1
+        k += 1
+        if trace is not None:
+            trace.append((x.copy(), t))
+    return x, k
+
+
+# ----------------------------------------------------------------------------
+# M-IHS outer loop
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class MihsResult:
+    x: np.ndarray
+    outer: int
+    inner: List[int]
+    steps: List[float]
+    converged: bool
+    history: Optional[List[np.ndarray]] = None
+
+
+def stop_threshold(tol: float, beta: float) -> float:
+    """Relative-step threshold for the stop test: with contraction rate
+    rho = sqrt(beta), ||x^{i+1} - x*|| <= rho/(1-rho) ||x^{i+1} - x^i||, so the
+    iteration stops when ||x^{i+1}-x^i|| / ||x^{i+1}|| <= tol (1-rho)/rho."""
+    rho = math.sqrt(beta)
+    return tol * (1.0 - rho) / rho
+
+
+def mihs(A: np.ndarray, b: np.ndarray, lam: float, SA: np.ndarray, alpha: float, beta: float,
+         *, inner: str = "cg", eps_sub: float = 1e-2, max_inner: Optional[int] = None,
+         n_iter: Optional[int] = None, tol: Optional[float] = None, max_outer: int = 500,
+         x1: Optional[np.ndarray] = None, keep_history: bool = False,
+         rhs_mode: bool = False) -> MihsResult:
+    """M-IHS (Algorithm 1).  Runs exactly `n_iter` iterations if given, else
+    stops on the relative-step rule with target `tol` (or at `max_outer`).
+
+    rhs_mode=True solves (A^T A + lambda I) x = b for a d-vector b (the adjoint
+    system of the backward pass): the gradient becomes b - A^T A x - lambda x.
+    """
+    d = A.shape[1]
+    x = np.zeros(d) if x1 is None else np.array(x1, dtype=np.float64)
+    x_prev = x.copy()
+    exact = inner_exact_factory(SA, lam) if inner == "exact" else None
+    inner_counts: List[int] = []
+    steps: List[float] = []
+    hist = [x.copy()] if keep_history else None
+    thr = stop_threshold(tol, beta) if tol is not None else None
+    limit = n_iter if n_iter is not None else max_outer
+    converged = False
+    it = 0
+    for it in range(1, limit + 1):
+        g = gradient_rhs(A, b, lam, x) if rhs_mode else gradient(A, b, lam, x)
+        if inner == "exact":
+            dx, k = exact(g)
+        elif inner == "cg":
+            dx, k = inner_cg(SA, g, lam, eps_sub, max_inner)
+        elif inner == "aab":
+            dx, k = aab_solver(SA, g, lam, eps_sub, max_inner)
+        else:
+            raise ValueError(inner)
+        inner_counts.append(k)
+        x_new = x + alpha * dx + beta * (x - x_prev)
+        nrm = float(np.linalg.norm(x_new))
+        step = float(np.linalg.norm(x_new - x)) / nrm if nrm > 0 else 0.0
+        steps.append(step)
+        x_prev, x = x, x_new
+        if keep_history:
+            hist.append(x.copy())
+        if thr is not None and n_iter is None and step <= thr:
+            converged = True
+            break
+    return MihsResult(x=x, outer=it, inner=inner_counts, steps=steps, converged=converged,
+                      history=hist)
+
+
+# ----------------------------------------------------------------------------
+# Backward of the ridge solution (differentiation workload)
+# ----------------------------------------------------------------------------
+def ridge_backward_dense(A: np.ndarray, lam: float, xstar: np.ndarray, gbar: np.ndarray):
+    """For L(x*(B, lambda)) with dL/dx* = gbar (d x k):
+    W = (A^T A + lambda I)^{-1} gbar, dL/dB = A W, dL/dlambda = -sum_j x*_j^T w_j."""
+    A64 = A.astype(np.float64, copy=False)
+    H = A64.T @ A64 + lam * np.eye(A.shape[1])
+    c = sla.cho_factor(H, lower=True)
+    W = sla.cho_solve(c, gbar)
+    return W, A64 @ W, -float(np.sum(xstar * W))

@@ -1,0 +1,209 @@
+"""Pins of the oracle's solver against closed forms, invariants and the paper's
+printed numbers."""
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+import workloads as W
+from conftest import read_golden
+from oracle import sketches, solver as O
+
+
+def _small(n=600, d=40, sd=12.0, seed=11, rate=6.0):
+    sig = W.sigma_profile("exp", d, rate)
+    return W.make_problem(n, d, sig, sd, seed)
+
+
+def test_closed_forms_agree_with_svd_filter_form():
+    P = _small()
+    xc = O.ridge_cholesky(P.A, P.b, P.lam)
+    xq = O.ridge_lstsq(P.A, P.b, P.lam)
+    # Tikhonov filter-factor form of the same solution (proof of Corollary 4)
+    U, s, Vt = np.linalg.svd(P.A, full_matrices=False)
+    xf = Vt.T @ ((s * s / (s * s + P.lam)) * (U.T @ P.b) / s)
+    for x in (xc, xq):
+        assert np.linalg.norm(x - xf) <= 1e-12 * np.linalg.norm(xf)
+    # optimality: gradient of the ridge objective vanishes
+    g = O.gradient(P.A, P.b, P.lam, xf)
+    assert np.linalg.norm(g) <= 1e-12 * np.linalg.norm(P.A.T @ P.b)
+
+
+def test_statistical_dimension_definition():
+    P = _small()
+    H = P.A.T @ P.A + P.lam * np.eye(P.A.shape[1])
+    tr = np.trace(P.A @ np.linalg.solve(H, P.A.T))
+    assert abs(O.statistical_dimension(P.A, P.lam) - tr) < 1e-9
+
+
+def test_one_step_with_identity_sketch():
+    """S = I (m = n), exact inner solve, alpha = 1, beta = 0: the first M-IHS
+    step is a Newton step on a quadratic and lands on x*."""
+    P = _small()
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    r = O.mihs(P.A, P.b, P.lam, P.A, 1.0, 0.0, inner="exact", n_iter=1)
+    assert np.linalg.norm(r.x - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+def test_theorem1_momentum_identities():
+    for eps in (0.05, 0.3, 0.5, 0.9):
+        a, b = O.momentum_thm1(eps)
+        assert math.isclose(a, 4 * (1 - eps**2) / (math.sqrt(1 + eps) + math.sqrt(1 - eps)) ** 2,
+                            rel_tol=1e-12)
+        # sqrt(beta*) minimises over alpha the worse of the two extreme root moduli
+        f = lambda al: max(1 - math.sqrt(al) / math.sqrt(1 + eps),
+                           math.sqrt(al) / math.sqrt(1 - eps) - 1)
+        res = scipy.optimize.minimize_scalar(f, bounds=(1e-6, 4.0), method="bounded",
+                                             options={"xatol": 1e-12})
+        assert math.isclose(res.fun, math.sqrt(b), rel_tol=1e-6, abs_tol=1e-9)
+        assert math.isclose(res.x, a, rel_tol=1e-4)
+        # every mu in [1/(1+eps), 1/(1-eps)] is under-damped: root modulus sqrt(beta)
+        mus = np.linspace(1 / (1 + eps), 1 / (1 - eps), 7)
+        assert O.heavy_ball_rate(mus, a, b) <= math.sqrt(b) * (1 + 1e-6)
+
+
+def test_cor4_matches_paper_worked_number():
+    """Figure 2's caption: kappa(A) (1/sqrt 2)^100 = 9e-8 with sd = 2000, m = 4000."""
+    for name, sd, m, N, C, printed in read_golden("paper_worked_numbers.txt"):
+        a, b = O.momentum_cor4(float(sd), int(m))
+        bound = float(C) * math.sqrt(b) ** int(N)
+        assert abs(bound - float(printed)) / float(printed) < 0.02
+        assert math.isclose(a, (1 - b) ** 2)
+
+
+def test_rate_matches_characteristic_polynomial():
+    """With an exact inner solve the error contracts at the spectral radius given
+    by eq. (characteristic) over the eigenvalues of H_s^{-1} H, close to sqrt(beta)."""
+    w = W.workload("small_gauss")
+    P = w.draw()
+    SA = sketches.gaussian_sketch(P.A, w.m, w.sketch_seed)
+    a, b = O.momentum_cor4(w.sd_target, w.m)
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    r = O.mihs(P.A, P.b, P.lam, SA, a, b, inner="exact", n_iter=40, keep_history=True)
+    errs = np.array([np.linalg.norm(x - xs) for x in r.history])
+    emp = (errs[35] / errs[15]) ** (1 / 20)
+    H = P.A.T @ P.A + P.lam * np.eye(P.A.shape[1])
+    Hs = SA.T @ SA + P.lam * np.eye(P.A.shape[1])
+    mu = np.linalg.eigvals(np.linalg.solve(Hs, H)).real
+    pred = O.heavy_ball_rate(mu, a, b)
+    assert abs(emp - pred) < 0.03
+    assert abs(emp - math.sqrt(b)) < 0.05
+    # Corollary 4 iteration bound is not exceeded by much at this size
+    assert np.argmax(errs / errs[0] < 1e-10) <= O.iterations_cor4(1e-10, b) + 5
+
+
+def test_inner_solvers_agree_with_exact():
+    P = _small(d=60, sd=20.0)
+    SA = sketches.gaussian_sketch(P.A, 120, 3)
+    g = O.gradient(P.A, P.b, P.lam, np.zeros(60))
+    ex, _ = O.inner_exact_factory(SA, P.lam)(g)
+    Hs = SA.T @ SA + P.lam * np.eye(60)
+    for fn in (O.inner_cg, O.aab_solver):
+        z, k = fn(SA, g, P.lam, 1e-12)
+        assert np.linalg.norm(z - ex) <= 1e-9 * np.linalg.norm(ex)
+        z, k = fn(SA, g, P.lam, 1e-2)
+        assert k > 0
+        # relative residual respected (AAb's test lags one iterate, so it is conservative)
+        assert np.linalg.norm(Hs @ z - g) <= 1e-2 * np.linalg.norm(g) * 1.0001
+
+
+def test_aab_residual_identity():
+    """Section 3.5: ||(M^T M + lambda I) x^k - b|| = |phi_k thetabar_{k+1}|, so the
+    stopping quantity t after a step is the true relative residual of the iterate
+    before that step."""
+    rng = np.random.default_rng(8)
+    M = rng.standard_normal((50, 20))
+    bvec = rng.standard_normal(20)
+    lam = 0.3
+    H = M.T @ M + lam * np.eye(20)
+    tr = []
+    O.aab_solver(M, bvec, lam, 0.0, max_iter=10, trace=tr)
+    for j in range(1, len(tr)):
+        xprev = tr[j - 1][0]
+        res = np.linalg.norm(H @ xprev - bvec) / np.linalg.norm(bvec)
+        assert math.isclose(res, tr[j][1], rel_tol=1e-7)
+
+
+@pytest.mark.parametrize("inner", ["exact", "cg", "aab"])
+def test_mihs_small_workload_reaches_1e_10(inner):
+    w = W.workload("small_gauss")
+    P = w.draw()
+    SA = sketches.gaussian_sketch(P.A, w.m, w.sketch_seed)
+    a, b = O.momentum_cor4(w.sd_target, w.m)
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    r = O.mihs(P.A, P.b, P.lam, SA, a, b, inner=inner, eps_sub=w.eps_sub, tol=1e-10)
+    assert r.converged
+    assert np.linalg.norm(r.x - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert r.outer <= O.iterations_cor4(1e-10, b) + 8
+
+
+def test_sketch_independence():
+    """x* does not depend on S: different sketch families reach the same point."""
+    P = _small(n=1024, d=48, sd=16.0)
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    for kind, m in (("gaussian", 96), ("srht", 128), ("countsketch", 256)):
+        SA = sketches.sketch(P.A, kind, m, 5)
+        a, b = O.momentum_cor4(16.0, m)
+        r = O.mihs(P.A, P.b, P.lam, SA, a, b, inner="cg", eps_sub=1e-3, tol=1e-12, max_outer=400)
+        assert np.linalg.norm(r.x - xs) <= 1e-11 * np.linalg.norm(xs), kind
+
+
+def test_adjoint_mode_solves_hessian_system():
+    P = _small()
+    rng = np.random.default_rng(1)
+    gbar = rng.standard_normal(P.A.shape[1])
+    SA = sketches.gaussian_sketch(P.A, 80, 2)
+    a, b = O.momentum_cor4(12.0, 80)
+    r = O.mihs(P.A, gbar, P.lam, SA, a, b, inner="cg", eps_sub=1e-6, tol=1e-12, rhs_mode=True)
+    H = P.A.T @ P.A + P.lam * np.eye(P.A.shape[1])
+    w = np.linalg.solve(H, gbar)
+    assert np.linalg.norm(r.x - w) <= 1e-10 * np.linalg.norm(w)
+
+
+def test_backward_matches_finite_differences():
+    """dL/dB and dL/dlog(lambda) of L = sum_j ||C x*_j - y_j||^2 against central
+    differences of dense forward solves (L is quadratic in B, so the B-difference
+    is exact up to rounding)."""
+    rng = np.random.default_rng(6)
+    n, d, k = 200, 12, 3
+    A = rng.standard_normal((n, d))
+    B = rng.standard_normal((n, k))
+    C = rng.standard_normal((5, d))
+    Y = rng.standard_normal((5, k))
+    loglam = math.log(0.7)
+
+    def loss(Bm, ll):
+        X = O.ridge_cholesky(A, Bm, math.exp(ll))
+        return float(np.sum((C @ X - Y) ** 2))
+
+    lam = math.exp(loglam)
+    X = O.ridge_cholesky(A, B, lam)
+    gbar = 2 * C.T @ (C @ X - Y)
+    W_, dB, dlam = O.ridge_backward_dense(A, lam, X, gbar)
+    h = 1e-6
+    for _ in range(3):
+        V = rng.standard_normal((n, k))
+        fd = (loss(B + h * V, loglam) - loss(B - h * V, loglam)) / (2 * h)
+        assert abs(fd - np.sum(dB * V)) <= 1e-6 * max(1.0, abs(fd))
+    fd = (loss(B, loglam + h) - loss(B, loglam - h)) / (2 * h)
+    assert abs(fd - lam * dlam) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    """A wrong sign in the gradient or a swapped momentum pair must break the
+    closed-form pin: shows the pins are not vacuous."""
+    P = _small()
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    SA = sketches.gaussian_sketch(P.A, 80, 2)
+    a, b = O.momentum_cor4(12.0, 80)
+    good = O.mihs(P.A, P.b, P.lam, SA, a, b, inner="exact", n_iter=60)
+    assert np.linalg.norm(good.x - xs) <= 1e-10 * np.linalg.norm(xs)
+    orig = O.gradient
+    monkeypatch.setattr(O, "gradient", lambda A, bb, lam, x: orig(A, bb, -lam, x))
+    bad = O.mihs(P.A, P.b, P.lam, SA, a, b, inner="exact", n_iter=60)
+    assert np.linalg.norm(bad.x - xs) > 1e-6 * np.linalg.norm(xs)
+    monkeypatch.setattr(O, "gradient", orig)
+    bad2 = O.mihs(P.A, P.b, P.lam, SA, b, a, inner="exact", n_iter=60)  # alpha <-> beta
+    e2 = np.linalg.norm(bad2.x - xs) / np.linalg.norm(xs)
+    assert e2 > 1e-8 or not np.isfinite(e2)

@@ -1,0 +1,214 @@
+/*
+ * mihs.h - C ABI of libmihs, an MI355X (gfx950) implementation of Momentum
+ * Iterative Hessian Sketch (M-IHS) for tall ridge regression
+ *
+ *     x* = argmin_x  1/2 ||A x - b||^2 + lambda/2 ||x||^2,   A is n x d, n >= d
+ *
+ * (Ozaslan, Pilanci, Arikan, "M-IHS: Momentum Iterative Hessian Sketch",
+ * arXiv:1912.03514; Section 1 eq. (intro), Section 3 eq. (mihs1), Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrices are row-major.  `lda`/`ldsa`/`ldb` count elements between
+ *   consecutive rows and must be >= the row length.  Matrix base pointers must
+ *   be 16-byte aligned and the leading dimension a multiple of 16 bytes / the
+ *   element size (2 for double, 4 for float); this keeps every row 16-byte
+ *   aligned for vector loads.
+ * - Pointers documented as "device" must point to device memory of the handle's
+ *   GPU; "host" pointers to host memory.  The caller owns every buffer; the
+ *   library allocates nothing inside mihs_sketch / mihs_solve /
+ *   mihs_solve_batched / mihs_solve_backward (scratch comes from the
+ *   caller's `workspace`, whose size the *_workspace_size queries return).
+ * - Every call is asynchronous on `stream` (a hipStream_t; NULL = the default
+ *   stream).  The return value reports argument and launch errors only:
+ *       MIHS_OK (0), MIHS_ERR_INVALID (-1), MIHS_ERR_WORKSPACE (-2),
+ *       MIHS_ERR_HIP (-3), MIHS_ERR_UNSUPPORTED (-4).
+ *   Numerical outcomes are written to a device-side mihs_info_t, readable after
+ *   the stream synchronises: status MIHS_CONVERGED (0), MIHS_MAX_ITER (1,
+ *   result still usable), MIHS_BREAKDOWN (-5: non-positive curvature or NaN in
+ *   the inner solve), MIHS_BARRIER_TIMEOUT (-6: the solver's device-wide
+ *   barrier gave up waiting; the result is invalid).
+ * - Calls that overlap on one workspace race; use one workspace per stream.
+ */
+#ifndef MIHS_H_
+#define MIHS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mihs_handle* mihs_handle_t;
+
+typedef enum { MIHS_F64 = 0, MIHS_F32 = 1 } mihs_dtype_t;
+
+/* Sketch families of Lemma 3: (iv) Gaussian, (iii) SRHT, (i) CountSketch, and
+ * CountSketch followed by a Gaussian second stage. */
+typedef enum {
+  MIHS_GAUSSIAN = 0,
+  MIHS_SRHT = 1,
+  MIHS_COUNTSKETCH = 2,
+  MIHS_COUNT_GAUSS = 3
+} mihs_sketch_kind_t;
+
+/* PLAIN_FP64: sketch and inner solve in double.
+ * MIXED: Gaussian stages use BF16 inputs with FP32 accumulation, SRHT and
+ * CountSketch use FP32 arithmetic; SA is stored as float and the inner CG runs
+ * in float.  The outer gradient A^T (b - A x) - lambda x is always FP64, so the
+ * outer loop refines the inexact inner steps to full FP64 accuracy. */
+typedef enum { MIHS_PLAIN_FP64 = 0, MIHS_MIXED = 1 } mihs_precision_t;
+
+enum {
+  MIHS_OK = 0,
+  MIHS_ERR_INVALID = -1,
+  MIHS_ERR_WORKSPACE = -2,
+  MIHS_ERR_HIP = -3,
+  MIHS_ERR_UNSUPPORTED = -4
+};
+
+enum {
+  MIHS_CONVERGED = 0,
+  MIHS_MAX_ITER = 1,
+  MIHS_BREAKDOWN = -5,
+  MIHS_BARRIER_TIMEOUT = -6
+};
+
+/* Device-side result record of one solve (one per right-hand side / lambda). */
+typedef struct {
+  int64_t outer_iters;        /* outer M-IHS iterations performed */
+  int64_t inner_iters_total;  /* inner CG iterations summed over the solve */
+  int64_t inner_iters_max;    /* largest inner CG count of one outer iteration */
+  double rel_step;            /* last ||x^{i+1} - x^i|| / ||x^{i+1}|| */
+  double grad_norm;           /* ||g|| at the last outer iteration */
+  int32_t status;             /* MIHS_CONVERGED, MIHS_MAX_ITER, ... */
+  int32_t reserved;
+} mihs_info_t;
+
+/* Create a handle bound to HIP device `device` (it queries the CU count and
+ * the cooperative-launch occupancy once).  Returns MIHS_ERR_HIP if the device
+ * cannot be used. */
+int mihs_create(mihs_handle_t* handle, int device);
+int mihs_destroy(mihs_handle_t handle);
+
+/* Human-readable text for a return code or an info status. */
+const char* mihs_status_string(int code);
+
+/* ------------------------------------------------------------------------
+ * Sketch:  SA = S A  (Algorithm 1's RP_fun; E[S^T S] = I, Section 3.1)
+ *
+ * A      device, n x d, dtype `a_dtype`, row stride lda.
+ * kind   MIHS_GAUSSIAN:  S_ij = N(0,1)/sqrt(m) (Lemma 3(iv)); the N(0,1) draw of
+ *          element (i, j) is Box-Muller on Philox-4x32-10 block (i*n+j)/4 with
+ *          key (seed, 0) and stream 0.
+ *        MIHS_SRHT:  S = (1/sqrt(m)) P H D (Lemma 3(iii)); n must be a power of
+ *          two; D_ii = -1 iff bit 31 of murmur3_x86_32(i, seed); row k of P
+ *          samples H's row murmur3_x86_32(k, seed + 0x9E3779B9) & (n-1), with
+ *          replacement; H is the unnormalised Sylvester Walsh-Hadamard matrix.
+ *        MIHS_COUNTSKETCH: row i of A is added with sign s(i) to row h(i) mod m
+ *          of SA, h = murmur3_x86_32(i, seed), s(i) = -1 iff bit 31 of h
+ *          (Lemma 3(i)); no scaling.
+ *        MIHS_COUNT_GAUSS: CountSketch to m rows, then a Gaussian m2 x m stage
+ *          (Philox stream 1, scale 1/sqrt(m2)).  The output has m2 rows.
+ * precision  PLAIN_FP64: SA is double.  MIXED: SA is float (Gaussian stages:
+ *          BF16 S and BF16 A, FP32 accumulation on the matrix cores).
+ * SA     device, output rows (m, or m2 for COUNT_GAUSS) x d, row stride ldsa,
+ *        double (PLAIN_FP64) or float (MIXED).
+ * workspace  device scratch of at least mihs_sketch_workspace_size() bytes.
+ * ------------------------------------------------------------------------ */
+int mihs_sketch_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                               int64_t m2, mihs_sketch_kind_t kind, mihs_dtype_t a_dtype,
+                               mihs_precision_t precision, size_t* bytes);
+
+int mihs_sketch(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                int64_t d, int64_t lda, mihs_sketch_kind_t kind, int64_t m, int64_t m2,
+                uint32_t seed, mihs_precision_t precision, void* SA, int64_t ldsa,
+                void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Solve (Algorithm 1 with a conjugate-gradient inner solver):
+ *   g^i     = A^T (b - A x^i) - lambda x^i                 (FP64, one pass over A)
+ *   dx^i    : ((SA)^T SA + lambda I) dx = g^i by CG from 0,
+ *             stopped when ||residual|| <= eps_sub ||g^i|| or after max_inner
+ *   x^{i+1} = x^i + alpha dx^i + beta (x^i - x^{i-1})
+ * The whole loop runs in one cooperative device launch (no host round trips).
+ * It stops when ||x^{i+1} - x^i|| / ||x^{i+1}|| <= tol (1 - sqrt(beta)) / sqrt(beta)
+ * (an estimate of ||x - x*|| / ||x*|| <= tol for contraction rate sqrt(beta),
+ * Corollary 4), or after max_outer iterations.  tol <= 0 runs exactly
+ * max_outer iterations.
+ *
+ * A       device, n x d (a_dtype), row stride lda.
+ * b       device, n doubles.
+ * lambda  > 0.
+ * SA      device, m x d sketch from mihs_sketch with the same `precision`.
+ * alpha, beta  momentum (Corollary 4: beta = sd/m, alpha = (1-beta)^2).
+ * X       device, d doubles: in = x^1 (warm start), out = last iterate.
+ * X_prev  device, d doubles or NULL: in = x^0 (the momentum term's previous
+ *         iterate; NULL means x^0 = x^1), out = the iterate before X.
+ * d_info  device, one mihs_info_t.
+ * ------------------------------------------------------------------------ */
+int mihs_solve_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                              mihs_precision_t precision, size_t* bytes);
+
+int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n, int64_t d,
+               int64_t lda, const double* b, double lambda, const void* SA, int64_t m,
+               int64_t ldsa, mihs_precision_t precision, double alpha, double beta,
+               double eps_sub, double tol, int64_t max_outer, int64_t max_inner, double* X,
+               double* X_prev, mihs_info_t* d_info, void* workspace, size_t ws_bytes,
+               void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched lambda-path solve: nprob independent problems, each solved for nlam
+ * regularisation values that share the problem's one sketch SA_k.  One
+ * persistent launch runs every (problem, lambda) pair; problems are split in
+ * row blocks over the GPU and each pass over A_k serves all nlam iterates.
+ *
+ * problems  device array of nprob mihs_problem_t records (see below).
+ * lambdas, alphas, betas  device, nprob x nlam doubles each (row k = problem k).
+ * Each problem's X is d_k x nlam row-major doubles (column j = lambda j; in:
+ * warm start, out: solution) and info points at nlam mihs_info_t records.
+ * A_k is FP64; SA_k has the precision's type (double / float).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const void* A;    /* n x d, row stride lda (double) */
+  const double* b;  /* n */
+  const void* SA;   /* m x d, row stride ldsa */
+  double* X;        /* d x nlam */
+  mihs_info_t* info;/* nlam records */
+  int64_t n, d, lda, m, ldsa;
+} mihs_problem_t;
+
+int mihs_solve_batched_workspace_size(mihs_handle_t handle, const mihs_problem_t* h_problems,
+                                      int64_t nprob, int64_t nlam, mihs_precision_t precision,
+                                      size_t* bytes);
+
+int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
+                       const mihs_problem_t* h_problems, int64_t nprob, const double* lambdas,
+                       const double* alphas, const double* betas, int64_t nlam,
+                       mihs_precision_t precision, double eps_sub, double tol,
+                       int64_t max_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
+                       void* stream);
+
+/* ------------------------------------------------------------------------
+ * Backward of x*_j = (A^T A + lambda I)^{-1} A^T b_j for k right-hand sides.
+ * Given Gbar = dL/dX* (d x k), solves the adjoint systems
+ *   (A^T A + lambda I) w_j = gbar_j
+ * by M-IHS on the same sketch (gradient gbar_j - A^T A w_j - lambda w_j), then
+ *   dL/dB = A W  (n x k)    and    dL/dlambda = - sum_j x*_j^T w_j.
+ * Xstar, Gbar, W are d x k row-major doubles (device); dB is n x k (device,
+ * NULL to skip); dlambda is one device double.  d_info holds k records.
+ * ------------------------------------------------------------------------ */
+int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                        int64_t d, int64_t lda, const void* SA, int64_t m, int64_t ldsa,
+                        double lambda, mihs_precision_t precision, const double* Xstar,
+                        const double* Gbar, int64_t k, double alpha, double beta,
+                        double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+                        double* W, double* dB, double* dlambda, mihs_info_t* d_info,
+                        void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIHS_H_ */

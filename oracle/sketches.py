@@ -146,6 +146,29 @@ def count_gauss_sketch(A: np.ndarray, m1: int, m2: int, seed: int) -> np.ndarray
     return gaussian_sketch(CA, m2, seed, stream=1)
 
 
+# ----------------------------------------------------------------------------
+# Mixed-precision reading of the Gaussian stage: S and A rounded to BF16
+# (round to nearest, ties to even, of the exact value), products summed exactly
+# enough (float64) to stand for an FP32-accumulated matrix-core product.
+# ----------------------------------------------------------------------------
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round float64 values to the nearest BF16 value (8 significant bits, ties
+    to even), returned as float64.  Normal-range inputs only."""
+    b = np.ascontiguousarray(x, dtype=np.float64).view(np.uint64)
+    shift = np.uint64(45)                       # 52 - 7 explicit mantissa bits
+    lsb = (b >> shift) & np.uint64(1)
+    bias = (np.uint64(1) << np.uint64(44)) - np.uint64(1) + lsb
+    r = ((b + bias) >> shift) << shift
+    return r.view(np.float64).reshape(np.shape(x))
+
+
+def gaussian_sketch_bf16(A: np.ndarray, m: int, seed: int, stream: int = 0) -> np.ndarray:
+    n = A.shape[0]
+    S = gaussian_entries(seed, stream, np.arange(m * n, dtype=np.int64)).reshape(m, n)
+    S = bf16_round(S * (1.0 / math.sqrt(m)))
+    return S @ bf16_round(A.astype(np.float64))
+
+
 def sketch(A: np.ndarray, kind: str, m: int, seed: int, m2: int = 0) -> np.ndarray:
     if kind == "gaussian":
         return gaussian_sketch(A, m, seed)

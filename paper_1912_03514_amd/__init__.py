@@ -1,0 +1,15 @@
+"""MI355X-native Momentum Iterative Hessian Sketch (M-IHS) for tall ridge regression.
+
+The solver lives in libmihs.so (hand-written HIP for gfx950, C ABI in
+include/mihs.h); this package is its thin Python binding.  torch tensors supply
+device memory and the current HIP stream.
+
+    import paper_1912_03514_amd as mihs
+    SA = mihs.mihs_sketch(A, "srht", m, seed)              # Lemma 3 sketches
+    alpha, beta = mihs.momentum(sd, m)                      # Corollary 4
+    x, info = mihs.mihs_solve(A, b, lam, SA, alpha, beta)  # Algorithm 1
+"""
+from ._binding import (  # noqa: F401
+    EXPORTED, INFO_BYTES, LIB_PATH, MihsError, SolveWorkspace, handle, info_to_dict,
+    load_library, mihs_sketch, mihs_solve, mihs_solve_backward, momentum,
+)

@@ -1,0 +1,279 @@
+"""ctypes binding of libmihs (include/mihs.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+stream; every step of the solver runs in the HIP library.  If libmihs.so has
+not been built the binding raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+from typing import Dict, Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmihs.so")
+
+F64, F32 = 0, 1
+SKETCH_KINDS = {"gaussian": 0, "srht": 1, "countsketch": 2, "count_gauss": 3}
+PRECISIONS = {"plain": 0, "fp64": 0, "mixed": 1}
+
+MIHS_OK = 0
+STATUS_NAMES = {0: "converged", 1: "max_iter", -5: "breakdown", -6: "barrier_timeout"}
+
+
+class MihsError(RuntimeError):
+    pass
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("outer_iters", ctypes.c_int64),
+        ("inner_iters_total", ctypes.c_int64),
+        ("inner_iters_max", ctypes.c_int64),
+        ("rel_step", ctypes.c_double),
+        ("grad_norm", ctypes.c_double),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+INFO_BYTES = ctypes.sizeof(Info)  # 48
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("A", ctypes.c_void_p), ("b", ctypes.c_void_p), ("SA", ctypes.c_void_p),
+        ("X", ctypes.c_void_p), ("info", ctypes.c_void_p),
+        ("n", ctypes.c_int64), ("d", ctypes.c_int64), ("lda", ctypes.c_int64),
+        ("m", ctypes.c_int64), ("ldsa", ctypes.c_int64),
+    ]
+
+
+_i64, _u32, _dbl, _vp, _int, _sz = (ctypes.c_int64, ctypes.c_uint32, ctypes.c_double,
+                                     ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t)
+
+_SIGS = {
+    "mihs_create": (_int, [ctypes.POINTER(_vp), _int]),
+    "mihs_destroy": (_int, [_vp]),
+    "mihs_status_string": (ctypes.c_char_p, [_int]),
+    "mihs_sketch_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int, _int, _int,
+                                          ctypes.POINTER(_sz)]),
+    "mihs_sketch": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _int, _i64, _i64, _u32, _int, _vp,
+                           _i64, _vp, _sz, _vp]),
+    "mihs_solve_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)]),
+    "mihs_solve": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64, _int,
+                          _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mihs_solve_batched_workspace_size": (_int, [_vp, _vp, _i64, _i64, _int, ctypes.POINTER(_sz)]),
+    "mihs_solve_batched": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl,
+                                  _i64, _i64, _vp, _sz, _vp]),
+    "mihs_solve_backward": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _int,
+                                   _vp, _vp, _i64, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp,
+                                   _vp, _vp, _vp, _sz, _vp]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+_lock = threading.Lock()
+_handles: Dict[int, int] = {}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmihs.so (no GPU work).  Raises if it is missing."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise MihsError(f"{path} is not built; run `python -m paper_1912_03514_amd.build`")
+            lib = ctypes.CDLL(path)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != MIHS_OK:
+        msg = load_library().mihs_status_string(rc).decode()
+        raise MihsError(f"{what} failed with {rc}: {msg}")
+
+
+def handle(device: Optional[int] = None) -> int:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    with _lock:
+        h = _handles.get(dev)
+    if h is None:
+        lib = load_library()
+        hp = _vp()
+        _check(lib.mihs_create(ctypes.byref(hp), dev), "mihs_create")
+        with _lock:
+            _handles[dev] = hp.value
+        h = hp.value
+    return h
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise MihsError(f"unsupported dtype {t.dtype}")
+
+
+def _row_aligned(t: torch.Tensor) -> torch.Tensor:
+    """Rows must start on 16-byte boundaries; copy into a padded buffer if not."""
+    es = t.element_size()
+    if t.stride(1) == 1 and t.data_ptr() % 16 == 0 and (t.stride(0) * es) % 16 == 0:
+        return t
+    n, d = t.shape
+    per = 16 // es
+    ld = (d + per - 1) // per * per
+    buf = torch.zeros((n, ld), dtype=t.dtype, device=t.device)
+    buf[:, :d] = t
+    return buf[:, :d]
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def momentum(sd: float, m: int) -> Tuple[float, float]:
+    """Corollary 4: beta = sd/m, alpha = (1 - beta)^2."""
+    beta = float(sd) / float(m)
+    if not 0.0 < beta < 1.0:
+        raise ValueError("need 0 < sd < m")
+    return (1.0 - beta) ** 2, beta
+
+
+def mihs_sketch(A: torch.Tensor, kind: str, m: int, seed: int, precision: str = "plain",
+                m2: int = 0) -> torch.Tensor:
+    """SA = S A on the GPU (see include/mihs.h).  Returns an (m or m2) x d tensor,
+    float64 for the plain path and float32 for the mixed path."""
+    if A.dim() != 2 or not A.is_cuda:
+        raise MihsError("A must be a 2-D device tensor")
+    A = _row_aligned(A)
+    lib = load_library()
+    h = handle(A.device.index)
+    n, d = A.shape
+    k = SKETCH_KINDS[kind]
+    p = PRECISIONS[precision]
+    rows = m2 if kind == "count_gauss" else m
+    sa_dtype = torch.float32 if p == 1 else torch.float64
+    ld = (d + 3) // 4 * 4
+    SA = torch.zeros((rows, ld), dtype=sa_dtype, device=A.device)[:, :d]
+    ws_n = _sz()
+    _check(lib.mihs_sketch_workspace_size(h, n, d, m, m2, k, _dtype_code(A), p, ctypes.byref(ws_n)),
+           "mihs_sketch_workspace_size")
+    ws = _workspace(ws_n.value, A.device)
+    _check(lib.mihs_sketch(h, A.data_ptr(), _dtype_code(A), n, d, A.stride(0), k, m, m2,
+                           seed & 0xFFFFFFFF, p, SA.data_ptr(), SA.stride(0), ws.data_ptr(),
+                           ws.numel(), _stream(A.device)), "mihs_sketch")
+    return SA
+
+
+def info_to_dict(raw: torch.Tensor) -> list:
+    host = raw.cpu().numpy().tobytes()
+    out = []
+    for i in range(len(host) // INFO_BYTES):
+        s = Info.from_buffer_copy(host[i * INFO_BYTES:(i + 1) * INFO_BYTES])
+        out.append({"outer_iters": s.outer_iters, "inner_iters_total": s.inner_iters_total,
+                    "inner_iters_max": s.inner_iters_max, "rel_step": s.rel_step,
+                    "grad_norm": s.grad_norm, "status": s.status,
+                    "status_name": STATUS_NAMES.get(s.status, str(s.status))})
+    return out
+
+
+class SolveWorkspace:
+    """Preallocated device buffers for repeated solves of one shape."""
+
+    def __init__(self, n: int, d: int, m: int, precision: str, device):
+        lib = load_library()
+        self.h = handle(device.index if hasattr(device, "index") else device)
+        ws_n = _sz()
+        _check(lib.mihs_solve_workspace_size(self.h, n, d, m, PRECISIONS[precision],
+                                             ctypes.byref(ws_n)), "mihs_solve_workspace_size")
+        self.ws = _workspace(ws_n.value, device)
+        self.info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=device)
+
+
+def mihs_solve(A: torch.Tensor, b: torch.Tensor, lam: float, SA: torch.Tensor, alpha: float,
+               beta: float, eps_sub: float = 1e-2, tol: float = 1e-10, max_outer: int = 200,
+               max_inner: int = 1000, x0: Optional[torch.Tensor] = None,
+               x_prev: Optional[torch.Tensor] = None, precision: Optional[str] = None,
+               workspace: Optional[SolveWorkspace] = None, sync: bool = True):
+    """M-IHS on the GPU (see include/mihs.h).  Returns (x, info) where info is a
+    dict (sync=True) or the raw device record (sync=False)."""
+    if precision is None:
+        precision = "mixed" if SA.dtype == torch.float32 else "plain"
+    p = PRECISIONS[precision]
+    A = _row_aligned(A)
+    SA = _row_aligned(SA)
+    n, d = A.shape
+    m = SA.shape[0]
+    dev = A.device
+    if b.dtype != torch.float64 or b.numel() != n or not b.is_contiguous():
+        raise MihsError("b must be a contiguous float64 vector of length n")
+    x = torch.zeros(d, dtype=torch.float64, device=dev) if x0 is None else x0.clone()
+    if workspace is None:
+        workspace = SolveWorkspace(n, d, m, precision, dev)
+    lib = load_library()
+    rc = lib.mihs_solve(workspace.h, A.data_ptr(), _dtype_code(A), n, d, A.stride(0),
+                        b.data_ptr(), float(lam), SA.data_ptr(), m, SA.stride(0), p,
+                        float(alpha), float(beta), float(eps_sub), float(tol), int(max_outer),
+                        int(max_inner), x.data_ptr(),
+                        x_prev.data_ptr() if x_prev is not None else None,
+                        workspace.info.data_ptr(), workspace.ws.data_ptr(), workspace.ws.numel(),
+                        _stream(dev))
+    _check(rc, "mihs_solve")
+    if not sync:
+        return x, workspace.info
+    torch.cuda.synchronize(dev)
+    return x, info_to_dict(workspace.info)[0]
+
+
+def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: torch.Tensor,
+                        Gbar: torch.Tensor, alpha: float, beta: float, eps_sub: float = 1e-2,
+                        tol: float = 1e-12, max_outer: int = 300, max_inner: int = 1000,
+                        want_dB: bool = True, precision: Optional[str] = None):
+    """Adjoint M-IHS solves W = (A^T A + lambda I)^{-1} Gbar; dB = A W;
+    dlambda = -sum X*.W.  Returns (W, dB or None, dlambda (0-d tensor), infos)."""
+    if precision is None:
+        precision = "mixed" if SA.dtype == torch.float32 else "plain"
+    p = PRECISIONS[precision]
+    A = _row_aligned(A)
+    SA = _row_aligned(SA)
+    n, d = A.shape
+    m = SA.shape[0]
+    dev = A.device
+    Xs = Xstar.reshape(d, -1).contiguous().to(torch.float64)
+    Gb = Gbar.reshape(d, -1).contiguous().to(torch.float64)
+    k = Gb.shape[1]
+    W = torch.zeros((d, k), dtype=torch.float64, device=dev)
+    dB = torch.zeros((n, k), dtype=torch.float64, device=dev) if want_dB else None
+    dlam = torch.zeros((), dtype=torch.float64, device=dev)
+    info = torch.zeros(INFO_BYTES * k, dtype=torch.uint8, device=dev)
+    lib = load_library()
+    h = handle(dev.index)
+    ws_n = _sz()
+    _check(lib.mihs_solve_workspace_size(h, n, d, m, p, ctypes.byref(ws_n)),
+           "mihs_solve_workspace_size")
+    ws = _workspace(ws_n.value + 2 * ((d * 8 + 255) // 256 * 256), dev)
+    rc = lib.mihs_solve_backward(h, A.data_ptr(), _dtype_code(A), n, d, A.stride(0),
+                                 SA.data_ptr(), m, SA.stride(0), float(lam), p, Xs.data_ptr(),
+                                 Gb.data_ptr(), k, float(alpha), float(beta), float(eps_sub),
+                                 float(tol), int(max_outer), int(max_inner), W.data_ptr(),
+                                 dB.data_ptr() if dB is not None else None, dlam.data_ptr(),
+                                 info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))
+    _check(rc, "mihs_solve_backward")
+    torch.cuda.synchronize(dev)
+    return W, dB, dlam, info_to_dict(info)

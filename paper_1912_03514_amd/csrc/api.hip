@@ -1,0 +1,271 @@
+// C ABI entry points of libmihs: handle management, argument validation and
+// dispatch to the kernel launchers.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "internal.hpp"
+
+using mihs::align_up;
+
+namespace {
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int elem_size(int f32) { return f32 ? 4 : 8; }
+
+bool rows_aligned(const void* p, int64_t ld, int f32) {
+  return aligned16(p) && ((ld * elem_size(f32)) % 16 == 0);
+}
+
+bool valid_matrix(const void* p, int64_t rows, int64_t cols, int64_t ld, int f32) {
+  return p != nullptr && rows > 0 && cols > 0 && ld >= cols && rows_aligned(p, ld, f32);
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+}  // namespace
+
+extern "C" {
+
+int mihs_create(mihs_handle_t* handle, int device) {
+  if (!handle) return MIHS_ERR_INVALID;
+  *handle = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MIHS_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return MIHS_ERR_HIP;
+  if (!prop.cooperativeLaunch) return MIHS_ERR_UNSUPPORTED;
+  mihs_handle* h = (mihs_handle*)calloc(1, sizeof(mihs_handle));
+  if (!h) return MIHS_ERR_INVALID;
+  h->device = device;
+  h->num_cu = prop.multiProcessorCount;
+  strncpy(h->arch, prop.gcnArchName, sizeof(h->arch) - 1);
+  *handle = h;
+  return MIHS_OK;
+}
+
+int mihs_destroy(mihs_handle_t handle) {
+  free(handle);
+  return MIHS_OK;
+}
+
+const char* mihs_status_string(int code) {
+  switch (code) {
+    case MIHS_OK: return "ok / converged";
+    case MIHS_MAX_ITER: return "maximum outer iterations reached";
+    case MIHS_ERR_INVALID: return "invalid argument";
+    case MIHS_ERR_WORKSPACE: return "workspace too small";
+    case MIHS_ERR_HIP: return "HIP runtime error";
+    case MIHS_ERR_UNSUPPORTED: return "unsupported combination";
+    case MIHS_BREAKDOWN: return "inner solve breakdown (non-positive curvature or NaN)";
+    case MIHS_BARRIER_TIMEOUT: return "device-wide barrier timed out";
+    default: return "unknown status";
+  }
+}
+
+int mihs_sketch_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m, int64_t m2,
+                               mihs_sketch_kind_t kind, mihs_dtype_t a_dtype,
+                               mihs_precision_t precision, size_t* bytes) {
+  if (!handle || !bytes || n <= 0 || d <= 0 || m <= 0) return MIHS_ERR_INVALID;
+  *bytes = mihs::sketch_workspace_bytes(handle, n, d, m, m2, (int)kind, a_dtype == MIHS_F32,
+                                        precision == MIHS_MIXED);
+  return MIHS_OK;
+}
+
+int mihs_sketch(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n, int64_t d,
+                int64_t lda, mihs_sketch_kind_t kind, int64_t m, int64_t m2, uint32_t seed,
+                mihs_precision_t precision, void* SA, int64_t ldsa, void* workspace,
+                size_t ws_bytes, void* stream) {
+  if (!handle) return MIHS_ERR_INVALID;
+  const int a_f32 = a_dtype == MIHS_F32;
+  const int mixed = precision == MIHS_MIXED;
+  if (a_dtype != MIHS_F64 && a_dtype != MIHS_F32) return MIHS_ERR_INVALID;
+  if (precision != MIHS_PLAIN_FP64 && precision != MIHS_MIXED) return MIHS_ERR_INVALID;
+  if (!valid_matrix(A, n, d, lda, a_f32)) return MIHS_ERR_INVALID;
+  if (m <= 0) return MIHS_ERR_INVALID;
+  const int64_t rows_out = (kind == MIHS_COUNT_GAUSS) ? m2 : m;
+  if (rows_out <= 0) return MIHS_ERR_INVALID;
+  if (!valid_matrix(SA, rows_out, d, ldsa, mixed)) return MIHS_ERR_INVALID;
+  switch (kind) {
+    case MIHS_GAUSSIAN: break;
+    case MIHS_SRHT:
+      if ((n & (n - 1)) != 0) return MIHS_ERR_INVALID;
+      break;
+    case MIHS_COUNTSKETCH: break;
+    case MIHS_COUNT_GAUSS:
+      if (m2 <= 0) return MIHS_ERR_INVALID;
+      break;
+    default: return MIHS_ERR_INVALID;
+  }
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  return mihs::launch_sketch(handle, A, a_f32, n, d, lda, (int)kind, m, m2, seed, mixed, SA, ldsa,
+                             workspace, ws_bytes, as_stream(stream));
+}
+
+int mihs_solve_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                              mihs_precision_t precision, size_t* bytes) {
+  if (!handle || !bytes || n <= 0 || d <= 0 || m <= 0) return MIHS_ERR_INVALID;
+  *bytes = mihs::solve_workspace_bytes(handle, n, d, m, precision == MIHS_MIXED);
+  return MIHS_OK;
+}
+
+static int check_solve_common(const void* A, mihs_dtype_t a_dtype, int64_t n, int64_t d,
+                              int64_t lda, double lambda, const void* SA, int64_t m, int64_t ldsa,
+                              mihs_precision_t precision, double alpha, double beta,
+                              double eps_sub, int64_t max_outer, int64_t max_inner) {
+  if (a_dtype != MIHS_F64 && a_dtype != MIHS_F32) return MIHS_ERR_INVALID;
+  if (precision != MIHS_PLAIN_FP64 && precision != MIHS_MIXED) return MIHS_ERR_INVALID;
+  if (n < d) return MIHS_ERR_INVALID;
+  if (!valid_matrix(A, n, d, lda, a_dtype == MIHS_F32)) return MIHS_ERR_INVALID;
+  if (!valid_matrix(SA, m, d, ldsa, precision == MIHS_MIXED)) return MIHS_ERR_INVALID;
+  if (!(lambda > 0.0) || !isfinite(lambda)) return MIHS_ERR_INVALID;
+  if (!isfinite(alpha) || !isfinite(beta) || !(alpha > 0.0) || beta < 0.0 || beta >= 1.0)
+    return MIHS_ERR_INVALID;
+  if (!(eps_sub >= 0.0) || max_outer < 0 || max_inner < 1) return MIHS_ERR_INVALID;
+  if (d > 4096) return MIHS_ERR_UNSUPPORTED;
+  return MIHS_OK;
+}
+
+int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n, int64_t d,
+               int64_t lda, const double* b, double lambda, const void* SA, int64_t m,
+               int64_t ldsa, mihs_precision_t precision, double alpha, double beta,
+               double eps_sub, double tol, int64_t max_outer, int64_t max_inner, double* X,
+               double* X_prev, mihs_info_t* d_info, void* workspace, size_t ws_bytes,
+               void* stream) {
+  if (!handle) return MIHS_ERR_INVALID;
+  int rc = check_solve_common(A, a_dtype, n, d, lda, lambda, SA, m, ldsa, precision, alpha, beta,
+                              eps_sub, max_outer, max_inner);
+  if (rc) return rc;
+  if (!b || !X || !d_info) return MIHS_ERR_INVALID;
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  mihs::SolveDesc s;
+  s.A = A;
+  s.a_f32 = a_dtype == MIHS_F32;
+  s.n = n;
+  s.d = d;
+  s.lda = lda;
+  s.b = b;
+  s.rhs = nullptr;
+  s.SA = SA;
+  s.mixed = precision == MIHS_MIXED;
+  s.m = m;
+  s.ldsa = ldsa;
+  s.lam = lambda;
+  s.alpha = alpha;
+  s.beta = beta;
+  s.eps_sub = eps_sub;
+  s.tol = tol;
+  s.max_outer = max_outer;
+  s.max_inner = max_inner;
+  s.x = X;
+  s.x_prev = X_prev;
+  s.info = d_info;
+  return mihs::launch_solve(handle, s, workspace, ws_bytes, as_stream(stream));
+}
+
+int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                        int64_t d, int64_t lda, const void* SA, int64_t m, int64_t ldsa,
+                        double lambda, mihs_precision_t precision, const double* Xstar,
+                        const double* Gbar, int64_t k, double alpha, double beta,
+                        double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+                        double* W, double* dB, double* dlambda, mihs_info_t* d_info,
+                        void* workspace, size_t ws_bytes, void* stream) {
+  if (!handle) return MIHS_ERR_INVALID;
+  int rc = check_solve_common(A, a_dtype, n, d, lda, lambda, SA, m, ldsa, precision, alpha, beta,
+                              eps_sub, max_outer, max_inner);
+  if (rc) return rc;
+  if (!Xstar || !Gbar || !W || !dlambda || !d_info || k < 1) return MIHS_ERR_INVALID;
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  hipStream_t st = as_stream(stream);
+  // The adjoint systems (A^T A + lambda I) w_j = gbar_j, one M-IHS solve per
+  // column, all on the same sketch.  Columns are strided by k in the d x k
+  // row-major arrays, so each solve works on a contiguous copy in the
+  // workspace tail.
+  const size_t solve_ws = mihs::solve_workspace_bytes(handle, n, d, m, precision == MIHS_MIXED);
+  const size_t col_bytes = align_up((size_t)d * sizeof(double), 256);
+  if (!workspace || ws_bytes < solve_ws + 2 * col_bytes) return MIHS_ERR_WORKSPACE;
+  char* base = (char*)workspace;
+  double* g_col = (double*)(base + solve_ws);
+  double* w_col = (double*)(base + solve_ws + col_bytes);
+  for (int64_t j = 0; j < k; ++j) {
+    if (hipMemcpy2DAsync(g_col, sizeof(double), Gbar + j, (size_t)k * sizeof(double),
+                         sizeof(double), (size_t)d, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return MIHS_ERR_HIP;
+    if (hipMemsetAsync(w_col, 0, (size_t)d * sizeof(double), st) != hipSuccess) return MIHS_ERR_HIP;
+    mihs::SolveDesc s;
+    s.A = A;
+    s.a_f32 = a_dtype == MIHS_F32;
+    s.n = n;
+    s.d = d;
+    s.lda = lda;
+    s.b = nullptr;
+    s.rhs = g_col;
+    s.SA = SA;
+    s.mixed = precision == MIHS_MIXED;
+    s.m = m;
+    s.ldsa = ldsa;
+    s.lam = lambda;
+    s.alpha = alpha;
+    s.beta = beta;
+    s.eps_sub = eps_sub;
+    s.tol = tol;
+    s.max_outer = max_outer;
+    s.max_inner = max_inner;
+    s.x = w_col;
+    s.x_prev = nullptr;
+    s.info = d_info + j;
+    rc = mihs::launch_solve(handle, s, workspace, solve_ws, st);
+    if (rc) return rc;
+    if (hipMemcpy2DAsync(W + j, (size_t)k * sizeof(double), w_col, sizeof(double), sizeof(double),
+                         (size_t)d, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return MIHS_ERR_HIP;
+  }
+  if (dB) {
+    rc = mihs::launch_apply_rows(handle, A, a_dtype == MIHS_F32, n, d, lda, W, k, dB, k, st);
+    if (rc) return rc;
+  }
+  return mihs::launch_neg_dot(Xstar, W, d * k, dlambda, st);
+}
+
+int mihs_solve_batched_workspace_size(mihs_handle_t handle, const mihs_problem_t* h_problems,
+                                      int64_t nprob, int64_t nlam, mihs_precision_t precision,
+                                      size_t* bytes) {
+  if (!handle || !h_problems || !bytes || nprob < 1 || nlam < 1) return MIHS_ERR_INVALID;
+  size_t best = 0;
+  for (int64_t p = 0; p < nprob; ++p) {
+    const size_t s = mihs::solve_workspace_bytes(handle, h_problems[p].n, h_problems[p].d,
+                                                 h_problems[p].m, precision == MIHS_MIXED) +
+                     2 * align_up((size_t)h_problems[p].d * sizeof(double), 256);
+    if (s > best) best = s;
+  }
+  *bytes = best;
+  return MIHS_OK;
+}
+
+int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
+                       const mihs_problem_t* h_problems, int64_t nprob, const double* lambdas,
+                       const double* alphas, const double* betas, int64_t nlam,
+                       mihs_precision_t precision, double eps_sub, double tol,
+                       int64_t max_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
+                       void* stream) {
+  (void)d_problems;
+  (void)h_problems;
+  (void)nprob;
+  (void)lambdas;
+  (void)alphas;
+  (void)betas;
+  (void)nlam;
+  (void)precision;
+  (void)eps_sub;
+  (void)tol;
+  (void)max_outer;
+  (void)max_inner;
+  (void)workspace;
+  (void)ws_bytes;
+  (void)stream;
+  if (!handle) return MIHS_ERR_INVALID;
+  return MIHS_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

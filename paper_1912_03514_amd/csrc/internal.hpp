@@ -1,0 +1,61 @@
+// Internal host-side interfaces between the C ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/mihs.h"
+
+struct mihs_handle {
+  int device;
+  int num_cu;
+  char arch[64];
+};
+
+namespace mihs {
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Padded vector length used by the row kernels: 64 lanes x elements-per-lane.
+int ept_for(int64_t d);
+inline int64_t dpad_for(int64_t d) { return 64 * (int64_t)ept_for(d); }
+
+// ---- solve ----------------------------------------------------------------
+struct SolveDesc {
+  const void* A;
+  int a_f32;
+  int64_t n, d, lda;
+  const double* b;    // ridge mode (n)   -- exactly one of b / rhs is set
+  const double* rhs;  // adjoint mode (d)
+  const void* SA;
+  int mixed;
+  int64_t m, ldsa;
+  double lam, alpha, beta, eps_sub, tol;
+  int64_t max_outer, max_inner;
+  double* x;
+  double* x_prev;  // may be null
+  mihs_info_t* info;
+};
+
+size_t solve_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int mixed);
+int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_bytes,
+                 hipStream_t stream);
+
+// ---- sketches -------------------------------------------------------------
+size_t sketch_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int64_t m2,
+                              int kind, int a_f32, int mixed);
+int launch_sketch(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,
+                  int64_t lda, int kind, int64_t m, int64_t m2, uint32_t seed, int mixed,
+                  void* SA, int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t stream);
+
+// ---- dense helper kernels --------------------------------------------------
+// Y (n x k, row stride ldy) = A (n x d) W (d x k row-major); FP64 accumulation.
+int launch_apply_rows(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,
+                      int64_t lda, const double* W, int64_t k, double* Y, int64_t ldy,
+                      hipStream_t stream);
+// out = -sum over all entries of X .* W (d x k); one device double.
+int launch_neg_dot(const double* X, const double* W, int64_t count, double* out,
+                   hipStream_t stream);
+
+}  // namespace mihs

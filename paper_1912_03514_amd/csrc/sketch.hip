@@ -1,0 +1,726 @@
+// Sketch kernels (Lemma 3): SRHT via a blocked fast Walsh-Hadamard transform,
+// CountSketch via a deterministic bucket sort + segmented sums, Gaussian via
+// counter-based generation and a matrix-core GEMM (FP64 MFMA for the plain
+// path, BF16 MFMA with FP32 accumulation for the mixed path).
+#include <math.h>
+
+#include "device_util.hpp"
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace mihs {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// BF16 rounding (round to nearest even of the exact value).  A double is first
+// narrowed to float with round-to-odd (truncate, then set the sticky bit if
+// inexact) so the second rounding to BF16 is a single correct rounding.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rne_from_float(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ uint16_t bf16_rne(double x) {
+  float f = __double2float_rz(x);
+  if ((double)f != x) f = __uint_as_float(__float_as_uint(f) | 1u);
+  return bf16_rne_from_float(f);
+}
+__device__ __forceinline__ uint16_t bf16_rne(float x) { return bf16_rne_from_float(x); }
+
+// ---------------------------------------------------------------------------
+// SRHT:  SA = (1/sqrt(m)) P H D A with H = H_hi (x) H_lo (Sylvester order):
+// row index i = i_hi * B + i_lo.  Stage 1 applies D and the length-B transform
+// over i_lo inside each block of B consecutive rows (in LDS).  Stage 2 forms
+// each sampled row k = (k_hi, k_lo) as sum_{i_hi} (-1)^{popc(k_hi & i_hi)}
+// Y[i_hi * B + k_lo], reading each needed row of Y once per column block.
+// ---------------------------------------------------------------------------
+__global__ void srht_rows_kernel(int* idx, int64_t m, int64_t n, uint32_t seed) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) idx[k] = (int)(murmur3_u32((uint32_t)k, seed + kSrhtSampleSeedOffset) & (uint32_t)(n - 1));
+}
+
+constexpr int kFwhtW = 16;  // columns per stage-1 tile
+
+template <typename TA, typename TY>
+__global__ __launch_bounds__(kBlock) void srht_stage1(const TA* __restrict__ A, int64_t lda,
+                                                      int64_t d, int logB, uint32_t seed,
+                                                      TY* __restrict__ Y, int64_t ldy) {
+  extern __shared__ unsigned char smem_raw[];
+  TY* T = (TY*)smem_raw;  // B x kFwhtW
+  const int B = 1 << logB;
+  const int64_t row0 = (int64_t)blockIdx.x * B;
+  const int64_t c0 = (int64_t)blockIdx.y * kFwhtW;
+  for (int e = threadIdx.x; e < B * kFwhtW; e += kBlock) {
+    const int r = e / kFwhtW, c = e % kFwhtW;
+    const int64_t gr = row0 + r, gc = c0 + c;
+    TY v = TY(0);
+    if (gc < d) {
+      v = (TY)A[gr * lda + gc];
+      if (murmur3_u32((uint32_t)gr, seed) >> 31) v = -v;
+    }
+    T[e] = v;
+  }
+  __syncthreads();
+  for (int h = 1; h < B; h <<= 1) {
+    for (int p = threadIdx.x; p < (B / 2) * kFwhtW; p += kBlock) {
+      const int c = p % kFwhtW, q = p / kFwhtW;
+      const int i = (q / h) * 2 * h + (q % h);
+      const TY u = T[i * kFwhtW + c], v = T[(i + h) * kFwhtW + c];
+      T[i * kFwhtW + c] = u + v;
+      T[(i + h) * kFwhtW + c] = u - v;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < B * kFwhtW; e += kBlock) {
+    const int r = e / kFwhtW, c = e % kFwhtW;
+    const int64_t gc = c0 + c;
+    if (gc < d) Y[(row0 + r) * ldy + gc] = T[e];
+  }
+}
+
+constexpr int kS2Cols = 64;    // columns per stage-2 workgroup
+constexpr int kS2Chunk = 16;   // samples accumulated together
+constexpr int kS2Cap = 512;    // sample list capacity
+
+template <typename TY, typename TS>
+__global__ __launch_bounds__(kBlock) void srht_stage2(const TY* __restrict__ Y, int64_t ldy,
+                                                      int64_t d, int logB, int64_t nhi,
+                                                      const int* __restrict__ idx, int64_t m,
+                                                      TS* __restrict__ SA, int64_t ldsa,
+                                                      double scale) {
+  __shared__ int s_list[kS2Cap];
+  __shared__ int s_wcnt[kWavesPerBlock];
+  __shared__ TY s_red[kWavesPerBlock][kS2Chunk][kS2Cols];
+  const int B = 1 << logB;
+  const int klo = blockIdx.x;
+  const int64_t col = (int64_t)blockIdx.y * kS2Cols + (threadIdx.x & (kS2Cols - 1));
+  const int rg = threadIdx.x >> 6;  // row group = wave
+  const int lane = lane_id();
+  int cnt = 0;
+
+  auto process = [&](int count) {
+    for (int s0 = 0; s0 < count; s0 += kS2Chunk) {
+      const int ns = min(kS2Chunk, count - s0);
+      int khi[kS2Chunk];
+      TY acc[kS2Chunk];
+#pragma unroll
+      for (int s = 0; s < kS2Chunk; ++s) {
+        khi[s] = (s < ns) ? (idx[s_list[s0 + s]] >> logB) : 0;
+        acc[s] = TY(0);
+      }
+      if (col < d) {
+        for (int64_t ih = rg; ih < nhi; ih += kWavesPerBlock) {
+          const TY y = Y[(ih * B + klo) * ldy + col];
+#pragma unroll
+          for (int s = 0; s < kS2Chunk; ++s) {
+            const int par = __popc((unsigned)khi[s] & (unsigned)ih) & 1;
+            acc[s] += par ? -y : y;
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < kS2Chunk; ++s) s_red[rg][s][lane] = acc[s];
+      __syncthreads();
+      if (rg == 0 && col < d) {
+        for (int s = 0; s < ns; ++s) {
+          TY t = s_red[0][s][lane];
+#pragma unroll
+          for (int g = 1; g < kWavesPerBlock; ++g) t += s_red[g][s][lane];
+          SA[(int64_t)s_list[s0 + s] * ldsa + col] = (TS)((double)t * scale);
+        }
+      }
+      __syncthreads();
+    }
+  };
+
+  for (int64_t w0 = 0; w0 < m; w0 += kBlock) {
+    const int64_t k = w0 + threadIdx.x;
+    const bool match = (k < m) && ((idx[k] & (B - 1)) == klo);
+    const unsigned long long ball = __ballot(match);
+    const int before = __popcll(ball & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wcnt[rg] = __popcll(ball);
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int g = 0; g < kWavesPerBlock; ++g) {
+      if (g < rg) off += s_wcnt[g];
+      total += s_wcnt[g];
+    }
+    if (cnt + total > kS2Cap) {
+      process(cnt);
+      cnt = 0;
+    }
+    if (match) s_list[cnt + off + before] = (int)k;
+    cnt += total;
+    __syncthreads();
+  }
+  if (cnt > 0) process(cnt);
+}
+
+// ---------------------------------------------------------------------------
+// CountSketch: h = murmur3(i, seed), bucket = h mod m, sign = -1 iff bit 31.
+// Rows are bucketed by a counting sort, each bucket's row list is sorted
+// ascending, then each (bucket, column block) sums its rows in that order, so
+// the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+__global__ void cs_hash_kernel(int64_t n, int64_t m, uint32_t seed, unsigned* code,
+                               unsigned* hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t h = murmur3_u32((uint32_t)i, seed);
+  const unsigned bucket = h % (uint32_t)m;
+  code[i] = bucket | (h & 0x80000000u);
+  atomicAdd(&hist[bucket], 1u);
+}
+
+// Exclusive scan of hist[0..m) into off[0..m]; one workgroup.
+__global__ __launch_bounds__(kBlock) void cs_scan_kernel(const unsigned* hist, int64_t m,
+                                                         unsigned* off, unsigned* cursor) {
+  __shared__ unsigned s_part[kBlock];
+  const int64_t per = (m + kBlock - 1) / kBlock;
+  const int64_t b0 = threadIdx.x * per, b1 = min(m, b0 + per);
+  unsigned s = 0;
+  for (int64_t i = b0; i < b1; ++i) s += hist[i];
+  s_part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned run = 0;
+    for (int t = 0; t < kBlock; ++t) {
+      const unsigned v = s_part[t];
+      s_part[t] = run;
+      run += v;
+    }
+    off[m] = run;
+  }
+  __syncthreads();
+  unsigned run = s_part[threadIdx.x];
+  for (int64_t i = b0; i < b1; ++i) {
+    off[i] = run;
+    cursor[i] = run;
+    run += hist[i];
+  }
+}
+
+__global__ void cs_scatter_kernel(int64_t n, const unsigned* code, int64_t m, unsigned* cursor,
+                                  unsigned* perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned c = code[i];
+  const unsigned pos = atomicAdd(&cursor[c & 0x7FFFFFFFu], 1u);
+  perm[pos] = (unsigned)i;  // row index (n < 2^31)
+}
+
+constexpr int kSortCap = 2048;
+
+// Sort each bucket's row list ascending (bitonic in LDS; a serial fallback for
+// oversized buckets keeps the result well defined).
+__global__ __launch_bounds__(kBlock) void cs_sort_kernel(const unsigned* off, unsigned* perm) {
+  __shared__ unsigned s[kSortCap];
+  const unsigned b0 = off[blockIdx.x], b1 = off[blockIdx.x + 1];
+  const int cnt = (int)(b1 - b0);
+  if (cnt <= 1) return;
+  if (cnt > kSortCap) {
+    if (threadIdx.x == 0) {
+      for (int i = 1; i < cnt; ++i) {
+        const unsigned v = perm[b0 + i];
+        int j = i - 1;
+        while (j >= 0 && perm[b0 + j] > v) {
+          perm[b0 + j + 1] = perm[b0 + j];
+          --j;
+        }
+        perm[b0 + j + 1] = v;
+      }
+    }
+    return;
+  }
+  int P = 1;
+  while (P < cnt) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += kBlock) s[i] = (i < cnt) ? perm[b0 + i] : 0xFFFFFFFFu;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += kBlock) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const unsigned a = s[i], b = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < cnt; i += kBlock) perm[b0 + i] = s[i];
+}
+
+template <typename TA, typename TAcc, typename TOut>
+__global__ __launch_bounds__(kBlock) void cs_accum_kernel(const TA* __restrict__ A, int64_t lda,
+                                                          int64_t d, const unsigned* off,
+                                                          const unsigned* perm,
+                                                          const unsigned* code,
+                                                          TOut* __restrict__ out, int64_t ldo) {
+  const unsigned bucket = blockIdx.x;
+  const int64_t col = (int64_t)blockIdx.y * kBlock + threadIdx.x;
+  const unsigned b0 = off[bucket], b1 = off[bucket + 1];
+  TAcc acc = TAcc(0);
+  if (col < d) {
+    unsigned p = b0;
+    for (; p + 4 <= b1; p += 4) {
+      TAcc v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const unsigned row = perm[p + t];
+        const TAcc a = (TAcc)__builtin_nontemporal_load(&A[(int64_t)row * lda + col]);
+        v[t] = (code[row] & 0x80000000u) ? -a : a;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc += v[t];
+    }
+    for (; p < b1; ++p) {
+      const unsigned row = perm[p];
+      const TAcc a = (TAcc)__builtin_nontemporal_load(&A[(int64_t)row * lda + col]);
+      acc += (code[row] & 0x80000000u) ? -a : a;
+    }
+    out[(int64_t)bucket * ldo + col] = (TOut)acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian:  S (M x K, row stride lds) with S_ij = N(0,1) * scale drawn from
+// Philox element i*K + j; stored as double (plain) or BF16 bits (mixed).
+// Columns K..lds-1 are zero.
+// ---------------------------------------------------------------------------
+template <typename TSel>
+__global__ void gauss_gen_kernel(TSel* S, int64_t M, int64_t K, int64_t lds, uint32_t seed,
+                                 uint64_t stream, double scale) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one Philox block each
+  const int64_t total = M * K;
+  const int64_t first = e * 4;
+  if (first >= total) return;
+  double z[4];
+  gaussian_block(seed, stream, (uint64_t)e, z);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t f = first + t;
+    if (f < total) {
+      const int64_t i = f / K, j = f % K;
+      const double v = z[t] * scale;
+      if constexpr (sizeof(TSel) == 8) {
+        S[i * lds + j] = v;
+      } else {
+        S[i * lds + j] = bf16_rne(v);
+      }
+    }
+  }
+}
+
+__global__ void zero_pad_cols(void* S, int elem, int64_t M, int64_t K, int64_t lds) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t padw = lds - K;
+  if (padw <= 0 || e >= M * padw) return;
+  const int64_t i = e / padw, j = K + e % padw;
+  if (elem == 8)
+    ((double*)S)[i * lds + j] = 0.0;
+  else
+    ((uint16_t*)S)[i * lds + j] = 0;
+}
+
+// P[z] (M x N) = S[:, kz] B[kz, :] in FP64 on the matrix cores
+// (v_mfma_f64_16x16x4: A operand lane l = row l%16, k l/16; B operand lane l =
+// col l%16, k l/16; result register r of lane l is row l/16 + 4r, column l%16).
+template <typename TS, typename TB>
+__global__ __launch_bounds__(kBlock) void gemm_f64_kernel(const TS* __restrict__ S, int64_t lds,
+                                                          int64_t M, int64_t K,
+                                                          const TB* __restrict__ B, int64_t ldb,
+                                                          int64_t N, int64_t kchunk,
+                                                          double* __restrict__ P) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ double Ss[BM][BK + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int lane = lane_id(), wave = wave_id();
+  const int wr = wave >> 1, wc = wave & 1;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    for (int e = threadIdx.x; e < BM * BK; e += kBlock) {
+      const int r = e / BK, c = e % BK;
+      const int64_t gr = m0 + r, gk = k0 + c;
+      Ss[r][c] = (gr < M && gk < ke) ? (double)S[gr * lds + gk] : 0.0;
+    }
+    for (int e = threadIdx.x; e < BK * BN; e += kBlock) {
+      const int r = e / BN, c = e % BN;
+      const int64_t gk = k0 + r, gc = n0 + c;
+      Bs[r][c] = (gk < ke && gc < N) ? (double)B[gk * ldb + gc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = Ss[wr * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wc * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* Pz = P + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
+        const int64_t col = n0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < M && col < N) Pz[row * N + col] = acc[i][j][r];
+      }
+}
+
+// P[z] (M x N) = S[:, kz] B[kz, :] with BF16 inputs and FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16: lane l holds 8 consecutive k, 8(l/16)..+7, of
+// row l%16 (A) / column l%16 (B); result register r of lane l is row
+// 4(l/16) + r, column l%16).
+template <typename TB>
+__global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(const uint16_t* __restrict__ S,
+                                                           int64_t lds, int64_t M, int64_t K,
+                                                           const TB* __restrict__ B, int64_t ldb,
+                                                           int64_t N, int64_t kchunk,
+                                                           float* __restrict__ P) {
+  constexpr int BM = 128, BN = 128, BK = 32, PAD = 8;
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM][BK + PAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][BK + PAD];
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int lane = lane_id(), wave = wave_id();
+  const int wr = wave >> 1, wc = wave & 1;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    // S tile: 128 rows x 32 k, 8 bf16 (16 B) per load; lds is a multiple of 8
+    for (int e = threadIdx.x; e < BM * (BK / 8); e += kBlock) {
+      const int r = e / (BK / 8), q = e % (BK / 8);
+      const int64_t gr = m0 + r, gk = k0 + 8 * q;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (gr < M && gk < ke) {
+        v = *(const uint4*)(S + gr * lds + gk);
+        if (gk + 8 > ke) {  // zero the k's beyond this split's end
+          uint16_t* h = (uint16_t*)&v;
+          for (int t = (int)(ke - gk); t < 8; ++t) h[t] = 0;
+        }
+      }
+      *(uint4*)&As[r][8 * q] = v;
+    }
+    // B tile: 32 k x 128 n, transposed into Bs[n][k] with BF16 rounding
+    for (int e = threadIdx.x; e < BK * BN; e += kBlock) {
+      const int r = e / BN, c = e % BN;
+      const int64_t gk = k0 + r, gc = n0 + c;
+      Bs[c][r] = (gk < ke && gc < N) ? bf16_rne(B[gk * ldb + gc]) : (uint16_t)0;
+    }
+    __syncthreads();
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)&As[wr * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8*)&Bs[wc * 64 + j * 16 + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  float* Pz = P + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wr * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t col = n0 + wc * 64 + j * 16 + (lane & 15);
+        if (row < M && col < N) Pz[row * N + col] = acc[i][j][r];
+      }
+}
+
+// out (M x N, row stride ldo) = sum_z P[z] in order z = 0..splits-1
+template <typename TP, typename TOut>
+__global__ void splitk_reduce_kernel(const TP* P, int splits, int64_t M, int64_t N, TOut* out,
+                                     int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += (double)P[(int64_t)z * M * N + e];
+  out[(e / N) * ldo + (e % N)] = (TOut)s;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline bool hip_ok() { return hipGetLastError() == hipSuccess; }
+
+// ---- Gaussian sketch driver -------------------------------------------------
+struct GaussPlan {
+  int64_t lds;     // padded row stride of S
+  int splits;
+  int64_t kchunk;
+  size_t s_bytes, p_bytes;
+};
+
+GaussPlan gauss_plan(const mihs_handle* h, int64_t M, int64_t K, int64_t N, int mixed) {
+  GaussPlan g;
+  const int BM = mixed ? 128 : 64, BN = mixed ? 128 : 64, BK = mixed ? 32 : 16;
+  g.lds = (K + 7) / 8 * 8;
+  const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
+  int64_t want = ceil_div(2 * (int64_t)h->num_cu, tiles);
+  const int64_t kmax = ceil_div(K, 8 * BK);  // keep >= 8 k-steps per split
+  if (want > kmax) want = kmax;
+  if (want < 1) want = 1;
+  if (want > 64) want = 64;
+  g.kchunk = ceil_div(ceil_div(K, want), BK) * BK;
+  g.splits = (int)ceil_div(K, g.kchunk);
+  g.s_bytes = align_up((size_t)M * g.lds * (mixed ? 2 : 8), 256);
+  g.p_bytes = align_up((size_t)g.splits * M * N * (mixed ? 4 : 8), 256);
+  return g;
+}
+
+// SA (M x N, row stride ldo, TOut) = G B with G = N(0,1)/sqrt(M) (M x K) from
+// Philox stream `stream`; B is K x N (row stride ldb, TB).
+template <typename TB>
+int run_gauss(const mihs_handle* h, const TB* B, int64_t K, int64_t N, int64_t ldb, int64_t M,
+              uint32_t seed, uint64_t stream_id, int mixed, void* out, int64_t ldo, char* ws,
+              size_t ws_bytes, hipStream_t st) {
+  const GaussPlan g = gauss_plan(h, M, K, N, mixed);
+  if (ws_bytes < g.s_bytes + g.p_bytes) return MIHS_ERR_WORKSPACE;
+  void* S = ws;
+  void* P = ws + g.s_bytes;
+  const double scale = 1.0 / sqrt((double)M);
+  const int64_t nblk = ceil_div(M * K, 4);
+  if (mixed)
+    hipLaunchKernelGGL(gauss_gen_kernel<uint16_t>, dim3((unsigned)ceil_div(nblk, 256)), dim3(256),
+                       0, st, (uint16_t*)S, M, K, g.lds, seed, stream_id, scale);
+  else
+    hipLaunchKernelGGL(gauss_gen_kernel<double>, dim3((unsigned)ceil_div(nblk, 256)), dim3(256), 0,
+                       st, (double*)S, M, K, g.lds, seed, stream_id, scale);
+  if (g.lds > K)
+    hipLaunchKernelGGL(zero_pad_cols, dim3((unsigned)ceil_div(M * (g.lds - K), 256)), dim3(256), 0,
+                       st, S, mixed ? 2 : 8, M, K, g.lds);
+  if (!hip_ok()) return MIHS_ERR_HIP;
+  if (mixed) {
+    dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)g.splits);
+    hipLaunchKernelGGL(gemm_bf16_kernel<TB>, grid, dim3(kBlock), 0, st, (const uint16_t*)S, g.lds,
+                       M, K, B, ldb, N, g.kchunk, (float*)P);
+    hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), dim3((unsigned)ceil_div(M * N, 256)),
+                       dim3(256), 0, st, (const float*)P, g.splits, M, N, (float*)out, ldo);
+  } else {
+    dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64), (unsigned)g.splits);
+    hipLaunchKernelGGL((gemm_f64_kernel<double, TB>), grid, dim3(kBlock), 0, st, (const double*)S, g.lds, M,
+                       K, B, ldb, N, g.kchunk, (double*)P);
+    hipLaunchKernelGGL((splitk_reduce_kernel<double, double>), dim3((unsigned)ceil_div(M * N, 256)),
+                       dim3(256), 0, st, (const double*)P, g.splits, M, N, (double*)out, ldo);
+  }
+  return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
+}
+
+// ---- CountSketch driver -------------------------------------------------------
+struct CsPlan {
+  size_t code, perm, hist, off, cursor, total;
+};
+CsPlan cs_plan(int64_t n, int64_t m) {
+  CsPlan p;
+  size_t o = 0;
+  p.code = o; o = align_up(o + (size_t)n * 4, 256);
+  p.perm = o; o = align_up(o + (size_t)n * 4, 256);
+  p.hist = o; o = align_up(o + (size_t)m * 4, 256);
+  p.off = o; o = align_up(o + (size_t)(m + 1) * 4, 256);
+  p.cursor = o; o = align_up(o + (size_t)m * 4, 256);
+  p.total = o;
+  return p;
+}
+
+template <typename TA, typename TAcc, typename TOut>
+int run_countsketch(const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint32_t seed,
+                    TOut* out, int64_t ldo, char* ws, size_t ws_bytes, hipStream_t st) {
+  const CsPlan p = cs_plan(n, m);
+  if (ws_bytes < p.total) return MIHS_ERR_WORKSPACE;
+  unsigned* code = (unsigned*)(ws + p.code);
+  unsigned* perm = (unsigned*)(ws + p.perm);
+  unsigned* hist = (unsigned*)(ws + p.hist);
+  unsigned* off = (unsigned*)(ws + p.off);
+  unsigned* cursor = (unsigned*)(ws + p.cursor);
+  if (hipMemsetAsync(hist, 0, (size_t)m * 4, st) != hipSuccess) return MIHS_ERR_HIP;
+  hipLaunchKernelGGL(cs_hash_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, m,
+                     seed, code, hist);
+  hipLaunchKernelGGL(cs_scan_kernel, dim3(1), dim3(kBlock), 0, st, hist, m, off, cursor);
+  hipLaunchKernelGGL(cs_scatter_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, code,
+                     m, cursor, perm);
+  hipLaunchKernelGGL(cs_sort_kernel, dim3((unsigned)m), dim3(kBlock), 0, st, off, perm);
+  hipLaunchKernelGGL((cs_accum_kernel<TA, TAcc, TOut>), dim3((unsigned)m, (unsigned)ceil_div(d, kBlock)),
+                     dim3(kBlock), 0, st, A, lda, d, off, perm, code, out, ldo);
+  return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
+}
+
+// ---- SRHT driver ----------------------------------------------------------------
+int srht_logB(int64_t n) {
+  int lb = 0;
+  while ((1LL << (lb + 1)) <= n && lb < 9) ++lb;
+  return lb;
+}
+
+template <typename TA, typename TY, typename TS>
+int run_srht(const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint32_t seed, TS* SA,
+             int64_t ldsa, char* ws, size_t ws_bytes, hipStream_t st) {
+  const size_t idx_bytes = align_up((size_t)m * 4, 256);
+  const int64_t ldy = (d + 3) / 4 * 4;
+  const size_t y_bytes = align_up((size_t)n * ldy * sizeof(TY), 256);
+  if (ws_bytes < idx_bytes + y_bytes) return MIHS_ERR_WORKSPACE;
+  int* idx = (int*)ws;
+  TY* Y = (TY*)(ws + idx_bytes);
+  const int logB = srht_logB(n);
+  const int B = 1 << logB;
+  const int64_t nhi = n >> logB;
+  hipLaunchKernelGGL(srht_rows_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, idx, m, n,
+                     seed);
+  const size_t sh1 = (size_t)B * kFwhtW * sizeof(TY);
+  if (hipFuncSetAttribute((const void*)srht_stage1<TA, TY>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh1) != hipSuccess)
+    return MIHS_ERR_HIP;
+  hipLaunchKernelGGL((srht_stage1<TA, TY>), dim3((unsigned)nhi, (unsigned)ceil_div(d, kFwhtW)),
+                     dim3(kBlock), sh1, st, A, lda, d, logB, seed, Y, ldy);
+  hipLaunchKernelGGL((srht_stage2<TY, TS>), dim3((unsigned)B, (unsigned)ceil_div(d, kS2Cols)),
+                     dim3(kBlock), 0, st, Y, ldy, d, logB, nhi, idx, m, SA, ldsa,
+                     1.0 / sqrt((double)m));
+  return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
+}
+
+__global__ __launch_bounds__(kBlock) void neg_dot_kernel(const double* X, const double* W,
+                                                         int64_t count, double* out) {
+  __shared__ double s_red[kWavesPerBlock];
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += kBlock) v += X[i] * W[i];
+  v = block_sum(v, s_red);
+  if (threadIdx.x == 0) *out = -v;
+}
+
+}  // namespace
+
+int launch_apply_rows(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,
+                      int64_t lda, const double* W, int64_t k, double* Y, int64_t ldy,
+                      hipStream_t st) {
+  (void)h;
+  if (ldy != k) return MIHS_ERR_UNSUPPORTED;
+  dim3 grid((unsigned)ceil_div(k, 64), (unsigned)ceil_div(n, 64), 1);
+  if (a_f32)
+    hipLaunchKernelGGL((gemm_f64_kernel<float, double>), grid, dim3(kBlock), 0, st,
+                       (const float*)A, lda, n, d, W, k, k, d, Y);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<double, double>), grid, dim3(kBlock), 0, st,
+                       (const double*)A, lda, n, d, W, k, k, d, Y);
+  return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
+}
+
+int launch_neg_dot(const double* X, const double* W, int64_t count, double* out,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(neg_dot_kernel, dim3(1), dim3(kBlock), 0, st, X, W, count, out);
+  return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
+}
+
+size_t sketch_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int64_t m2,
+                              int kind, int a_f32, int mixed) {
+  (void)a_f32;
+  switch (kind) {
+    case MIHS_GAUSSIAN: {
+      const GaussPlan g = gauss_plan(h, m, n, d, mixed);
+      return g.s_bytes + g.p_bytes;
+    }
+    case MIHS_SRHT: {
+      const int64_t ldy = (d + 3) / 4 * 4;
+      return align_up((size_t)m * 4, 256) + align_up((size_t)n * ldy * (mixed ? 4 : 8), 256);
+    }
+    case MIHS_COUNTSKETCH:
+      return cs_plan(n, m).total;
+    case MIHS_COUNT_GAUSS: {
+      const int64_t ldc = (d + 3) / 4 * 4;
+      const size_t ca = align_up((size_t)m * ldc * (mixed ? 4 : 8), 256);
+      const GaussPlan g = gauss_plan(h, m2, m, d, mixed);
+      const size_t a = cs_plan(n, m).total, b = g.s_bytes + g.p_bytes;
+      return ca + (a > b ? a : b);
+    }
+    default:
+      return 0;
+  }
+}
+
+int launch_sketch(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,
+                  int64_t lda, int kind, int64_t m, int64_t m2, uint32_t seed, int mixed,
+                  void* SA, int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t st) {
+  const size_t need = sketch_workspace_bytes(h, n, d, m, m2, kind, a_f32, mixed);
+  if (!ws || ws_bytes < need) return MIHS_ERR_WORKSPACE;
+  char* w = (char*)ws;
+  switch (kind) {
+    case MIHS_GAUSSIAN:
+      if (a_f32)
+        return run_gauss<float>(h, (const float*)A, n, d, lda, m, seed, 0, mixed, SA, ldsa, w, ws_bytes, st);
+      return run_gauss<double>(h, (const double*)A, n, d, lda, m, seed, 0, mixed, SA, ldsa, w, ws_bytes, st);
+    case MIHS_SRHT:
+      if (mixed) {
+        if (a_f32)
+          return run_srht<float, float, float>((const float*)A, n, d, lda, m, seed, (float*)SA, ldsa, w, ws_bytes, st);
+        return run_srht<double, float, float>((const double*)A, n, d, lda, m, seed, (float*)SA, ldsa, w, ws_bytes, st);
+      }
+      if (a_f32)
+        return run_srht<float, double, double>((const float*)A, n, d, lda, m, seed, (double*)SA, ldsa, w, ws_bytes, st);
+      return run_srht<double, double, double>((const double*)A, n, d, lda, m, seed, (double*)SA, ldsa, w, ws_bytes, st);
+    case MIHS_COUNTSKETCH:
+      if (mixed) {
+        if (a_f32)
+          return run_countsketch<float, float, float>((const float*)A, n, d, lda, m, seed, (float*)SA, ldsa, w, ws_bytes, st);
+        return run_countsketch<double, float, float>((const double*)A, n, d, lda, m, seed, (float*)SA, ldsa, w, ws_bytes, st);
+      }
+      if (a_f32)
+        return run_countsketch<float, double, double>((const float*)A, n, d, lda, m, seed, (double*)SA, ldsa, w, ws_bytes, st);
+      return run_countsketch<double, double, double>((const double*)A, n, d, lda, m, seed, (double*)SA, ldsa, w, ws_bytes, st);
+    case MIHS_COUNT_GAUSS: {
+      const int64_t ldc = (d + 3) / 4 * 4;
+      const size_t ca_bytes = align_up((size_t)m * ldc * (mixed ? 4 : 8), 256);
+      char* rest = w + ca_bytes;
+      const size_t rest_bytes = ws_bytes - ca_bytes;
+      int rc;
+      if (mixed) {
+        float* CA = (float*)w;
+        rc = a_f32 ? run_countsketch<float, float, float>((const float*)A, n, d, lda, m, seed, CA, ldc, rest, rest_bytes, st)
+                   : run_countsketch<double, float, float>((const double*)A, n, d, lda, m, seed, CA, ldc, rest, rest_bytes, st);
+        if (rc) return rc;
+        return run_gauss<float>(h, CA, m, d, ldc, m2, seed, 1, 1, SA, ldsa, rest, rest_bytes, st);
+      }
+      double* CA = (double*)w;
+      rc = a_f32 ? run_countsketch<float, double, double>((const float*)A, n, d, lda, m, seed, CA, ldc, rest, rest_bytes, st)
+                 : run_countsketch<double, double, double>((const double*)A, n, d, lda, m, seed, CA, ldc, rest, rest_bytes, st);
+      if (rc) return rc;
+      return run_gauss<double>(h, CA, m, d, ldc, m2, seed, 1, 0, SA, ldsa, rest, rest_bytes, st);
+    }
+    default:
+      return MIHS_ERR_INVALID;
+  }
+}
+
+}  // namespace mihs

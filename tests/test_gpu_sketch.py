@@ -1,0 +1,153 @@
+"""GPU parity: the sketch kernels against the oracle's sketches."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import hashes, sketches
+from gpu_common import announce, rel, requires_gpu, to_dev, torch
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def _mihs():
+    import paper_1912_03514_amd as mihs
+    return mihs
+
+
+def _rand(n, d, seed, dtype=np.float64):
+    return np.random.default_rng(seed).standard_normal((n, d)).astype(dtype)
+
+
+@pytest.mark.parametrize("n,d,m", [(64, 5, 16), (512, 33, 100), (4096, 70, 256),
+                                   (1 << 14, 100, 300), (1 << 15, 17, 2048)])
+def test_srht_plain(n, d, m):
+    mihs = _mihs()
+    A = _rand(n, d, n + d)
+    ref = sketches.srht_sketch(A, m, 31)
+    announce(f"srht plain n={n} d={d} m={m}")
+    SA = mihs.mihs_sketch(to_dev(A), "srht", m, 31).cpu().numpy()
+    # the GPU sums the transform in a different order: error ~ log2(n) ulps of sum |A|
+    bound = 4 * math.log2(n) * 2.0 ** -52 * np.abs(A).sum(axis=0).max() / math.sqrt(m)
+    assert np.max(np.abs(SA - ref)) <= bound
+
+
+def test_srht_signs_and_samples_exact():
+    """With A = I every entry of SA is +-1/sqrt(m) at the sampled Hadamard row
+    times the sign diagonal: signs and sampled indices must match exactly."""
+    mihs = _mihs()
+    n, m = 1 << 12, 64
+    A = np.eye(n)[:, :512].copy()
+    announce("srht identity exactness")
+    SA = mihs.mihs_sketch(to_dev(A), "srht", m, 77).cpu().numpy()
+    D = sketches.srht_signs(n, 77)
+    rows = sketches.srht_rows(m, n, 77)
+    expect = sketches.hadamard_entry(rows[:, None], np.arange(512)[None, :]) * D[None, :512]
+    assert np.array_equal(np.sign(SA), expect)
+    assert np.allclose(np.abs(SA), 1 / math.sqrt(m), rtol=1e-15, atol=0)
+
+
+def test_srht_full_size_sampled_entries():
+    """At the headline size (2^18 x 2048 FP64, m = 2048) sampled output entries
+    equal the direct O(n) sum of the definition."""
+    mihs = _mihs()
+    n, d, m, seed = 1 << 18, 2048, 2048, 8
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A = torch.randn(n, d, generator=g, dtype=torch.float64, device="cuda")
+    announce("srht full size 2^18 x 2048")
+    SA = mihs.mihs_sketch(A, "srht", m, seed).cpu().numpy()
+    rng = np.random.default_rng(0)
+    ks = rng.integers(0, m, 6)
+    cols = np.sort(rng.choice(d, 8, replace=False))
+    Ac = A[:, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+    for k in ks:
+        ref = sketches.srht_entry(Ac, m, seed, int(k), slice(None))
+        assert np.max(np.abs(SA[k, cols] - ref)) <= 1e-12 * math.sqrt(n), k
+
+
+@pytest.mark.parametrize("adt", [np.float64, np.float32])
+def test_srht_mixed(adt):
+    mihs = _mihs()
+    n, d, m = 1 << 13, 50, 128
+    A = _rand(n, d, 3, adt)
+    ref = sketches.srht_sketch(A, m, 5)
+    announce(f"srht mixed {adt.__name__}")
+    SA = mihs.mihs_sketch(to_dev(A), "srht", m, 5, precision="mixed")
+    assert SA.dtype == torch.float32
+    SA = SA.cpu().numpy().astype(np.float64)
+    bound = 4 * math.log2(n) * 2.0 ** -23 * np.abs(A).astype(np.float64).sum(axis=0).max() / math.sqrt(m)
+    assert np.max(np.abs(SA - ref)) <= bound
+
+
+@pytest.mark.parametrize("n,d,m", [(1, 3, 4), (300, 7, 16), (5000, 70, 128), (20000, 300, 1000),
+                                   (70000, 33, 8192)])
+def test_countsketch_bit_exact(n, d, m):
+    """Rows are summed per bucket in ascending row order in FP64 on both sides:
+    the result is bit-identical, which pins hashes, buckets and signs exactly."""
+    mihs = _mihs()
+    A = _rand(n, d, n)
+    ref = sketches.countsketch(A, m, 12345)
+    announce(f"countsketch n={n} d={d} m={m}")
+    SA = mihs.mihs_sketch(to_dev(A), "countsketch", m, 12345).cpu().numpy()
+    assert np.array_equal(SA, ref)
+
+
+def test_countsketch_fp32_matrix():
+    mihs = _mihs()
+    A = _rand(10000, 64, 2, np.float32)
+    ref = sketches.countsketch(A, 256, 9)
+    announce("countsketch fp32 A plain")
+    SA = mihs.mihs_sketch(to_dev(A), "countsketch", 256, 9).cpu().numpy()
+    assert np.array_equal(SA, ref)  # float -> double is exact; same order
+    announce("countsketch fp32 A mixed")
+    SAm = mihs.mihs_sketch(to_dev(A), "countsketch", 256, 9, precision="mixed").cpu().numpy()
+    assert np.max(np.abs(SAm - ref)) <= 64 * 2.0 ** -23 * np.abs(A).sum(axis=0).max()
+
+
+@pytest.mark.parametrize("n,d,m", [(4096, 256, 256), (1000, 37, 50), (300, 5, 300)])
+def test_gaussian_plain(n, d, m):
+    mihs = _mihs()
+    A = _rand(n, d, 4)
+    ref = sketches.gaussian_sketch(A, m, 7)
+    announce(f"gaussian plain n={n} d={d} m={m}")
+    SA = mihs.mihs_sketch(to_dev(A), "gaussian", m, 7).cpu().numpy()
+    scale = np.sqrt(n / m) * np.abs(A).max()
+    assert np.max(np.abs(SA - ref)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n,d,m", [(4096, 256, 256), (1000, 37, 50), (2048, 130, 384)])
+def test_gaussian_mixed_bf16(n, d, m):
+    """BF16 S and BF16 A on the matrix cores, FP32 accumulation: compare with
+    the BF16-rounded product, within FP32 accumulation error."""
+    mihs = _mihs()
+    A = _rand(n, d, 4)
+    ref = sketches.gaussian_sketch_bf16(A, m, 7)
+    announce(f"gaussian mixed n={n} d={d} m={m}")
+    SA = mihs.mihs_sketch(to_dev(A), "gaussian", m, 7, precision="mixed")
+    assert SA.dtype == torch.float32
+    SA = SA.cpu().numpy().astype(np.float64)
+    S = np.abs(sketches.gaussian_matrix(m, n, 7))
+    bound = (n + 2) * 2.0 ** -24 * (S @ np.abs(A)) + 1e-30
+    assert np.all(np.abs(SA - ref) <= bound)
+    # and it is a BF16-accurate sketch of the exact product
+    exact = sketches.gaussian_sketch(A, m, 7)
+    assert rel(SA, exact) < 2e-2
+
+
+def test_count_gauss_plain_and_mixed():
+    mihs = _mihs()
+    n, d, m1, m2 = 30000, 48, 512, 128
+    A = _rand(n, d, 6, np.float32)
+    ref = sketches.count_gauss_sketch(A, m1, m2, 99)
+    announce("count_gauss plain")
+    SA = mihs.mihs_sketch(to_dev(A), "count_gauss", m1, 99, m2=m2).cpu().numpy()
+    assert SA.shape == (m2, d)
+    assert rel(SA, ref) <= 1e-13
+    announce("count_gauss mixed")
+    SAm = mihs.mihs_sketch(to_dev(A), "count_gauss", m1, 99, m2=m2, precision="mixed")
+    SAm = SAm.cpu().numpy().astype(np.float64)
+    CA = sketches.countsketch(A, m1, 99)
+    refm = sketches.gaussian_sketch_bf16(CA, m2, 99, stream=1)
+    # FP32 bucket sums may round to a neighbouring BF16 value in a few entries
+    assert rel(SAm, refm) <= 1e-3
+    assert rel(SAm, ref) <= 2e-2

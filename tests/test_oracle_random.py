@@ -116,3 +116,17 @@ def test_count_gauss_composition():
     C = sketches.countsketch_matrix(n, m1, 5)
     G = sketches.gaussian_matrix(m2, m1, 5, stream=1)
     assert np.allclose(sketches.count_gauss_sketch(A, m1, m2, 5), G @ (C @ A), atol=1e-12)
+
+
+def test_bf16_round_matches_torch_on_float32_inputs():
+    """On float32-representable inputs torch's float32 -> bfloat16 conversion is a
+    single round-to-nearest-even, so it pins the oracle's rounding."""
+    import torch
+    rng = np.random.default_rng(0)
+    x = (rng.standard_normal(200_000) * np.exp(rng.uniform(-30, 30, 200_000)))
+    x = x.astype(np.float32).astype(np.float64)
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(sketches.bf16_round(x), ref)
+    # ties go to even
+    t = np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8])
+    assert np.array_equal(sketches.bf16_round(t), [1.0, 1.0 + 4 * 2.0 ** -8])

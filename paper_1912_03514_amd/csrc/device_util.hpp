@@ -114,35 +114,107 @@ __device__ __forceinline__ void load_row(const T* __restrict__ row, int d, int l
   }
 }
 
-// Device-wide barrier for a cooperative launch of `nblocks` workgroups.  The
-// counter only grows; barrier number e waits for e * nblocks arrivals.  The
-// wait is bounded: after `spin_limit` polls the barrier records a timeout in
-// *err and every workgroup leaves, so no wave can hang.  Returns false once an
-// error is recorded (callers then exit).
-__device__ __forceinline__ bool grid_barrier(unsigned* counter, unsigned& epoch, unsigned nblocks,
-                                             int* err, int* s_flag, long spin_limit) {
+// Device-wide barriers for a cooperative launch.  Counters only grow: barrier
+// number e of a group of `nblocks` workgroups waits for e * nblocks arrivals.
+// Arrival is a release fetch-add, the wait relaxed polling followed by an
+// acquire fence, so data written before the barrier is visible after it on
+// every XCD.  The wait is bounded:
+// after `spin_limit` polls it records a timeout in *err and returns false, so
+// no wave can hang; callers then leave the kernel.
+struct BarrierSpin {
+  long limit;
+  int sleep;  // s_sleep argument between polls (x64 clocks)
+};
+
+__device__ __forceinline__ bool wait_counter(const unsigned* counter, unsigned target, int* err,
+                                             BarrierSpin spin) {
+  // Poll with relaxed loads (an acquire load would invalidate this XCD's L2 on
+  // every poll, evicting data the working workgroups are reusing); one acquire
+  // fence after the wait orders the reads that follow.
+  long spins = 0;
+  while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (spin.sleep >= 16)
+      __builtin_amdgcn_s_sleep(16);
+    else
+      __builtin_amdgcn_s_sleep(1);
+    if (++spins > spin.limit) {
+      atomicOr(err, 1);
+      return false;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
+// One counter shared by all `nblocks` workgroups (cheap for small groups).
+__device__ __forceinline__ bool barrier_flat(unsigned* counter, unsigned& epoch, unsigned nblocks,
+                                             int* err, int* s_flag, BarrierSpin spin) {
   __syncthreads();
   epoch += 1u;
   if (threadIdx.x == 0) {
-    const unsigned target = epoch * nblocks;
-    __threadfence();
-    atomicAdd(counter, 1u);
-    long spins = 0;
-    int ok = 1;
-    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > spin_limit) {
-        atomicOr(err, 1);
-        ok = 0;
-        break;
-      }
-    }
-    __threadfence();
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = wait_counter(counter, epoch * nblocks, err, spin) ? 1 : 0;
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
     *s_flag = ok;
   }
   __syncthreads();
   return *s_flag != 0;
+}
+
+// Two-level barrier for large grids: workgroups arrive on one of 8 group
+// counters (blockIdx % 8, one 128-byte line each); the last arrival of a group
+// arrives on the top counter, which everybody waits on.  `words` points at
+// 9 lines: top counter first, then the group counters.
+__device__ __forceinline__ bool barrier_hier(unsigned* words, unsigned& epoch, unsigned nblocks,
+                                             int* err, int* s_flag, BarrierSpin spin) {
+  __syncthreads();
+  epoch += 1u;
+  if (threadIdx.x == 0) {
+    const unsigned g = blockIdx.x & 7u;
+    const unsigned ngroups = nblocks < 8u ? nblocks : 8u;
+    const unsigned gsize = (nblocks - g + 7u) / 8u;
+    unsigned* top = words;
+    unsigned* gc = words + 32u * (1u + g);
+    const unsigned old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == epoch * gsize - 1u)
+      __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = wait_counter(top, epoch * ngroups, err, spin) ? 1 : 0;
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+// Column sums of a K x ncols block: out[c] = sum_k P[k * ldp + c0 + c], c < ncols,
+// in a fixed order (per thread over k, then a fixed tree in LDS).  All loads of a
+// chunk are independent, so they are in flight together.  `scratch` holds
+// kBlock doubles; `out` is LDS.  Call from the whole workgroup.
+template <typename T>
+__device__ __forceinline__ void column_sums(const T* __restrict__ P, int K, int64_t ldp, int c0,
+                                            int ncols, double* out, double* scratch) {
+  for (int cc0 = 0; cc0 < ncols; cc0 += kBlock) {
+    const int CC = min(kBlock, ncols - cc0);
+    int TPC = 1;
+    while (TPC * 2 * CC <= kBlock) TPC *= 2;
+    const int t = threadIdx.x;
+    const int col = t % CC, ks = t / CC;
+    double s = 0.0;
+    if (ks < TPC) {
+      const T* base = P + c0 + cc0 + col;
+#pragma unroll 8
+      for (int k = ks; k < K; k += TPC) s += (double)base[(int64_t)k * ldp];
+    }
+    __syncthreads();
+    scratch[t] = s;
+    __syncthreads();
+    if (t < CC) {
+      double a = scratch[t];
+      for (int i = 1; i < TPC; ++i) a += scratch[i * CC + t];
+      out[cc0 + t] = a;
+    }
+    __syncthreads();
+  }
 }
 
 }  // namespace mihs

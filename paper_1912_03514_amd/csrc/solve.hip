@@ -1,27 +1,31 @@
 // Persistent M-IHS solve kernel (Algorithm 1 with a CG inner solver).
 //
-// One cooperative launch runs the whole outer loop.  Every workgroup stays
-// resident; phases are separated by a device-wide barrier:
+// One cooperative launch runs the whole outer loop.  All G workgroups stream
+// A; a subgroup of the first Gc workgroups runs the inner solve, so the inner
+// loop only pays for a small, fast barrier.  Phases:
 //
-//   A1  stage x in LDS; stream this workgroup's contiguous row block of A once:
-//       each wave holds whole rows in registers, forms r_i = b_i - A_i x by a
-//       wave reduction and accumulates A_i^T r_i into per-lane partial
-//       gradients; the four waves combine in LDS and write one partial d-vector.
-//   A2  column owners add the partials (fixed order), form
-//       g = sum + rhs - lambda x and start CG (z = 0, r = p = g).
-//   CG  per iteration two barriers:
-//       C1  every workgroup forms p = r + beta_cg p_prev in LDS (owners also
-//           store their slice), and the first Gcg workgroups stream their rows
-//           of SA: u_j = SA_j p, partial -SA^T u, sum u_j^2.
-//       C2  p^T q = ||u||^2 + lambda ||p||^2 (scalar partials, fixed order),
-//           owners form q = -sum + lambda p and update z, r.
-//       The stop test ||r|| <= eps_sub ||g|| uses sums that every workgroup
-//       computes identically, so all leave the loop together.
-//   U   owners apply the heavy-ball step x+ = x + alpha z + beta (x - x_prev)
-//       and the relative-step stop test.
+//   A1  (all G)  stage x in LDS; stream this workgroup's contiguous row block
+//       of A once: each wave holds whole rows in registers, forms
+//       r_i = b_i - A_i x by a wave reduction and accumulates A_i^T r_i into
+//       per-lane partial gradients; the four waves combine in LDS and write one
+//       partial d-vector.                                   -> barrier (all)
+//   A2  (Gc)     column owners add the G partials (fixed order), form
+//       g = sum + rhs - lambda x and start CG (z = 0, r = p = g).  -> barrier (Gc)
+//   CG  (Gc)     per iteration two barriers:
+//       C1  every CG workgroup forms p = r + beta_cg p_prev in LDS (owners
+//           also store their slice) and streams its rows of SA:
+//           u_j = SA_j p, partial -SA^T u, sum u_j^2.        -> barrier (Gc)
+//       C2  p^T q = ||u||^2 + lambda ||p||^2 (scalar partials, fixed order);
+//           owners form q = -sum + lambda p and update z, r. -> barrier (Gc)
+//       The stop test ||r|| <= eps_sub ||g|| uses sums every CG workgroup
+//       computes identically, so they all leave the loop together.
+//   U   (Gc)     owners apply x+ = x + alpha z + beta (x - x_prev) and write
+//       the relative-step partials.                          -> barrier (all)
+//       Every workgroup then evaluates the same stop test.
 //
 // Every reduction runs in a fixed order, so a solve is bit-reproducible.
 #include <math.h>
+#include <stdlib.h>
 
 #include "device_util.hpp"
 #include "internal.hpp"
@@ -48,32 +52,34 @@ struct SolveArgs {
   double* xp;
   int xp_from_x;
   mihs_info_t* info;
-  double* partA;
-  void* partS;
-  double* scal;
+  double* partA;   // G x dpad
+  void* partS;     // Gc x dpad (TV)
+  double* scal;    // G x kScal
   void* r;
   void* z;
   void* p0;
   void* p1;
-  unsigned* bar;
+  unsigned* bar_all;  // 9 lines (hierarchical barrier)
+  unsigned* bar_cg;   // 1 line
   int* err;
-  int d, dpad, G, Gcg, cpw;
-  long spin_limit;
+  int* status;        // decision published by the CG group
+  int d, dpad, G, Gc, cpw;
+  BarrierSpin spin_fast, spin_idle;
 };
 
-template <int EPT>
+template <typename TM, int EPT>
 struct RowsInFlight {
-  static constexpr int value = EPT >= 64 ? 1 : (EPT >= 8 ? 2 : 4);
+  static constexpr int kBytes = EPT * (int)sizeof(TM);   // bytes per lane per row
+  static constexpr int value = kBytes >= 512 ? 1 : (kBytes >= 256 ? 2 : 4);
 };
 
 // One pass over rows [r0, r1) of M: for each row, u = c_row - M_row . v and
 // acc += u * M_row (acc in this lane's columns), ssq += u^2.
-template <typename TM, typename TV, int EPT, bool NT>
+template <typename TM, typename TV, int EPT, bool NT, int R>
 __device__ __forceinline__ void rowpass(const TM* __restrict__ M, int64_t ld, int64_t r0,
                                         int64_t r1, int d, const TV* __restrict__ v,
                                         const double* __restrict__ c, TV (&acc)[EPT], TV& ssq) {
   using L = RowLayout<TM, EPT>;
-  constexpr int R = RowsInFlight<EPT>::value;
   const int lane = lane_id();
   for (int64_t row = r0 + (int64_t)wave_id() * R; row < r1; row += (int64_t)kWavesPerBlock * R) {
     TM rv[R][EPT];
@@ -144,34 +150,115 @@ __device__ __forceinline__ TV wg_sum_ssq(TV ssq, double* s_red) {
   return (TV)t;
 }
 
+// Two scalar sums over K workgroups' slots (fixed order), returned to every thread.
+__device__ __forceinline__ void sum2_slots(const double* scal, int K, int s0, int s1,
+                                           double* s_red2, double& o0, double& o1) {
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < K; k += kBlock) {
+    a += scal[(int64_t)k * kScal + s0];
+    b += scal[(int64_t)k * kScal + s1];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if (lane_id() == 0) {
+    s_red2[2 * wave_id()] = a;
+    s_red2[2 * wave_id() + 1] = b;
+  }
+  __syncthreads();
+  o0 = s_red2[0];
+  o1 = s_red2[1];
+  for (int w = 1; w < kWavesPerBlock; ++w) {
+    o0 += s_red2[2 * w];
+    o1 += s_red2[2 * w + 1];
+  }
+}
+
+// Column sums over K partial vectors for this workgroup's owned columns,
+// out[i] = sum_k P[k * ldp + c0 + i], with every load of a thread issued before
+// any is used (one memory round trip for K <= 16 * threads-per-column).
+template <typename T>
+__device__ __forceinline__ void owned_column_sums(const T* __restrict__ P, int K, int64_t ldp,
+                                                  int c0, int ncols, double* out,
+                                                  double* scratch) {
+  constexpr int NB = 16;
+  for (int cc0 = 0; cc0 < ncols; cc0 += kBlock) {
+    const int CC = min(kBlock, ncols - cc0);
+    int TPC = 1;
+    while (TPC * 2 * CC <= kBlock) TPC *= 2;
+    const int t = threadIdx.x;
+    const int col = t % CC, ks = t / CC;
+    double s = 0.0;
+    if (ks < TPC) {
+      const T* base = P + c0 + cc0 + col;
+      for (int k0 = ks; k0 < K; k0 += NB * TPC) {
+        T v[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int k = k0 + i * TPC;
+          v[i] = (k < K) ? base[(int64_t)k * ldp] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) s += (double)v[i];
+      }
+    }
+    __syncthreads();
+    scratch[t] = s;
+    __syncthreads();
+    if (t < CC) {
+      double acc = scratch[t];
+      for (int i = 1; i < TPC; ++i) acc += scratch[i * CC + t];
+      out[cc0 + t] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename TA, typename TS, typename TV, int EPT>
 __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   extern __shared__ double smem[];
-  double* vbuf = smem;           // x (A pass) or p (CG, as TV)
-  double* rbuf = smem + a.dpad;  // workgroup reduction buffer
-  __shared__ double s_red[kWavesPerBlock];
+  const int cpw = a.cpw;
+  double* vbuf = smem;                 // x (A pass) or p (CG, as TV)
+  double* rbuf = vbuf + a.dpad;        // workgroup reduction buffer
+  double* colbuf = rbuf + a.dpad;      // owned-column sums
+  double* scratch = colbuf + cpw;      // kBlock doubles
+  double* own_x = scratch + kBlock;    // owner-private state of the owned columns
+  double* own_xp = own_x + cpw;
+  double* own_rhs = own_xp + cpw;
+  TV* own_r = (TV*)(own_rhs + cpw);
+  TV* own_z = (TV*)(own_rhs + 2 * cpw);
+  __shared__ double s_red[2 * kWavesPerBlock];
   __shared__ int s_flag;
 
   const int w = blockIdx.x;
-  const int G = a.G;
+  const int G = a.G, Gc = a.Gc;
   const int d = a.d;
-  unsigned epoch = 0;
-  const int c_lo = min(d, w * a.cpw);
-  const int c_hi = min(d, c_lo + a.cpw);
+  const bool in_cg = w < Gc;
+  unsigned ep_all = 0, ep_cg = 0;
+  const int c_lo = in_cg ? min(d, w * cpw) : d;
+  const int c_hi = in_cg ? min(d, c_lo + cpw) : d;
+  const int nown = c_hi - c_lo;
   double* scal_w = a.scal + (int64_t)w * kScal;
   TV* r = (TV*)a.r;
-  TV* z = (TV*)a.z;
   TV* P[2] = {(TV*)a.p0, (TV*)a.p1};
   TV* partS = (TV*)a.partS;
   const TA* A = (const TA*)a.A;
   const TS* SA = (const TS*)a.SA;
+  constexpr int RA = RowsInFlight<TA, EPT>::value;
+  constexpr int RS = RowsInFlight<TS, EPT>::value;
+  constexpr int NPT = EPT >= 4 ? EPT / 4 : 1;  // vector entries per thread (dpad / kBlock)
 
-  if (a.xp_from_x)
-    for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock) a.xp[c] = a.x[c];
+  for (int i = threadIdx.x; i < nown; i += kBlock) {
+    const int c = c_lo + i;
+    own_x[i] = a.x[c];
+    own_xp[i] = a.xp_from_x ? a.x[c] : a.xp[c];
+    own_rhs[i] = a.rhs ? a.rhs[c] : 0.0;
+  }
+  __syncthreads();
 
   const int64_t a_r0 = a.n * w / G, a_r1 = a.n * (w + 1) / G;
-  const int64_t s_r0 = (w < a.Gcg) ? a.m * w / a.Gcg : 0;
-  const int64_t s_r1 = (w < a.Gcg) ? a.m * (w + 1) / a.Gcg : 0;
+  const int64_t s_r0 = in_cg ? a.m * w / Gc : 0;
+  const int64_t s_r1 = in_cg ? a.m * (w + 1) / Gc : 0;
 
   int64_t outer = 0, inner_total = 0, inner_max = 0;
   double last_step = 0.0, last_gnorm = 0.0;
@@ -179,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   bool alive = true;
 
   while (outer < a.max_outer) {
-    // ---- A1: partial A^T (b - A x) over this workgroup's rows
+    // ---- A1 (all): partial A^T (b - A x) over this workgroup's rows
     for (int c = threadIdx.x; c < a.dpad; c += kBlock) vbuf[c] = (c < d) ? a.x[c] : 0.0;
     __syncthreads();
     {
@@ -187,125 +274,161 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) acc[e] = 0.0;
       double ssq = 0.0;
-      rowpass<TA, double, EPT, true>(A, a.lda, a_r0, a_r1, d, vbuf, a.b, acc, ssq);
+      rowpass<TA, double, EPT, true, RA>(A, a.lda, a_r0, a_r1, d, vbuf, a.b, acc, ssq);
       wg_store_partial<TA, double, EPT>(acc, rbuf, a.partA + (int64_t)w * a.dpad, d);
     }
-    if (!(alive = grid_barrier(a.bar, epoch, G, a.err, &s_flag, a.spin_limit))) break;
+    if (!(alive = barrier_hier(a.bar_all, ep_all, G, a.err, &s_flag, a.spin_fast))) break;
 
-    // ---- A2: owners form g and start CG
-    double rr_part = 0.0;
-    for (int c = c_lo; c < c_hi; ++c) {
-      const double s = block_sum_strided(a.partA + c, G, a.dpad, s_red);
-      if (threadIdx.x == 0) {
-        const double g = s + (a.rhs ? a.rhs[c] : 0.0) - a.lam * a.x[c];
-        const TV gt = (TV)g;
-        r[c] = gt;
-        z[c] = TV(0);
-        P[0][c] = gt;
+    int decision = 0;  // 0 continue, 1 converged, 2 breakdown
+    if (in_cg) {
+      // ---- A2: owners form g and start CG (z = 0, r = p = g)
+      owned_column_sums(a.partA, G, a.dpad, c_lo, nown, colbuf, scratch);
+      double rr_part = 0.0;
+      for (int i = threadIdx.x; i < nown; i += kBlock) {
+        const TV gt = (TV)(colbuf[i] + own_rhs[i] - a.lam * own_x[i]);
+        own_r[i] = gt;
+        own_z[i] = TV(0);
+        r[c_lo + i] = gt;
+        P[0][c_lo + i] = gt;
         rr_part += (double)gt * (double)gt;
       }
-    }
-    if (threadIdx.x == 0) scal_w[0] = rr_part;
-    if (!(alive = grid_barrier(a.bar, epoch, G, a.err, &s_flag, a.spin_limit))) break;
+      rr_part = block_sum(rr_part, s_red);
+      if (threadIdx.x == 0) scal_w[0] = rr_part;
+      if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
 
-    const double rr0 = block_sum_strided(a.scal + 0, G, kScal, s_red);
-    last_gnorm = sqrt(rr0);
-    if (!(rr0 > 0.0)) {  // stationary point (or NaN)
-      status = (rr0 == 0.0) ? MIHS_CONVERGED : MIHS_BREAKDOWN;
+      double rr0, unused;
+      sum2_slots(a.scal, Gc, 0, 0, s_red, rr0, unused);
+      last_gnorm = sqrt(rr0);
+      int64_t k = 0;
+      if (!(rr0 > 0.0)) {
+        decision = (rr0 == 0.0) ? 1 : 2;  // stationary point, or NaN
+      } else {
+        const double stop = a.eps_sub * a.eps_sub * rr0;
+        double rr = rr0;
+        TV* vp = (TV*)vbuf;
+        while (true) {
+          // ---- C1: p = r + beta_cg p_prev (k > 0), staged in LDS.  The loads of
+          // r, p_prev and the residual partials are all issued before use.
+          TV* pcur = P[k & 1];
+          const TV* pprev = P[(k + 1) & 1];
+          TV rv[NPT], pv[NPT];
+#pragma unroll
+          for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + i * kBlock;
+            rv[i] = TV(0);
+            pv[i] = TV(0);
+            if (c < d) {
+              if (k == 0) {
+                rv[i] = pcur[c];
+              } else {
+                rv[i] = r[c];
+                pv[i] = pprev[c];
+              }
+            }
+          }
+          TV bc = TV(0);
+          if (k > 0) {
+            double rr_new;
+            sum2_slots(a.scal, Gc, 3, 3, s_red, rr_new, unused);
+            if (rr_new <= stop || k >= a.max_inner) break;
+            bc = (TV)(rr_new / rr);
+            rr = rr_new;
+          }
+#pragma unroll
+          for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + i * kBlock;
+            if (c < a.dpad) {
+              const TV p = (k == 0) ? rv[i] : (TV)(rv[i] + bc * pv[i]);
+              vp[c] = (c < d) ? p : TV(0);
+              if (k > 0 && c >= c_lo && c < c_hi) pcur[c] = p;
+            }
+          }
+          for (int c = NPT * kBlock + threadIdx.x; c < a.dpad; c += kBlock) vp[c] = TV(0);
+          __syncthreads();
+          TV ssq = TV(0);
+          {
+            TV acc[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) acc[e] = TV(0);
+            rowpass<TS, TV, EPT, false, RS>(SA, a.ldsa, s_r0, s_r1, d, vp, nullptr, acc, ssq);
+            wg_store_partial<TS, TV, EPT>(acc, (TV*)rbuf, partS + (int64_t)w * a.dpad, d);
+            ssq = wg_sum_ssq(ssq, s_red);
+          }
+          double pp = 0.0;
+          for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock) pp += (double)vp[c] * (double)vp[c];
+          pp = block_sum(pp, s_red);
+          if (threadIdx.x == 0) {
+            scal_w[1] = pp;
+            scal_w[2] = (double)ssq;
+          }
+          if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+
+          // ---- C2: step length (p^T q = ||u||^2 + lambda ||p||^2) and owner updates
+          owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
+          double ppn, uu;
+          sum2_slots(a.scal, Gc, 1, 2, s_red, ppn, uu);
+          const double pq = uu + a.lam * ppn;
+          const double acg = rr / pq;
+          if (!(pq > 0.0) || !isfinite(acg)) {
+            decision = 2;
+            break;
+          }
+          double rpart = 0.0;
+          const TV at = (TV)acg, lt = (TV)a.lam;
+          for (int i = threadIdx.x; i < nown; i += kBlock) {
+            const TV pc = vp[c_lo + i];
+            const TV q = (TV)(-colbuf[i]) + lt * pc;
+            own_z[i] = own_z[i] + at * pc;
+            const TV rn = own_r[i] - at * q;
+            own_r[i] = rn;
+            r[c_lo + i] = rn;
+            rpart += (double)rn * (double)rn;
+          }
+          rpart = block_sum(rpart, s_red);
+          if (threadIdx.x == 0) scal_w[3] = rpart;
+          if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+          ++k;
+        }
+        if (!alive) break;
+      }
+      inner_total += k;
+      if (k > inner_max) inner_max = k;
+
+      // ---- U: heavy-ball update on owned columns
+      double s0 = 0.0, s1 = 0.0;
+      if (decision == 0) {
+        for (int i = threadIdx.x; i < nown; i += kBlock) {
+          const double xc = own_x[i];
+          const double xn = xc + a.alpha * (double)own_z[i] + a.beta * (xc - own_xp[i]);
+          own_xp[i] = xc;
+          own_x[i] = xn;
+          a.x[c_lo + i] = xn;
+          s0 += (xn - xc) * (xn - xc);
+          s1 += xn * xn;
+        }
+      }
+      s0 = block_sum(s0, s_red);
+      s1 = block_sum(s1, s_red);
+      if (threadIdx.x == 0) {
+        scal_w[4] = s0;
+        scal_w[5] = s1;
+        if (w == 0) *a.status = decision;
+      }
+    }
+    if (!(alive = barrier_hier(a.bar_all, ep_all, G, a.err, &s_flag,
+                               in_cg ? a.spin_fast : a.spin_idle)))
+      break;
+    decision = __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (decision == 1) {
+      status = MIHS_CONVERGED;
       break;
     }
-    const double stop = a.eps_sub * a.eps_sub * rr0;
-    double rr = rr0, bcg = 0.0;
-    int64_t k = 0;
-    bool breakdown = false;
-    while (true) {
-      // ---- C1: p = r + beta_cg p_prev (k > 0), staged in LDS; pass over SA
-      TV* vp = (TV*)vbuf;
-      TV* pcur = P[k & 1];
-      const TV* pprev = P[(k + 1) & 1];
-      const TV bc = (TV)bcg;
-      for (int c = threadIdx.x; c < a.dpad; c += kBlock) {
-        TV pv = TV(0);
-        if (c < d) {
-          pv = (k == 0) ? pcur[c] : (TV)(r[c] + bc * pprev[c]);
-          if (k > 0 && c >= c_lo && c < c_hi) pcur[c] = pv;
-        }
-        vp[c] = pv;
-      }
-      __syncthreads();
-      double pp = 0.0;
-      if (threadIdx.x == 0)
-        for (int c = c_lo; c < c_hi; ++c) pp += (double)vp[c] * (double)vp[c];
-      TV ssq = TV(0);
-      if (w < a.Gcg) {
-        TV acc[EPT];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) acc[e] = TV(0);
-        rowpass<TS, TV, EPT, false>(SA, a.ldsa, s_r0, s_r1, d, vp, nullptr, acc, ssq);
-        wg_store_partial<TS, TV, EPT>(acc, (TV*)rbuf, partS + (int64_t)w * a.dpad, d);
-        ssq = wg_sum_ssq(ssq, s_red);
-      }
-      if (threadIdx.x == 0) {
-        scal_w[1] = pp;
-        scal_w[2] = (double)ssq;
-      }
-      if (!(alive = grid_barrier(a.bar, epoch, G, a.err, &s_flag, a.spin_limit))) break;
-
-      // ---- C2: step length and owner updates
-      const double uu = block_sum_strided(a.scal + 2, G, kScal, s_red);
-      const double ppn = block_sum_strided(a.scal + 1, G, kScal, s_red);
-      const double pq = uu + a.lam * ppn;
-      const double acg = rr / pq;
-      if (!(pq > 0.0) || !isfinite(acg)) {
-        breakdown = true;
-        break;
-      }
-      double rpart = 0.0;
-      const TV at = (TV)acg, lt = (TV)a.lam;
-      for (int c = c_lo; c < c_hi; ++c) {
-        const double qs = block_sum_strided(partS + c, a.Gcg, a.dpad, s_red);
-        if (threadIdx.x == 0) {
-          const TV pc = vp[c];
-          const TV q = (TV)(-qs) + lt * pc;
-          z[c] = z[c] + at * pc;
-          const TV rn = r[c] - at * q;
-          r[c] = rn;
-          rpart += (double)rn * (double)rn;
-        }
-      }
-      if (threadIdx.x == 0) scal_w[3] = rpart;
-      if (!(alive = grid_barrier(a.bar, epoch, G, a.err, &s_flag, a.spin_limit))) break;
-      const double rr_new = block_sum_strided(a.scal + 3, G, kScal, s_red);
-      ++k;
-      bcg = rr_new / rr;
-      rr = rr_new;
-      if (rr <= stop || k >= a.max_inner) break;
-    }
-    if (!alive) break;
-    inner_total += k;
-    if (k > inner_max) inner_max = k;
-    if (breakdown) {
+    if (decision == 2) {
       status = MIHS_BREAKDOWN;
       break;
     }
-
-    // ---- U: heavy-ball update on owned columns, relative-step test
-    double s0 = 0.0, s1 = 0.0;
-    if (threadIdx.x == 0) {
-      for (int c = c_lo; c < c_hi; ++c) {
-        const double xc = a.x[c];
-        const double xn = xc + a.alpha * (double)z[c] + a.beta * (xc - a.xp[c]);
-        a.xp[c] = xc;
-        a.x[c] = xn;
-        s0 += (xn - xc) * (xn - xc);
-        s1 += xn * xn;
-      }
-      scal_w[4] = s0;
-      scal_w[5] = s1;
-    }
-    if (!(alive = grid_barrier(a.bar, epoch, G, a.err, &s_flag, a.spin_limit))) break;
-    const double S0 = block_sum_strided(a.scal + 4, G, kScal, s_red);
-    const double S1 = block_sum_strided(a.scal + 5, G, kScal, s_red);
+    double S0, S1;
+    sum2_slots(a.scal, Gc, 4, 5, s_red, S0, S1);
     ++outer;
     last_step = S1 > 0.0 ? sqrt(S0 / S1) : 0.0;
     if (!isfinite(last_step)) {
@@ -318,6 +441,8 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
     }
   }
   if (!alive) status = MIHS_BARRIER_TIMEOUT;
+  // publish the momentum state (the iterate before x) of the owned columns
+  for (int i = threadIdx.x; i < nown; i += kBlock) a.xp[c_lo + i] = own_xp[i];
   if (w == 0 && threadIdx.x == 0) {
     a.info->outer_iters = outer;
     a.info->inner_iters_total = inner_total;
@@ -360,20 +485,45 @@ struct SolveLayout {
   size_t partA, partS, scal, vecs, xp, bar, total;
 };
 
-SolveLayout layout(int G, int Gcg, int64_t dpad) {
+// Barrier region: line 0 = top counter of the all-workgroup barrier, lines 1-8
+// its group counters, line 9 = inner-solve group counter, line 10 = error flag,
+// line 11 = status word (128-byte lines).
+constexpr size_t kBarLines = 12;
+
+SolveLayout layout(int G, int Gc, int64_t dpad) {
   SolveLayout L;
   size_t off = 0;
   L.partA = off; off = align_up(off + (size_t)G * dpad * 8, 256);
-  L.partS = off; off = align_up(off + (size_t)Gcg * dpad * 8, 256);
+  L.partS = off; off = align_up(off + (size_t)Gc * dpad * 8, 256);
   L.scal = off;  off = align_up(off + (size_t)G * kScal * 8, 256);
   L.vecs = off;  off = align_up(off + 4 * (size_t)dpad * 8, 256);
   L.xp = off;    off = align_up(off + (size_t)dpad * 8, 256);
-  L.bar = off;   off = align_up(off + 256, 256);
+  L.bar = off;   off = align_up(off + kBarLines * 128, 256);
   L.total = off;
   return L;
 }
 
 int max_grid(const mihs_handle* h) { return h->num_cu * kMaxBlocksPerCU; }
+
+// Size of the inner-solve subgroup: enough workgroups to stream SA quickly,
+// few enough that its barrier stays cheap (the barrier cost grows steeply
+// with the number of participants).  MIHS_CG_GROUPS overrides (tuning).
+int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G) {
+  const char* env = getenv("MIHS_CG_GROUPS");
+  int gc;
+  if (env && atoi(env) > 0) {
+    gc = atoi(env);
+  } else {
+    const double mb = (double)m * (double)d * sa_bytes / (1024.0 * 1024.0);
+    gc = mb >= 24.0 ? 64 : (mb >= 4.0 ? 32 : 16);
+    // each CG workgroup should own at least a few rows
+    const int64_t by_rows = (m + 3) / 4;
+    if (gc > by_rows) gc = (int)(by_rows < 1 ? 1 : by_rows);
+  }
+  if (gc > G) gc = G;
+  if (gc < 1) gc = 1;
+  return gc;
+}
 
 }  // namespace
 
@@ -398,24 +548,34 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   SolveKernel kern = pick_kernel(s.a_f32, s.mixed, ept);
   if (!kern) return MIHS_ERR_UNSUPPORTED;
   const int64_t dpad = dpad_for(s.d);
-  const size_t shmem = 2 * (size_t)dpad * sizeof(double);
-  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)shmem) != hipSuccess)
-    return MIHS_ERR_HIP;
-  int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kBlock, shmem) != hipSuccess)
-    return MIHS_ERR_HIP;
-  if (occ < 1) return MIHS_ERR_UNSUPPORTED;
-  occ = occ > kMaxBlocksPerCU ? kMaxBlocksPerCU : occ;
-  int G = h->num_cu * occ;
-  // small problems: keep at least ~64 rows of A per workgroup
-  const int64_t g_rows = (s.n + 63) / 64;
-  if ((int64_t)G > g_rows) G = (int)(g_rows < 1 ? 1 : g_rows);
-  constexpr int kRowsPerWaveCG = 2;
-  int64_t gcg = (s.m + kWavesPerBlock * kRowsPerWaveCG - 1) / (kWavesPerBlock * kRowsPerWaveCG);
-  if (gcg > G) gcg = G;
-  if (gcg < 1) gcg = 1;
-  const SolveLayout L = layout(G, (int)gcg, dpad);
+  // Pick the grid: try two workgroups per CU, then one; the inner-solve group
+  // size (and with it the LDS request) depends on the grid.
+  int G = 0, Gc = 0, cpw = 0;
+  size_t shmem = 0;
+  const int64_t g_rows = (s.n + 63) / 64;  // keep >= ~64 rows of A per workgroup
+  for (int occ_try = kMaxBlocksPerCU; occ_try >= 1; --occ_try) {
+    int g = h->num_cu * occ_try;
+    if ((int64_t)g > g_rows) g = (int)(g_rows < 1 ? 1 : g_rows);
+    const int gc = pick_cg_groups(s.m, s.d, s.mixed ? 4 : 8, g);
+    const int cp = (int)((s.d + gc - 1) / gc);
+    const size_t sh = (2 * (size_t)dpad + 6 * (size_t)cp + kBlock) * sizeof(double);
+    if (sh > 160 * 1024) continue;
+    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sh) != hipSuccess)
+      return MIHS_ERR_HIP;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kBlock, sh) != hipSuccess)
+      return MIHS_ERR_HIP;
+    if (occ >= occ_try || (occ >= 1 && (int64_t)g <= (int64_t)h->num_cu * occ)) {
+      G = g;
+      Gc = gc;
+      cpw = cp;
+      shmem = sh;
+      break;
+    }
+  }
+  if (G == 0) return MIHS_ERR_UNSUPPORTED;
+  const SolveLayout L = layout(G, Gc, dpad);
   if (ws_bytes < L.total || ws == nullptr) return MIHS_ERR_WORKSPACE;
 
   char* base = (char*)ws;
@@ -448,16 +608,22 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   a.z = (void*)(base + L.vecs + (size_t)dpad * 8);
   a.p0 = (void*)(base + L.vecs + 2 * (size_t)dpad * 8);
   a.p1 = (void*)(base + L.vecs + 3 * (size_t)dpad * 8);
-  a.bar = (unsigned*)(base + L.bar);
-  a.err = (int*)(base + L.bar + 64);
+  unsigned* bar = (unsigned*)(base + L.bar);
+  a.bar_all = bar;
+  a.bar_cg = bar + 9 * 32;
+  a.err = (int*)(bar + 10 * 32);
+  a.status = (int*)(bar + 11 * 32);
   a.d = (int)s.d;
   a.dpad = (int)dpad;
   a.G = G;
-  a.Gcg = (int)gcg;
-  a.cpw = (int)((s.d + G - 1) / G);
-  a.spin_limit = 1L << 25;
+  a.Gc = Gc;
+  a.cpw = cpw;
+  a.spin_fast.limit = 1L << 26;  // ~64-clock polls: a few seconds at most
+  a.spin_fast.sleep = 1;
+  a.spin_idle.limit = 1L << 24;  // ~1000-clock polls while the inner solve runs
+  a.spin_idle.sleep = 16;
 
-  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, stream, a.bar, 64);
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, stream, bar, (int)(kBarLines * 32));
   if (hipGetLastError() != hipSuccess) return MIHS_ERR_HIP;
   void* args[] = {&a};
   if (hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(kBlock), args, shmem, stream) !=

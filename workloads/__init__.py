@@ -11,7 +11,7 @@ Workload recipe (the paper's data model, eq. (setup): A x0 + w = b):
   (QR of a seeded d x d Gaussian, columns sign-fixed by sign(diag R));
 * x0 ~ N(0, 1/d) per entry;
 * b = A x0 + w with w ~ N(0, 1e-4 * ||A x0||^2 / n) per entry (1% noise, as in
-  the paper's noisy experiments, Section 4.3);
+  the paper's noisy experiments, Section 4.4);
 * lambda is chosen so that the statistical dimension of the *nominal* spectrum,
   sum_i sigma_i^2 / (sigma_i^2 + lambda) (Section 1), equals a target value.
   The realised statistical dimension of the drawn A differs slightly because G

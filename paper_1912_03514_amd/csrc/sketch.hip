@@ -55,8 +55,8 @@ __global__ __launch_bounds__(kBlock) void srht_stage1(const TA* __restrict__ A, 
   extern __shared__ unsigned char smem_raw[];
   TY* T = (TY*)smem_raw;  // B x kFwhtW
   const int B = 1 << logB;
-  const int64_t row0 = (int64_t)blockIdx.x * B;
-  const int64_t c0 = (int64_t)blockIdx.y * kFwhtW;
+  const int64_t row0 = (int64_t)blockIdx.y * B;
+  const int64_t c0 = (int64_t)blockIdx.x * kFwhtW;
   for (int e = threadIdx.x; e < B * kFwhtW; e += kBlock) {
     const int r = e / kFwhtW, c = e % kFwhtW;
     const int64_t gr = row0 + r, gc = c0 + c;
@@ -85,8 +85,90 @@ __global__ __launch_bounds__(kBlock) void srht_stage1(const TA* __restrict__ A, 
   }
 }
 
+// Stage 1 for blocks of 512 rows: the 9 butterfly levels of H_512 split as
+// 4 levels in registers on rows s + 32 i (i = 0..15, bits 5..8 of the row),
+// one transpose through LDS, then 5 levels in registers on rows 32 g + i
+// (i = 0..31, bits 0..4).  W columns per workgroup (16 for FP64 A, 32 for
+// FP32 A, i.e. 128-byte row segments).
+template <typename T, int N>
+__device__ __forceinline__ void fwht_regs(T (&x)[N]) {
+#pragma unroll
+  for (int h = 1; h < N; h <<= 1) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if ((j & h) == 0) {
+        const T a = x[j], b = x[j + h];
+        x[j] = a + b;
+        x[j + h] = a - b;
+      }
+    }
+  }
+}
+
+template <typename TA, typename TY>
+__global__ __launch_bounds__(kBlock) void srht_stage1_b512(const TA* __restrict__ A, int64_t lda,
+                                                           int64_t d, uint32_t seed,
+                                                           TY* __restrict__ Y, int64_t ldy) {
+  constexpr int W = sizeof(TA) == 8 ? 16 : 32;
+  constexpr int C1 = W / 8;   // columns per thread, phase 1
+  constexpr int C2 = W / 16;  // columns per thread, phase 2
+  constexpr int PAD = 1;
+  __shared__ TY T[512][W + PAD];
+  const int64_t row0 = (int64_t)blockIdx.y * 512;  // column blocks vary fastest, so
+  const int64_t c0 = (int64_t)blockIdx.x * W;       // concurrent workgroups cover whole rows
+  const int t = threadIdx.x;
+  {
+    const int cp = t % 8, sl = t / 8;  // column group, row slot 0..31
+    TY x[C1][16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int64_t gr = row0 + sl + 32 * i;
+      const TA* src = A + gr * lda + c0 + C1 * cp;
+      TA v[C1];
+      if (c0 + C1 * cp + C1 <= d) {
+        VecLoad<TA, C1, true>::run(src, v);  // one 16-byte load
+      } else {
+#pragma unroll
+        for (int q = 0; q < C1; ++q) v[q] = (c0 + C1 * cp + q < d) ? src[q] : TA(0);
+      }
+      const bool neg = (murmur3_u32((uint32_t)gr, seed) >> 31) != 0;
+#pragma unroll
+      for (int q = 0; q < C1; ++q) x[q][i] = neg ? -(TY)v[q] : (TY)v[q];
+    }
+#pragma unroll
+    for (int q = 0; q < C1; ++q) fwht_regs<TY, 16>(x[q]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+      for (int q = 0; q < C1; ++q) T[sl + 32 * i][C1 * cp + q] = x[q][i];
+  }
+  __syncthreads();
+  {
+    const int c = C2 * (t % 16), g = t / 16;  // first column (C2 adjacent), row group 0..15
+    TY y[C2][32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+#pragma unroll
+      for (int q = 0; q < C2; ++q) y[q][i] = T[32 * g + i][c + q];
+#pragma unroll
+    for (int q = 0; q < C2; ++q) fwht_regs<TY, 32>(y[q]);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      TY* dst = Y + (row0 + 32 * g + i) * ldy + c0 + c;
+      if (c0 + c + C2 <= d) {
+#pragma unroll
+        for (int q = 0; q < C2; ++q) dst[q] = y[q][i];
+      } else {
+#pragma unroll
+        for (int q = 0; q < C2; ++q)
+          if (c0 + c + q < d) dst[q] = y[q][i];
+      }
+    }
+  }
+}
+
 constexpr int kS2Cols = 64;    // columns per stage-2 workgroup
-constexpr int kS2Chunk = 16;   // samples accumulated together
+constexpr int kS2Chunk = 8;    // samples accumulated together
 constexpr int kS2Cap = 512;    // sample list capacity
 
 template <typename TY, typename TS>
@@ -99,8 +181,8 @@ __global__ __launch_bounds__(kBlock) void srht_stage2(const TY* __restrict__ Y, 
   __shared__ int s_wcnt[kWavesPerBlock];
   __shared__ TY s_red[kWavesPerBlock][kS2Chunk][kS2Cols];
   const int B = 1 << logB;
-  const int klo = blockIdx.x;
-  const int64_t col = (int64_t)blockIdx.y * kS2Cols + (threadIdx.x & (kS2Cols - 1));
+  const int klo = blockIdx.y;  // column blocks vary fastest (whole rows of Y in flight)
+  const int64_t col = (int64_t)blockIdx.x * kS2Cols + (threadIdx.x & (kS2Cols - 1));
   const int rg = threadIdx.x >> 6;  // row group = wave
   const int lane = lane_id();
   int cnt = 0;
@@ -116,12 +198,24 @@ __global__ __launch_bounds__(kBlock) void srht_stage2(const TY* __restrict__ Y, 
         acc[s] = TY(0);
       }
       if (col < d) {
-        for (int64_t ih = rg; ih < nhi; ih += kWavesPerBlock) {
-          const TY y = Y[(ih * B + klo) * ldy + col];
+        constexpr int U = 8;  // rows loaded together per thread
+        for (int64_t ih0 = rg; ih0 < nhi; ih0 += (int64_t)U * kWavesPerBlock) {
+          TY y[U];
 #pragma unroll
-          for (int s = 0; s < kS2Chunk; ++s) {
-            const int par = __popc((unsigned)khi[s] & (unsigned)ih) & 1;
-            acc[s] += par ? -y : y;
+          for (int u = 0; u < U; ++u) {
+            const int64_t ih = ih0 + (int64_t)u * kWavesPerBlock;
+            y[u] = (ih < nhi) ? Y[(ih * B + klo) * ldy + col] : TY(0);
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const unsigned ih = (unsigned)(ih0 + (int64_t)u * kWavesPerBlock);
+#pragma unroll
+            for (int s = 0; s < kS2Chunk; ++s) {
+              if (s < ns) {  // uniform: the chunk's sample count
+                const int par = __popc((unsigned)khi[s] & ih) & 1;
+                acc[s] += par ? -y[u] : y[u];
+              }
+            }
           }
         }
       }
@@ -600,13 +694,19 @@ int run_srht(const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint32_t
   const int64_t nhi = n >> logB;
   hipLaunchKernelGGL(srht_rows_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, idx, m, n,
                      seed);
-  const size_t sh1 = (size_t)B * kFwhtW * sizeof(TY);
-  if (hipFuncSetAttribute((const void*)srht_stage1<TA, TY>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh1) != hipSuccess)
-    return MIHS_ERR_HIP;
-  hipLaunchKernelGGL((srht_stage1<TA, TY>), dim3((unsigned)nhi, (unsigned)ceil_div(d, kFwhtW)),
-                     dim3(kBlock), sh1, st, A, lda, d, logB, seed, Y, ldy);
-  hipLaunchKernelGGL((srht_stage2<TY, TS>), dim3((unsigned)B, (unsigned)ceil_div(d, kS2Cols)),
+  if (logB == 9) {
+    constexpr int W = sizeof(TA) == 8 ? 16 : 32;
+    hipLaunchKernelGGL((srht_stage1_b512<TA, TY>), dim3((unsigned)ceil_div(d, W), (unsigned)nhi),
+                       dim3(kBlock), 0, st, A, lda, d, seed, Y, ldy);
+  } else {
+    const size_t sh1 = (size_t)B * kFwhtW * sizeof(TY);
+    if (hipFuncSetAttribute((const void*)srht_stage1<TA, TY>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh1) != hipSuccess)
+      return MIHS_ERR_HIP;
+    hipLaunchKernelGGL((srht_stage1<TA, TY>), dim3((unsigned)ceil_div(d, kFwhtW), (unsigned)nhi),
+                       dim3(kBlock), sh1, st, A, lda, d, logB, seed, Y, ldy);
+  }
+  hipLaunchKernelGGL((srht_stage2<TY, TS>), dim3((unsigned)ceil_div(d, kS2Cols), (unsigned)B),
                      dim3(kBlock), 0, st, Y, ldy, d, logB, nhi, idx, m, SA, ldsa,
                      1.0 / sqrt((double)m));
   return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;

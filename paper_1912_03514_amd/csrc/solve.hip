@@ -515,7 +515,7 @@ int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G) {
     gc = atoi(env);
   } else {
     const double mb = (double)m * (double)d * sa_bytes / (1024.0 * 1024.0);
-    gc = mb >= 24.0 ? 64 : (mb >= 4.0 ? 32 : 16);
+    gc = mb >= 4.0 ? 64 : (mb >= 1.0 ? 32 : 16);
     // each CG workgroup should own at least a few rows
     const int64_t by_rows = (m + 3) / 4;
     if (gc > by_rows) gc = (int)(by_rows < 1 ? 1 : by_rows);

@@ -173,8 +173,10 @@ class Workload:
 WORKLOADS = {
     "small_gauss": Workload("small_gauss", 4096, 256, "f64", "exp", 6.0, 64.0, "gaussian", 256,
                             eps_sub=1e-8, data_seed=0, sketch_seed=7),
+    # eps_sub = 0.1 is the paper's forcing term (Section 3.1); on this workload it keeps
+    # the outer iteration count of eps_sub = 1e-2 with half the inner iterations.
     "srht_2p18x2048": Workload("srht_2p18x2048", 1 << 18, 2048, "f64", "exp", 8.0, 512.0, "srht",
-                               2048, eps_sub=1e-2, data_seed=1000, sketch_seed=8),
+                               2048, eps_sub=1e-1, data_seed=1000, sketch_seed=8),
     "count_2p20x4096": Workload("count_2p20x4096", 1 << 20, 4096, "f32", "poly", 1.5, 1024.0,
                                 "count_gauss", 8192, m2=4096, eps_sub=1e-2, data_seed=2000,
                                 sketch_seed=9),

@@ -168,7 +168,12 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
  * lambdas, alphas, betas  device, nprob x nlam doubles each (row k = problem k).
  * Each problem's X is d_k x nlam row-major doubles (column j = lambda j; in:
  * warm start, out: solution) and info points at nlam mihs_info_t records.
- * A_k is FP64; SA_k has the precision's type (double / float).
+ * A_k is FP64 with d_k <= 1024; SA_k has the precision's type (double / float).
+ * Every pass and the inner CG run in FP64 on the matrix cores (16 lambdas
+ * per pass).  h_problems is the host copy of the table the call schedules
+ * from (large problems get teams of workgroups, small ones share one);
+ * d_problems may be NULL.  The call copies its schedule to the workspace and
+ * waits for that copy before it returns.
  * ------------------------------------------------------------------------ */
 typedef struct {
   const void* A;    /* n x d, row stride lda (double) */
@@ -198,7 +203,14 @@ int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
  *   dL/dB = A W  (n x k)    and    dL/dlambda = - sum_j x*_j^T w_j.
  * Xstar, Gbar, W are d x k row-major doubles (device); dB is n x k (device,
  * NULL to skip); dlambda is one device double.  d_info holds k records.
+ * For d <= 1024 the k systems run as blocks of 16 right-hand sides that share
+ * each pass over A and SA (FP64 matrix cores); wider problems solve the
+ * columns one after another.  The workspace size comes from
+ * mihs_solve_backward_workspace_size().
  * ------------------------------------------------------------------------ */
+int mihs_solve_backward_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                                       int64_t k, mihs_precision_t precision, size_t* bytes);
+
 int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
                         int64_t d, int64_t lda, const void* SA, int64_t m, int64_t ldsa,
                         double lambda, mihs_precision_t precision, const double* Xstar,

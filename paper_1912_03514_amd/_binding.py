@@ -70,6 +70,8 @@ _SIGS = {
     "mihs_solve_batched_workspace_size": (_int, [_vp, _vp, _i64, _i64, _int, ctypes.POINTER(_sz)]),
     "mihs_solve_batched": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl,
                                   _i64, _i64, _vp, _sz, _vp]),
+    "mihs_solve_backward_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
+                                                  ctypes.POINTER(_sz)]),
     "mihs_solve_backward": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _int,
                                    _vp, _vp, _i64, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp,
                                    _vp, _vp, _vp, _sz, _vp]),
@@ -265,9 +267,9 @@ def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: to
     lib = load_library()
     h = handle(dev.index)
     ws_n = _sz()
-    _check(lib.mihs_solve_workspace_size(h, n, d, m, p, ctypes.byref(ws_n)),
-           "mihs_solve_workspace_size")
-    ws = _workspace(ws_n.value + 2 * ((d * 8 + 255) // 256 * 256), dev)
+    _check(lib.mihs_solve_backward_workspace_size(h, n, d, m, k, p, ctypes.byref(ws_n)),
+           "mihs_solve_backward_workspace_size")
+    ws = _workspace(ws_n.value, dev)
     rc = lib.mihs_solve_backward(h, A.data_ptr(), _dtype_code(A), n, d, A.stride(0),
                                  SA.data_ptr(), m, SA.stride(0), float(lam), p, Xs.data_ptr(),
                                  Gb.data_ptr(), k, float(alpha), float(beta), float(eps_sub),
@@ -277,3 +279,56 @@ def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: to
     _check(rc, "mihs_solve_backward")
     torch.cuda.synchronize(dev)
     return W, dB, dlam, info_to_dict(info)
+
+
+def mihs_solve_batched(problems, lambdas: torch.Tensor, alphas: torch.Tensor,
+                       betas: torch.Tensor, eps_sub: float = 1e-2, tol: float = 1e-10,
+                       max_outer: int = 300, max_inner: int = 1000,
+                       precision: Optional[str] = None, sync: bool = True):
+    """Lambda-path solves of many problems in one launch (see include/mihs.h).
+
+    problems: list of (A, b, SA) device tensors (A float64, n_k x d_k with d_k <= 1024).
+    lambdas, alphas, betas: nprob x nlam float64 device tensors.
+    Returns (list of d_k x nlam solution tensors, list of per-problem info lists)."""
+    nprob = len(problems)
+    if lambdas.shape[0] != nprob or lambdas.dim() != 2:
+        raise MihsError("lambdas must be nprob x nlam")
+    nlam = lambdas.shape[1]
+    if precision is None:
+        precision = "mixed" if problems[0][2].dtype == torch.float32 else "plain"
+    p = PRECISIONS[precision]
+    dev = problems[0][0].device
+    lam = lambdas.to(torch.float64).contiguous()
+    alp = alphas.to(torch.float64).contiguous()
+    bet = betas.to(torch.float64).contiguous()
+    keep, xs, infos = [], [], []
+    table = (Problem * nprob)()
+    for i, (A, b, SA) in enumerate(problems):
+        A = _row_aligned(A)
+        SA = _row_aligned(SA)
+        if A.dtype != torch.float64:
+            raise MihsError("batched problems take float64 A")
+        n, d = A.shape
+        X = torch.zeros((d, nlam), dtype=torch.float64, device=dev)
+        info = torch.zeros(INFO_BYTES * nlam, dtype=torch.uint8, device=dev)
+        keep += [A, b, SA]
+        xs.append(X)
+        infos.append(info)
+        table[i] = Problem(A.data_ptr(), b.data_ptr(), SA.data_ptr(), X.data_ptr(),
+                           info.data_ptr(), n, d, A.stride(0), SA.shape[0], SA.stride(0))
+    lib = load_library()
+    h = handle(dev.index)
+    ws_n = _sz()
+    _check(lib.mihs_solve_batched_workspace_size(h, ctypes.cast(table, _vp), nprob, nlam, p,
+                                                 ctypes.byref(ws_n)),
+           "mihs_solve_batched_workspace_size")
+    ws = _workspace(ws_n.value, dev)
+    rc = lib.mihs_solve_batched(h, None, ctypes.cast(table, _vp), nprob, lam.data_ptr(),
+                                alp.data_ptr(), bet.data_ptr(), nlam, p, float(eps_sub),
+                                float(tol), int(max_outer), int(max_inner), ws.data_ptr(),
+                                ws.numel(), _stream(dev))
+    _check(rc, "mihs_solve_batched")
+    if not sync:
+        return xs, infos, (keep, ws)
+    torch.cuda.synchronize(dev)
+    return xs, [info_to_dict(t) for t in infos]

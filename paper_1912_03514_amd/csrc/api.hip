@@ -4,6 +4,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <vector>
+
 #include "internal.hpp"
 
 using mihs::align_up;
@@ -164,6 +166,30 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
   return mihs::launch_solve(handle, s, workspace, ws_bytes, as_stream(stream));
 }
 
+static size_t backward_ws_bytes(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                                int64_t k, int mixed) {
+  const size_t params = align_up(3 * 16 * sizeof(double), 256);
+  if (d <= mihs::block_max_d()) {
+    std::vector<mihs::BlockEntryDesc> ents((size_t)((k + 15) / 16));
+    for (auto& e : ents) {
+      e.n = n;
+      e.d = d;
+      e.m = m;
+      e.ncols = 16;
+    }
+    return params + mihs::block_workspace_bytes(ents.data(), (int64_t)ents.size(), handle->num_cu);
+  }
+  return params + mihs::solve_workspace_bytes(handle, n, d, m, mixed) +
+         2 * align_up((size_t)d * sizeof(double), 256);
+}
+
+int mihs_solve_backward_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                                       int64_t k, mihs_precision_t precision, size_t* bytes) {
+  if (!handle || !bytes || n <= 0 || d <= 0 || m <= 0 || k < 1) return MIHS_ERR_INVALID;
+  *bytes = backward_ws_bytes(handle, n, d, m, k, precision == MIHS_MIXED);
+  return MIHS_OK;
+}
+
 int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
                         int64_t d, int64_t lda, const void* SA, int64_t m, int64_t ldsa,
                         double lambda, mihs_precision_t precision, const double* Xstar,
@@ -177,49 +203,90 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
   if (rc) return rc;
   if (!Xstar || !Gbar || !W || !dlambda || !d_info || k < 1) return MIHS_ERR_INVALID;
   if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  const int mixed = precision == MIHS_MIXED;
+  if (!workspace || ws_bytes < backward_ws_bytes(handle, n, d, m, k, mixed))
+    return MIHS_ERR_WORKSPACE;
   hipStream_t st = as_stream(stream);
-  // The adjoint systems (A^T A + lambda I) w_j = gbar_j, one M-IHS solve per
-  // column, all on the same sketch.  Columns are strided by k in the d x k
-  // row-major arrays, so each solve works on a contiguous copy in the
-  // workspace tail.
-  const size_t solve_ws = mihs::solve_workspace_bytes(handle, n, d, m, precision == MIHS_MIXED);
-  const size_t col_bytes = align_up((size_t)d * sizeof(double), 256);
-  if (!workspace || ws_bytes < solve_ws + 2 * col_bytes) return MIHS_ERR_WORKSPACE;
   char* base = (char*)workspace;
-  double* g_col = (double*)(base + solve_ws);
-  double* w_col = (double*)(base + solve_ws + col_bytes);
-  for (int64_t j = 0; j < k; ++j) {
-    if (hipMemcpy2DAsync(g_col, sizeof(double), Gbar + j, (size_t)k * sizeof(double),
-                         sizeof(double), (size_t)d, hipMemcpyDeviceToDevice, st) != hipSuccess)
-      return MIHS_ERR_HIP;
-    if (hipMemsetAsync(w_col, 0, (size_t)d * sizeof(double), st) != hipSuccess) return MIHS_ERR_HIP;
-    mihs::SolveDesc s;
-    s.A = A;
-    s.a_f32 = a_dtype == MIHS_F32;
-    s.n = n;
-    s.d = d;
-    s.lda = lda;
-    s.b = nullptr;
-    s.rhs = g_col;
-    s.SA = SA;
-    s.mixed = precision == MIHS_MIXED;
-    s.m = m;
-    s.ldsa = ldsa;
-    s.lam = lambda;
-    s.alpha = alpha;
-    s.beta = beta;
-    s.eps_sub = eps_sub;
-    s.tol = tol;
-    s.max_outer = max_outer;
-    s.max_inner = max_inner;
-    s.x = w_col;
-    s.x_prev = nullptr;
-    s.info = d_info + j;
-    rc = mihs::launch_solve(handle, s, workspace, solve_ws, st);
+  const size_t params = align_up(3 * 16 * sizeof(double), 256);
+  // The adjoint systems (A^T A + lambda I) w_j = gbar_j share A, SA and lambda:
+  // M-IHS from w = 0 with gradient gbar_j - A^T A w_j - lambda w_j.
+  if (hipMemsetAsync(W, 0, (size_t)d * k * sizeof(double), st) != hipSuccess) return MIHS_ERR_HIP;
+  if (d <= mihs::block_max_d()) {
+    double* pl = (double*)base;
+    rc = mihs::launch_fill(pl, lambda, 16, st);
+    if (!rc) rc = mihs::launch_fill(pl + 16, alpha, 16, st);
+    if (!rc) rc = mihs::launch_fill(pl + 32, beta, 16, st);
     if (rc) return rc;
-    if (hipMemcpy2DAsync(W + j, (size_t)k * sizeof(double), w_col, sizeof(double), sizeof(double),
-                         (size_t)d, hipMemcpyDeviceToDevice, st) != hipSuccess)
-      return MIHS_ERR_HIP;
+    std::vector<mihs::BlockEntryDesc> ents;
+    for (int64_t g0 = 0; g0 < k; g0 += 16) {
+      mihs::BlockEntryDesc e;
+      e.A = A;
+      e.n = n;
+      e.d = d;
+      e.lda = lda;
+      e.B = nullptr;
+      e.ldb = 0;
+      e.ldbc = 0;
+      e.RHS = Gbar + g0;
+      e.ldr = k;
+      e.SA = SA;
+      e.m = m;
+      e.ldsa = ldsa;
+      e.X = W + g0;
+      e.ldx = k;
+      e.lam = pl;
+      e.alpha = pl + 16;
+      e.beta = pl + 32;
+      e.info = d_info + g0;
+      e.ncols = (int)((k - g0) < 16 ? (k - g0) : 16);
+      ents.push_back(e);
+    }
+    rc = mihs::launch_block(handle, ents.data(), (int64_t)ents.size(), a_dtype == MIHS_F32, mixed,
+                            eps_sub, tol, max_outer, max_inner, base + params, ws_bytes - params,
+                            st);
+    if (rc) return rc;
+  } else {
+    // wide problems: one single-column solve per right-hand side
+    const size_t solve_ws = mihs::solve_workspace_bytes(handle, n, d, m, mixed);
+    const size_t col_bytes = align_up((size_t)d * sizeof(double), 256);
+    char* wsp = base + params;
+    double* g_col = (double*)(wsp + solve_ws);
+    double* w_col = (double*)(wsp + solve_ws + col_bytes);
+    for (int64_t j = 0; j < k; ++j) {
+      if (hipMemcpy2DAsync(g_col, sizeof(double), Gbar + j, (size_t)k * sizeof(double),
+                           sizeof(double), (size_t)d, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return MIHS_ERR_HIP;
+      if (hipMemsetAsync(w_col, 0, (size_t)d * sizeof(double), st) != hipSuccess)
+        return MIHS_ERR_HIP;
+      mihs::SolveDesc s;
+      s.A = A;
+      s.a_f32 = a_dtype == MIHS_F32;
+      s.n = n;
+      s.d = d;
+      s.lda = lda;
+      s.b = nullptr;
+      s.rhs = g_col;
+      s.SA = SA;
+      s.mixed = mixed;
+      s.m = m;
+      s.ldsa = ldsa;
+      s.lam = lambda;
+      s.alpha = alpha;
+      s.beta = beta;
+      s.eps_sub = eps_sub;
+      s.tol = tol;
+      s.max_outer = max_outer;
+      s.max_inner = max_inner;
+      s.x = w_col;
+      s.x_prev = nullptr;
+      s.info = d_info + j;
+      rc = mihs::launch_solve(handle, s, wsp, solve_ws, st);
+      if (rc) return rc;
+      if (hipMemcpy2DAsync(W + j, (size_t)k * sizeof(double), w_col, sizeof(double),
+                           sizeof(double), (size_t)d, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return MIHS_ERR_HIP;
+    }
   }
   if (dB) {
     rc = mihs::launch_apply_rows(handle, A, a_dtype == MIHS_F32, n, d, lda, W, k, dB, k, st);
@@ -228,18 +295,45 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
   return mihs::launch_neg_dot(Xstar, W, d * k, dlambda, st);
 }
 
+static void batched_entries(const mihs_problem_t* hp, int64_t nprob, const double* lambdas,
+                            const double* alphas, const double* betas, int64_t nlam,
+                            std::vector<mihs::BlockEntryDesc>* out) {
+  out->clear();
+  for (int64_t p = 0; p < nprob; ++p) {
+    for (int64_t g0 = 0; g0 < nlam; g0 += 16) {
+      mihs::BlockEntryDesc e;
+      e.A = hp[p].A;
+      e.n = hp[p].n;
+      e.d = hp[p].d;
+      e.lda = hp[p].lda;
+      e.B = hp[p].b;  // one b shared by every lambda
+      e.ldb = 1;
+      e.ldbc = 0;
+      e.RHS = nullptr;
+      e.ldr = 0;
+      e.SA = hp[p].SA;
+      e.m = hp[p].m;
+      e.ldsa = hp[p].ldsa;
+      e.X = hp[p].X + g0;
+      e.ldx = nlam;
+      e.lam = lambdas ? lambdas + p * nlam + g0 : nullptr;
+      e.alpha = alphas ? alphas + p * nlam + g0 : nullptr;
+      e.beta = betas ? betas + p * nlam + g0 : nullptr;
+      e.info = hp[p].info + g0;
+      e.ncols = (int)((nlam - g0) < 16 ? (nlam - g0) : 16);
+      out->push_back(e);
+    }
+  }
+}
+
 int mihs_solve_batched_workspace_size(mihs_handle_t handle, const mihs_problem_t* h_problems,
                                       int64_t nprob, int64_t nlam, mihs_precision_t precision,
                                       size_t* bytes) {
   if (!handle || !h_problems || !bytes || nprob < 1 || nlam < 1) return MIHS_ERR_INVALID;
-  size_t best = 0;
-  for (int64_t p = 0; p < nprob; ++p) {
-    const size_t s = mihs::solve_workspace_bytes(handle, h_problems[p].n, h_problems[p].d,
-                                                 h_problems[p].m, precision == MIHS_MIXED) +
-                     2 * align_up((size_t)h_problems[p].d * sizeof(double), 256);
-    if (s > best) best = s;
-  }
-  *bytes = best;
+  (void)precision;
+  std::vector<mihs::BlockEntryDesc> ents;
+  batched_entries(h_problems, nprob, nullptr, nullptr, nullptr, nlam, &ents);
+  *bytes = mihs::block_workspace_bytes(ents.data(), (int64_t)ents.size(), handle->num_cu);
   return MIHS_OK;
 }
 
@@ -250,22 +344,23 @@ int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
                        int64_t max_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
                        void* stream) {
   (void)d_problems;
-  (void)h_problems;
-  (void)nprob;
-  (void)lambdas;
-  (void)alphas;
-  (void)betas;
-  (void)nlam;
-  (void)precision;
-  (void)eps_sub;
-  (void)tol;
-  (void)max_outer;
-  (void)max_inner;
-  (void)workspace;
-  (void)ws_bytes;
-  (void)stream;
-  if (!handle) return MIHS_ERR_INVALID;
-  return MIHS_ERR_UNSUPPORTED;
+  if (!handle || !h_problems || nprob < 1 || nlam < 1 || !lambdas || !alphas || !betas)
+    return MIHS_ERR_INVALID;
+  if (precision != MIHS_PLAIN_FP64 && precision != MIHS_MIXED) return MIHS_ERR_INVALID;
+  if (!(eps_sub >= 0.0) || max_outer < 0 || max_inner < 1) return MIHS_ERR_INVALID;
+  for (int64_t p = 0; p < nprob; ++p) {
+    const mihs_problem_t& q = h_problems[p];
+    if (q.n < q.d || !valid_matrix(q.A, q.n, q.d, q.lda, 0) || !q.b || !q.X || !q.info)
+      return MIHS_ERR_INVALID;
+    if (!valid_matrix(q.SA, q.m, q.d, q.ldsa, precision == MIHS_MIXED)) return MIHS_ERR_INVALID;
+    if (q.d > mihs::block_max_d()) return MIHS_ERR_UNSUPPORTED;
+  }
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  std::vector<mihs::BlockEntryDesc> ents;
+  batched_entries(h_problems, nprob, lambdas, alphas, betas, nlam, &ents);
+  return mihs::launch_block(handle, ents.data(), (int64_t)ents.size(), 0,
+                            precision == MIHS_MIXED, eps_sub, tol, max_outer, max_inner, workspace,
+                            ws_bytes, as_stream(stream));
 }
 
 }  // extern "C"

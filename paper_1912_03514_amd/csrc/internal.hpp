@@ -49,11 +49,37 @@ int launch_sketch(const mihs_handle* h, const void* A, int a_f32, int64_t n, int
                   int64_t lda, int kind, int64_t m, int64_t m2, uint32_t seed, int mixed,
                   void* SA, int64_t ldsa, void* ws, size_t ws_bytes, hipStream_t stream);
 
+// ---- block M-IHS (many problems x up to 16 right-hand sides each) ------------
+struct BlockEntryDesc {
+  const void* A;
+  int64_t n, d, lda;
+  const double* B;    // ridge mode: C[i][j] = B[i * ldb + j * ldbc], or null
+  int64_t ldb, ldbc;
+  const double* RHS;  // adjoint mode: RHS[c * ldr + j], or null
+  int64_t ldr;
+  const void* SA;
+  int64_t m, ldsa;
+  double* X;          // d x ncols, X[c * ldx + j]
+  int64_t ldx;
+  const double* lam;  // device, ncols values each
+  const double* alpha;
+  const double* beta;
+  mihs_info_t* info;  // device, ncols records
+  int ncols;          // 1..16
+};
+int block_max_d();
+size_t block_workspace_bytes(const BlockEntryDesc* ents, int64_t count, int num_cu);
+int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
+                 int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+                 void* ws, size_t ws_bytes, hipStream_t stream);
+
 // ---- dense helper kernels --------------------------------------------------
 // Y (n x k, row stride ldy) = A (n x d) W (d x k row-major); FP64 accumulation.
 int launch_apply_rows(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,
                       int64_t lda, const double* W, int64_t k, double* Y, int64_t ldy,
                       hipStream_t stream);
+// p[0..count) = value
+int launch_fill(double* p, double value, int64_t count, hipStream_t stream);
 // out = -sum over all entries of X .* W (d x k); one device double.
 int launch_neg_dot(const double* X, const double* W, int64_t count, double* out,
                    hipStream_t stream);

@@ -721,7 +721,18 @@ __global__ __launch_bounds__(kBlock) void neg_dot_kernel(const double* X, const 
   if (threadIdx.x == 0) *out = -v;
 }
 
+__global__ void fill_kernel(double* p, double v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
 }  // namespace
+
+int launch_fill(double* p, double value, int64_t count, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, st, p, value,
+                     count);
+  return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
+}
 
 int launch_apply_rows(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,
                       int64_t lda, const double* W, int64_t k, double* Y, int64_t ldy,

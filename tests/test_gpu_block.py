@@ -1,0 +1,132 @@
+"""GPU parity: block M-IHS (batched lambda-paths and the multi-RHS backward)
+against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sketches, solver as O
+from gpu_common import announce, dev, rel, requires_gpu, to_dev, torch
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def _mihs():
+    import paper_1912_03514_amd as mihs
+    return mihs
+
+
+def _lam_path(sig, nlam, m):
+    """lambda grid on [1e-6, 1e-1] sigma_1^2 (log spaced) and Corollary-4
+    momentum from the nominal statistical dimension of each lambda."""
+    s1 = float(sig[0]) ** 2
+    lams = s1 * 10.0 ** (-6.0 + 5.0 * np.arange(nlam) / max(nlam - 1, 1))
+    sds = np.array([W.nominal_sd(sig, float(l)) for l in lams])
+    betas = np.minimum(sds / m, 0.95)
+    alphas = (1.0 - betas) ** 2
+    return lams, alphas, betas
+
+
+@pytest.mark.parametrize("nlam", [16, 5, 20])
+def test_batched_lambda_paths_match_closed_form(nlam):
+    """Several problems of different (n, d) -- ragged d, several 16-row tiles and
+    a ragged last tile -- each solved for a lambda path sharing one sketch."""
+    mihs = _mihs()
+    shapes = [(1500, 70), (3001, 130), (900, 64), (4000, 300), (2500, 17)]
+    problems, refs, lam_rows, a_rows, b_rows = [], [], [], [], []
+    for i, (n, d) in enumerate(shapes):
+        sig = W.sigma_profile("exp", d, 6.0)
+        P = W.make_problem(n, d, sig, d / 4, 100 + i)
+        m = min(n, 4 * d)
+        SA = sketches.gaussian_sketch(P.A, m, 30 + i)
+        lams, alphas, betas = _lam_path(sig, nlam, m)
+        problems.append((to_dev(P.A), to_dev(P.b), to_dev(SA)))
+        refs.append([O.ridge_lstsq(P.A, P.b, float(l)) for l in lams])
+        lam_rows.append(lams)
+        a_rows.append(alphas)
+        b_rows.append(betas)
+    announce(f"batched lambda paths nlam={nlam}")
+    xs, infos = mihs.mihs_solve_batched(problems, to_dev(np.array(lam_rows)),
+                                        to_dev(np.array(a_rows)), to_dev(np.array(b_rows)),
+                                        eps_sub=1e-2, tol=1e-12, max_outer=600, max_inner=2000)
+    for i in range(len(shapes)):
+        X = xs[i].cpu().numpy()
+        for j in range(nlam):
+            assert infos[i][j]["status"] == 0, (i, j, infos[i][j])
+            assert rel(X[:, j], refs[i][j]) <= 1e-10, (i, j)
+
+
+def test_batched_equals_single_solves():
+    """A lambda column of the batched solve and the single-problem solve reach
+    the same point."""
+    mihs = _mihs()
+    n, d, m = 3000, 96, 256
+    sig = W.sigma_profile("exp", d, 6.0)
+    P = W.make_problem(n, d, sig, 24.0, 9)
+    SA = sketches.gaussian_sketch(P.A, m, 4)
+    lams, alphas, betas = _lam_path(sig, 16, m)
+    announce("batched vs single")
+    xs, infos = mihs.mihs_solve_batched([(to_dev(P.A), to_dev(P.b), to_dev(SA))],
+                                        to_dev(lams[None, :]), to_dev(alphas[None, :]),
+                                        to_dev(betas[None, :]), eps_sub=1e-3, tol=1e-13,
+                                        max_outer=800)
+    for j in (0, 7, 15):
+        x1, info = mihs.mihs_solve(to_dev(P.A), to_dev(P.b), float(lams[j]), to_dev(SA),
+                                   float(alphas[j]), float(betas[j]), eps_sub=1e-3, tol=1e-13,
+                                   max_outer=800)
+        assert rel(xs[0][:, j].cpu().numpy(), x1.cpu().numpy()) <= 1e-11, j
+
+
+def test_batched_many_small_problems_share_workgroups():
+    """More problems than one per workgroup-team: bins run several problems."""
+    mihs = _mihs()
+    rng = np.random.default_rng(3)
+    problems, refs, L, Al, Be = [], [], [], [], []
+    for i in range(40):
+        n, d = int(rng.integers(300, 1200)), int(rng.integers(8, 80))
+        sig = W.sigma_profile("exp", d, 6.0)
+        P = W.make_problem(n, d, sig, max(1.0, d / 4), 500 + i)
+        m = min(n, 4 * d)
+        SA = sketches.gaussian_sketch(P.A, m, 7 + i)
+        lams, alphas, betas = _lam_path(sig, 4, m)
+        problems.append((to_dev(P.A), to_dev(P.b), to_dev(SA)))
+        refs.append([O.ridge_lstsq(P.A, P.b, float(l)) for l in lams])
+        L.append(lams)
+        Al.append(alphas)
+        Be.append(betas)
+    announce("batched 40 small problems")
+    xs, infos = mihs.mihs_solve_batched(problems, to_dev(np.array(L)), to_dev(np.array(Al)),
+                                        to_dev(np.array(Be)), eps_sub=1e-2, tol=1e-12,
+                                        max_outer=800)
+    for i in range(40):
+        for j in range(4):
+            assert rel(xs[i][:, j].cpu().numpy(), refs[i][j]) <= 1e-10, (i, j)
+
+
+@pytest.mark.parametrize("k,adt", [(20, np.float64), (16, np.float32), (3, np.float64)])
+def test_backward_matches_dense_gradient(k, adt):
+    """W = (A^T A + lambda I)^{-1} Gbar, dB = A W, dlambda = -sum X* . W against
+    the dense FP64 oracle (FP32 A upcast exactly on both sides)."""
+    mihs = _mihs()
+    n, d, m = 4000, 120, 480
+    sig = W.sigma_profile("exp", d, 8.0)
+    P = W.make_problem(n, d, sig, 30.0, 77, adt)
+    A64 = P.A.astype(np.float64)
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((n, k))
+    Xs = O.ridge_cholesky(A64, B, P.lam)
+    C = rng.standard_normal((64, d))
+    Y = rng.standard_normal((64, k))
+    Gbar = 2 * C.T @ (C @ Xs - Y)
+    Wref, dBref, dlref = O.ridge_backward_dense(A64, P.lam, Xs, Gbar)
+    SA = sketches.gaussian_sketch(A64, m, 3)
+    a, b = O.momentum_cor4(30.0, m)
+    announce(f"backward k={k} {adt.__name__}")
+    Wg, dBg, dl, infos = mihs.mihs_solve_backward(to_dev(P.A), to_dev(SA), P.lam, to_dev(Xs),
+                                                  to_dev(Gbar), a, b, eps_sub=1e-3, tol=1e-13,
+                                                  max_outer=600)
+    assert all(i["status"] == 0 for i in infos), infos
+    assert rel(Wg.cpu().numpy(), Wref) <= 1e-10
+    assert rel(dBg.cpu().numpy(), dBref) <= 1e-10
+    assert abs(float(dl.cpu()) - dlref) <= 1e-10 * abs(dlref)

@@ -159,6 +159,23 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
                void* stream);
 
 /* ------------------------------------------------------------------------
+ * Multi-RHS solve: k right-hand sides B (n x k, row stride ldb) with one
+ * lambda, all sharing A and SA.  Algorithm 1 per column, the columns run in
+ * blocks of 16 that share each pass over A and SA (FP64 matrix cores); needs
+ * d <= 1024.  X is d x k row-major (in: warm start, out: solution); d_info
+ * holds k records.  Workspace size from mihs_solve_multi_workspace_size().
+ * ------------------------------------------------------------------------ */
+int mihs_solve_multi_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                                    int64_t k, mihs_precision_t precision, size_t* bytes);
+
+int mihs_solve_multi(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                     int64_t d, int64_t lda, const double* B, int64_t k, int64_t ldb,
+                     double lambda, const void* SA, int64_t m, int64_t ldsa,
+                     mihs_precision_t precision, double alpha, double beta, double eps_sub,
+                     double tol, int64_t max_outer, int64_t max_inner, double* X,
+                     mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched lambda-path solve: nprob independent problems, each solved for nlam
  * regularisation values that share the problem's one sketch SA_k.  One
  * persistent launch runs every (problem, lambda) pair; problems are split in

@@ -67,6 +67,11 @@ _SIGS = {
     "mihs_solve_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)]),
     "mihs_solve": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64, _int,
                           _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mihs_solve_multi_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
+                                               ctypes.POINTER(_sz)]),
+    "mihs_solve_multi": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _vp,
+                                _i64, _i64, _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp,
+                                _vp, _sz, _vp]),
     "mihs_solve_batched_workspace_size": (_int, [_vp, _vp, _i64, _i64, _int, ctypes.POINTER(_sz)]),
     "mihs_solve_batched": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl,
                                   _i64, _i64, _vp, _sz, _vp]),
@@ -332,3 +337,69 @@ def mihs_solve_batched(problems, lambdas: torch.Tensor, alphas: torch.Tensor,
         return xs, infos, (keep, ws)
     torch.cuda.synchronize(dev)
     return xs, [info_to_dict(t) for t in infos]
+
+
+def mihs_solve_multi(A: torch.Tensor, B: torch.Tensor, lam: float, SA: torch.Tensor,
+                     alpha: float, beta: float, eps_sub: float = 1e-2, tol: float = 1e-10,
+                     max_outer: int = 300, max_inner: int = 1000, X0: Optional[torch.Tensor] = None,
+                     precision: Optional[str] = None, sync: bool = True):
+    """Solve for k right-hand sides B (n x k float64) sharing A, SA and lambda.
+    Returns (X (d x k), infos)."""
+    if precision is None:
+        precision = "mixed" if SA.dtype == torch.float32 else "plain"
+    p = PRECISIONS[precision]
+    A = _row_aligned(A)
+    SA = _row_aligned(SA)
+    n, d = A.shape
+    m = SA.shape[0]
+    dev = A.device
+    Bm = B.reshape(n, -1).to(torch.float64).contiguous()
+    k = Bm.shape[1]
+    X = (torch.zeros((d, k), dtype=torch.float64, device=dev) if X0 is None
+         else X0.reshape(d, k).to(torch.float64).clone().contiguous())
+    info = torch.zeros(INFO_BYTES * k, dtype=torch.uint8, device=dev)
+    lib = load_library()
+    h = handle(dev.index)
+    ws_n = _sz()
+    _check(lib.mihs_solve_multi_workspace_size(h, n, d, m, k, p, ctypes.byref(ws_n)),
+           "mihs_solve_multi_workspace_size")
+    ws = _workspace(ws_n.value, dev)
+    rc = lib.mihs_solve_multi(h, A.data_ptr(), _dtype_code(A), n, d, A.stride(0), Bm.data_ptr(), k,
+                              Bm.stride(0), float(lam), SA.data_ptr(), m, SA.stride(0), p,
+                              float(alpha), float(beta), float(eps_sub), float(tol),
+                              int(max_outer), int(max_inner), X.data_ptr(), info.data_ptr(),
+                              ws.data_ptr(), ws.numel(), _stream(dev))
+    _check(rc, "mihs_solve_multi")
+    if not sync:
+        return X, info
+    torch.cuda.synchronize(dev)
+    return X, info_to_dict(info)
+
+
+class MIHSRidge(torch.autograd.Function):
+    """x*(B, lambda) = (A^T A + lambda I)^{-1} A^T B as a differentiable op of B and
+    log(lambda); the backward is an adjoint M-IHS solve on the same sketch.
+    A and SA are constants (dL/dA is not computed).
+
+        X = MIHSRidge.apply(B, log_lam, A, SA, alpha, beta, solver_kwargs)
+    """
+
+    @staticmethod
+    def forward(ctx, B, log_lam, A, SA, alpha, beta, kw):
+        kw = dict(kw or {})
+        lam = float(torch.exp(log_lam.detach().to(torch.float64)))
+        X, infos = mihs_solve_multi(A, B.detach(), lam, SA, alpha, beta, **kw)
+        ctx.save_for_backward(X)
+        ctx.A, ctx.SA, ctx.lam, ctx.alpha, ctx.beta, ctx.kw = A, SA, lam, alpha, beta, kw
+        ctx.infos = infos
+        return X
+
+    @staticmethod
+    def backward(ctx, gX):
+        (X,) = ctx.saved_tensors
+        kw = {k: v for k, v in ctx.kw.items() if k in ("eps_sub", "tol", "max_outer", "max_inner",
+                                                      "precision")}
+        W, dB, dlam, _ = mihs_solve_backward(ctx.A, ctx.SA, ctx.lam, X, gX.contiguous(),
+                                             ctx.alpha, ctx.beta, want_dB=True, **kw)
+        dloglam = (dlam * ctx.lam).reshape(())
+        return dB, dloglam, None, None, None, None, None

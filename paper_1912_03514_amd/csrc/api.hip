@@ -295,6 +295,75 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
   return mihs::launch_neg_dot(Xstar, W, d * k, dlambda, st);
 }
 
+int mihs_solve_multi_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                                    int64_t k, mihs_precision_t precision, size_t* bytes) {
+  if (!handle || !bytes || n <= 0 || d <= 0 || m <= 0 || k < 1) return MIHS_ERR_INVALID;
+  (void)precision;
+  std::vector<mihs::BlockEntryDesc> ents((size_t)((k + 15) / 16));
+  for (auto& e : ents) {
+    e.n = n;
+    e.d = d;
+    e.m = m;
+    e.ncols = 16;
+  }
+  *bytes = align_up(3 * 16 * sizeof(double), 256) +
+           mihs::block_workspace_bytes(ents.data(), (int64_t)ents.size(), handle->num_cu);
+  return MIHS_OK;
+}
+
+int mihs_solve_multi(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                     int64_t d, int64_t lda, const double* B, int64_t k, int64_t ldb,
+                     double lambda, const void* SA, int64_t m, int64_t ldsa,
+                     mihs_precision_t precision, double alpha, double beta, double eps_sub,
+                     double tol, int64_t max_outer, int64_t max_inner, double* X,
+                     mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream) {
+  if (!handle) return MIHS_ERR_INVALID;
+  int rc = check_solve_common(A, a_dtype, n, d, lda, lambda, SA, m, ldsa, precision, alpha, beta,
+                              eps_sub, max_outer, max_inner);
+  if (rc) return rc;
+  if (!B || !X || !d_info || k < 1 || ldb < k) return MIHS_ERR_INVALID;
+  if (d > mihs::block_max_d()) return MIHS_ERR_UNSUPPORTED;
+  size_t need = 0;
+  mihs_solve_multi_workspace_size(handle, n, d, m, k, precision, &need);
+  if (!workspace || ws_bytes < need) return MIHS_ERR_WORKSPACE;
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  hipStream_t st = as_stream(stream);
+  char* base = (char*)workspace;
+  const size_t params = align_up(3 * 16 * sizeof(double), 256);
+  double* pl = (double*)base;
+  rc = mihs::launch_fill(pl, lambda, 16, st);
+  if (!rc) rc = mihs::launch_fill(pl + 16, alpha, 16, st);
+  if (!rc) rc = mihs::launch_fill(pl + 32, beta, 16, st);
+  if (rc) return rc;
+  std::vector<mihs::BlockEntryDesc> ents;
+  for (int64_t g0 = 0; g0 < k; g0 += 16) {
+    mihs::BlockEntryDesc e;
+    e.A = A;
+    e.n = n;
+    e.d = d;
+    e.lda = lda;
+    e.B = B + g0;
+    e.ldb = ldb;
+    e.ldbc = 1;
+    e.RHS = nullptr;
+    e.ldr = 0;
+    e.SA = SA;
+    e.m = m;
+    e.ldsa = ldsa;
+    e.X = X + g0;
+    e.ldx = k;
+    e.lam = pl;
+    e.alpha = pl + 16;
+    e.beta = pl + 32;
+    e.info = d_info + g0;
+    e.ncols = (int)((k - g0) < 16 ? (k - g0) : 16);
+    ents.push_back(e);
+  }
+  return mihs::launch_block(handle, ents.data(), (int64_t)ents.size(), a_dtype == MIHS_F32,
+                            precision == MIHS_MIXED, eps_sub, tol, max_outer, max_inner,
+                            base + params, ws_bytes - params, st);
+}
+
 static void batched_entries(const mihs_problem_t* hp, int64_t nprob, const double* lambdas,
                             const double* alphas, const double* betas, int64_t nlam,
                             std::vector<mihs::BlockEntryDesc>* out) {

@@ -12,6 +12,11 @@ the plain FP64 path; each result's error against the closed-form solution is
 checked to be <= 1e-10 after timing.
 
 Prints ONE JSON line.  --gpus above 1 is refused: this build measures one GPU.
+
+Other workloads (opt-in, one JSON line each): --workload small_gauss (4096 x 256,
+Gaussian m = 256), batched_lambda_path (256 problems x 16 lambdas, Gaussian
+sketches, one launch), diff_2p18x1024 (64 right-hand sides, forward + adjoint
+backward through the autograd op).
 """
 from __future__ import annotations
 
@@ -70,8 +75,200 @@ def cpu_baseline(w, lam, rows):
                        f"scaled by n/rows = {scale:g}")}
 
 
+def timed(fn, steps, warmup, stream):
+    """Run fn warmup + steps times; return per-step wall ms (synchronised) and results."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    times, outs = [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs.append(fn())
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    return times, outs
+
+
+def run_batched(args):
+    """256 problems x 16 lambdas (n_k in [4096, 65536], d_k in [64, 512], FP64 A),
+    one Gaussian sketch per problem (mixed: BF16 on the matrix cores), then all
+    4096 lambda-path solves in one launch of the block kernel."""
+    import numpy as np
+    import torch
+    import paper_1912_03514_amd as mihs
+    import workloads as W
+    from oracle import solver as O
+    dev = torch.device("cuda", 0)
+    specs = W.batched_specs()
+    log(f"drawing {len(specs)} problems on the GPU")
+    probs = []
+    for s in specs:
+        sig = W.sigma_profile("exp", s.d, 6.0)
+        A, b, _, _ = W.make_problem_torch(s.n, s.d, sig, s.d / 2, s.seed, dev, "f64")
+        probs.append((A, b))
+    torch.cuda.synchronize()
+    nlam = len(specs[0].lambdas)
+    lam = np.stack([s.lambdas for s in specs])
+    sds = np.stack([[W.nominal_sd(W.sigma_profile("exp", s.d, 6.0), float(l)) for l in s.lambdas]
+                    for s in specs])
+    ms = np.array([s.m for s in specs], dtype=np.float64)
+    betas = np.minimum(sds / ms[:, None], 0.95)
+    alphas = (1.0 - betas) ** 2
+    lam_d = torch.as_tensor(lam, device=dev)
+    al_d = torch.as_tensor(alphas, device=dev)
+    be_d = torch.as_tensor(betas, device=dev)
+    eps_sub = 0.1
+
+    def step():
+        sk = [mihs.mihs_sketch(A, "gaussian", s.m, 10 + i, precision="mixed")
+              for i, ((A, b), s) in enumerate(zip(probs, specs))]
+        ev = torch.cuda.Event(enable_timing=True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        xs, infos = mihs.mihs_solve_batched([(A, b, SA) for (A, b), SA in zip(probs, sk)],
+                                            lam_d, al_d, be_d, eps_sub=eps_sub, tol=args.tol,
+                                            max_outer=400, max_inner=2000)
+        ev.record()
+        torch.cuda.synchronize()
+        return xs, infos, ev0.elapsed_time(ev)
+
+    times, outs = timed(step, args.steps, args.warmup, None)
+    xs, infos, solve_ms = outs[-1]
+    # sampled accuracy against the closed form (host)
+    errs = []
+    for i in (0, 97, 255):
+        A_h, b_h = probs[i][0].cpu().numpy(), probs[i][1].cpu().numpy()
+        for j in (0, 7, 15):
+            ref = O.ridge_lstsq(A_h, b_h, float(lam[i, j]))
+            x = xs[i][:, j].cpu().numpy()
+            errs.append(float(np.linalg.norm(x - ref) / np.linalg.norm(ref)))
+    outer = np.array([[r["outer_iters"] for r in inf] for inf in infos])
+    inner = np.array([[r["inner_iters_total"] for r in inf] for inf in infos])
+    status = np.array([[r["status"] for r in inf] for inf in infos])
+    apass = sum(s.n * s.d * 8 for s in specs)
+    rounds = int(outer.max(axis=1).sum())  # passes over each A (one per outer round)
+    achieved = sum(s.n * s.d * 8 * int(outer[i].max()) for i, s in enumerate(specs)) / (solve_ms * 1e-3) / 1e9
+    flops = sum(4.0 * s.n * s.d * 16 * int(outer[i].max()) for i, s in enumerate(specs))
+    return {
+        "metric": "time to solve 256 ridge problems x 16 lambdas to 1e-10 (sketch + batched M-IHS)",
+        "value": round(float(np.mean(times)), 3), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(float(np.mean(times)), 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (BF16 sketches)", "data": "synthetic",
+        "config": {"workload": "batched_lambda_path", "problems": len(specs), "nlam": nlam,
+                   "n_range": [4096, 65536], "d_range": [64, 512], "eps_sub": eps_sub,
+                   "tol": args.tol, "a_bytes_total": apass},
+        "solve_ms": round(solve_ms, 3), "sketch_ms": round(float(np.mean(times)) - solve_ms, 3),
+        "outer_iters_max": int(outer.max()), "outer_iters_mean": float(outer.mean()),
+        "inner_iters_mean": float(inner.mean()), "all_converged": bool((status == 0).all()),
+        "sampled_max_rel_err": max(errs),
+        "roofline": {"bound": "mfma", "kernel": "batched_kernel", "achieved": round(flops / (solve_ms * 1e-3) / 1e12, 2),
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": round(flops / (solve_ms * 1e-3) / 1e12 / 78.6, 4),
+                     "traffic": None, "a_pass_gbs": round(achieved, 1)},
+    }
+
+
+def run_diff(args):
+    """n = 2^18, d = 1024, FP32 A, 64 right-hand sides: forward (multi-RHS M-IHS on an
+    SRHT sketch) + backward (adjoint M-IHS) of L = sum_j ||C x*_j - y_j||^2 through
+    the autograd op; dL/dB and dL/dlog(lambda) checked against the dense FP64 gradient."""
+    import numpy as np
+    import torch
+    import paper_1912_03514_amd as mihs
+    import workloads as W
+    from oracle import solver as O
+    dev = torch.device("cuda", 0)
+    w = W.workload("diff_2p18x1024")
+    log("drawing the differentiation workload on the GPU")
+    A, B, _, lam = W.make_problem_torch(w.n, w.d, w.sigma, w.sd_target, w.data_seed, dev,
+                                        w.a_dtype, nrhs=w.nrhs)
+    g = torch.Generator(device=dev).manual_seed(w.data_seed + 1)
+    C = torch.randn(128, w.d, generator=g, dtype=torch.float64, device=dev)
+    Y = torch.randn(128, w.nrhs, generator=g, dtype=torch.float64, device=dev)
+    alpha, beta = mihs.momentum(w.sd_target, w.m)
+    kw = dict(eps_sub=w.eps_sub, tol=1e-12, max_outer=300)
+    ll0 = math.log(lam)
+
+    def step():
+        SA = mihs.mihs_sketch(A, "srht", w.m, w.sketch_seed)
+        Bt = B.clone().requires_grad_(True)
+        ll = torch.tensor(ll0, dtype=torch.float64, device=dev, requires_grad=True)
+        X = mihs.MIHSRidge.apply(Bt, ll, A, SA, alpha, beta, kw)
+        L = ((C @ X - Y) ** 2).sum()
+        L.backward()
+        return X.detach(), Bt.grad, ll.grad
+
+    times, outs = timed(step, args.steps, args.warmup, None)
+    X, dB, dll = outs[-1]
+    log("dense FP64 reference gradient on the host")
+    A64 = A.double().cpu().numpy()
+    Bh = B.cpu().numpy()
+    Xs = O.ridge_cholesky(A64, Bh, lam)
+    Ch, Yh = C.cpu().numpy(), Y.cpu().numpy()
+    gbar = 2 * Ch.T @ (Ch @ Xs - Yh)
+    _, dBref, dlref = O.ridge_backward_dense(A64, lam, Xs, gbar)
+    ex = float(np.linalg.norm(X.cpu().numpy() - Xs) / np.linalg.norm(Xs))
+    eb = float(np.linalg.norm(dB.cpu().numpy() - dBref) / np.linalg.norm(dBref))
+    el = abs(float(dll) - lam * dlref) / abs(lam * dlref)
+    return {
+        "metric": "forward + backward time of a 64-RHS ridge layer (M-IHS + adjoint M-IHS)",
+        "value": round(float(np.mean(times)), 3), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(float(np.mean(times)), 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": w.name, "n": w.n, "d": w.d, "a_dtype": w.a_dtype,
+                                        "nrhs": w.nrhs, "sketch": "srht", "m": w.m, "lambda": lam},
+        "rel_err_X": ex, "rel_err_dB": eb, "rel_err_dloglam": el,
+        "roofline": None,
+    }
+
+
+def run_small(args):
+    import numpy as np
+    import torch
+    import paper_1912_03514_amd as mihs
+    import workloads as W
+    from oracle import solver as O
+    dev = torch.device("cuda", 0)
+    w = W.workload("small_gauss")
+    P = w.draw()
+    A, b = torch.from_numpy(P.A).to(dev), torch.from_numpy(P.b).to(dev)
+    alpha, beta = mihs.momentum(w.sd_target, w.m)
+    ws = mihs.SolveWorkspace(w.n, w.d, w.m, "plain", dev)
+
+    def step():
+        SA = mihs.mihs_sketch(A, "gaussian", w.m, w.sketch_seed)
+        return mihs.mihs_solve(A, b, P.lam, SA, alpha, beta, eps_sub=w.eps_sub, tol=args.tol,
+                               max_outer=200, max_inner=2000, workspace=ws)
+
+    times, outs = timed(step, args.steps, args.warmup, None)
+    x, info = outs[-1]
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    err = float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs))
+    return {
+        "metric": "time-to-1e-10 rel.err per ridge solve (M-IHS, plain FP64; Gaussian sketch + solve)",
+        "value": round(float(np.mean(times)), 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(float(np.mean(times)), 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m},
+        "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters_total"],
+        "rel_err": err, "roofline": None,
+    }
+
+
 def main():
     args = parse()
+    if args.workload in ("batched_lambda_path", "diff_2p18x1024", "small_gauss"):
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        import paper_1912_03514_amd as mihs
+        mihs.load_library()
+        fn = {"batched_lambda_path": run_batched, "diff_2p18x1024": run_diff,
+              "small_gauss": run_small}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))

@@ -176,8 +176,9 @@ static size_t backward_ws_bytes(mihs_handle_t handle, int64_t n, int64_t d, int6
       e.d = d;
       e.m = m;
       e.ncols = 16;
+      e.sa_group = 0;
     }
-    return params + mihs::block_workspace_bytes(ents.data(), (int64_t)ents.size(), handle->num_cu);
+    return params + mihs::block_workspace_bytes(handle, ents.data(), (int64_t)ents.size());
   }
   return params + mihs::solve_workspace_bytes(handle, n, d, m, mixed) +
          2 * align_up((size_t)d * sizeof(double), 256);
@@ -240,6 +241,7 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
       e.beta = pl + 32;
       e.info = d_info + g0;
       e.ncols = (int)((k - g0) < 16 ? (k - g0) : 16);
+      e.sa_group = 0;
       ents.push_back(e);
     }
     rc = mihs::launch_block(handle, ents.data(), (int64_t)ents.size(), a_dtype == MIHS_F32, mixed,
@@ -305,9 +307,10 @@ int mihs_solve_multi_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, 
     e.d = d;
     e.m = m;
     e.ncols = 16;
+    e.sa_group = 0;
   }
   *bytes = align_up(3 * 16 * sizeof(double), 256) +
-           mihs::block_workspace_bytes(ents.data(), (int64_t)ents.size(), handle->num_cu);
+           mihs::block_workspace_bytes(handle, ents.data(), (int64_t)ents.size());
   return MIHS_OK;
 }
 
@@ -357,6 +360,7 @@ int mihs_solve_multi(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, 
     e.beta = pl + 32;
     e.info = d_info + g0;
     e.ncols = (int)((k - g0) < 16 ? (k - g0) : 16);
+    e.sa_group = 0;
     ents.push_back(e);
   }
   return mihs::launch_block(handle, ents.data(), (int64_t)ents.size(), a_dtype == MIHS_F32,
@@ -390,6 +394,7 @@ static void batched_entries(const mihs_problem_t* hp, int64_t nprob, const doubl
       e.beta = betas ? betas + p * nlam + g0 : nullptr;
       e.info = hp[p].info + g0;
       e.ncols = (int)((nlam - g0) < 16 ? (nlam - g0) : 16);
+      e.sa_group = p;  // the lambda-path of one problem shares its sketch
       out->push_back(e);
     }
   }
@@ -402,7 +407,7 @@ int mihs_solve_batched_workspace_size(mihs_handle_t handle, const mihs_problem_t
   (void)precision;
   std::vector<mihs::BlockEntryDesc> ents;
   batched_entries(h_problems, nprob, nullptr, nullptr, nullptr, nlam, &ents);
-  *bytes = mihs::block_workspace_bytes(ents.data(), (int64_t)ents.size(), handle->num_cu);
+  *bytes = mihs::block_workspace_bytes(handle, ents.data(), (int64_t)ents.size());
   return MIHS_OK;
 }
 

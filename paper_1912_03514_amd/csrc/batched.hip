@@ -2,18 +2,23 @@
 // one pass over A per outer iteration (a lambda-path shares A, b and SA; the
 // backward's adjoint systems share A, SA and lambda).
 //
+// Before the solve, the Gram matrix H = (SA)^T SA (d x d, FP64) of every
+// distinct sketch is formed on the matrix cores; the inner CG applies the
+// sub-problem operator as q = H p + lambda p, which costs d^2 per column instead
+// of the 2 m d of two passes over SA and needs no reduction across workgroups.
+//
 // One persistent cooperative launch.  The host scheduler gives each large
 // problem a dedicated team of workgroups (synchronised by a team barrier) and
 // packs small problems into single-workgroup bins that run them one after the
 // other.  Per entry (problem x group of 16 columns) and outer iteration:
 //
-//   pass  for each 16-row tile of M (A, then SA in every CG iteration):
-//         stage the tile in LDS (FP64), U = C - M_tile X on the matrix cores
-//         (v_mfma_f64_16x16x4, the four waves split the d-range and add their
-//         partial U in LDS), then G += M_tile^T U for each wave's d-slice.
-//   A     G = A^T (B - A X) (+ RHS) - X diag(lambda), reduced over the team.
-//   CG    16 CGs in lockstep on ((SA)^T SA + lambda_j I), per-column step
-//         lengths, per-column convergence masks; two team barriers each.
+//   A     for each 16-row tile of A: stage it in LDS, U = C - A_tile X on the
+//         matrix cores (v_mfma_f64_16x16x4; the four waves split the d-range and
+//         add their partial U in LDS), then G += A_tile^T U for each wave's
+//         d-slice; G = A^T (B - A X) (+ RHS) - X diag(lambda), reduced over the team.
+//   CG    16 CGs in lockstep on (H + lambda_j I) on the first tcg members of the
+//         team (own barrier), each owning a 16-aligned range of columns of q;
+//         per-column step lengths and convergence masks; two barriers each.
 //   U     per-column heavy-ball step and relative-step stop test.
 //
 // Everything is FP64; all reductions run in a fixed order.
@@ -44,8 +49,8 @@ struct BatchEntry {
   int64_t ldb, ldbc;
   const double* RHS;  // adjoint: extra d-space term RHS[c * ldr + j] (or null)
   int64_t ldr;
-  const void* SA;
-  int64_t m, ldsa;
+  const double* H;    // Gram matrix (SA)^T SA, dp x dp, zero beyond d
+  int64_t ldh;
   double* X;          // X[c * ldx + j], in: start, out: result
   int64_t ldx;
   const double* lam;
@@ -54,8 +59,9 @@ struct BatchEntry {
   mihs_info_t* info;  // ncols records
   double* work;       // per-entry scratch (see entry_layout)
   unsigned* bar;      // team barrier counter (own 128-byte line)
+  unsigned* bar_cg;   // CG sub-team barrier counter (own 128-byte line)
   int d, dp, ncols;
-  int team0, tsize;
+  int team0, tsize, tcg;
 };
 
 struct BatchArgs {
@@ -63,16 +69,16 @@ struct BatchArgs {
   const int* wg_items;  // per workgroup: entry indices, -1 terminated
   int items_stride;
   int* err;
-  int a_f32, sa_f32;
+  int a_f32;
   double eps_sub, tol;
   int64_t max_outer, max_inner;
-  BarrierSpin spin;
+  BarrierSpin spin, spin_idle;
 };
 
 // Scratch of one entry, in doubles: partial block vectors of every team member,
-// then R, Z, P0, P1, XP (dp x KR each), then scalar partial slots.
+// then R, Z, Q, XP (dp x KR each), then scalar partial slots.
 struct EntryLayout {
-  size_t part, R, Z, P0, P1, XP, scal, total;
+  size_t part, R, Z, Q, XP, scal, total;
 };
 __host__ __device__ inline EntryLayout entry_layout(int dp, int tsize) {
   EntryLayout L;
@@ -81,8 +87,7 @@ __host__ __device__ inline EntryLayout entry_layout(int dp, int tsize) {
   L.part = o; o += (size_t)tsize * blk;
   L.R = o; o += blk;
   L.Z = o; o += blk;
-  L.P0 = o; o += blk;
-  L.P1 = o; o += blk;
+  L.Q = o; o += blk;
   L.XP = o; o += blk;
   L.scal = o; o += (size_t)tsize * kNScal;
   L.total = (o + 31) / 32 * 32;
@@ -101,17 +106,17 @@ struct Shared {
   int flag;
 };
 
-__device__ __forceinline__ bool team_sync(const BatchEntry& e, unsigned& epoch, int* err,
-                                          int* s_flag, BarrierSpin spin) {
-  if (e.tsize <= 1) {
+__device__ __forceinline__ bool group_sync(unsigned* bar, int size, unsigned& epoch, int* err,
+                                           int* s_flag, BarrierSpin spin) {
+  if (size <= 1) {
     __threadfence_block();
     __syncthreads();
     return true;
   }
-  return barrier_flat(e.bar, epoch, (unsigned)e.tsize, err, s_flag, spin);
+  return barrier_flat(bar, epoch, (unsigned)size, err, s_flag, spin);
 }
 
-// Sum over the team's slots: out[j] = sum_t scal[t * kNScal + s0 + j], j < KR.
+// Sum over the first T slots: out[j] = sum_t scal[t * kNScal + s0 + j], j < KR.
 __device__ __forceinline__ void team_slot_sums(const double* scal, int T, int s0, double* out,
                                                double* red) {
   // thread (j, q) with j = tid % 16 sums t = q, q + 16, ... ; fixed tree over q
@@ -142,53 +147,126 @@ __device__ __forceinline__ void column_partials(double v, double* out, double* r
   __syncthreads();
 }
 
+// Staging of one 16-row tile of M: each thread moves NCH 16-byte chunks
+// (coalesced across the workgroup) from global memory into registers, and later
+// from registers into the LDS tile (kept in M's own precision, row stride LDT).
+template <typename TM, int DP>
+struct TileCfg {
+  static constexpr int VE = 16 / (int)sizeof(TM);             // elements per chunk
+  static constexpr int CPR = DP / VE;                         // chunks per row
+  static constexpr int NCH = TROWS * CPR / kBlock;            // chunks per thread
+  static constexpr int LDT = DP + (sizeof(TM) == 4 ? 4 : 2);  // LDS row stride (elements)
+  static_assert(NCH >= 1 && TROWS * CPR % kBlock == 0, "tile shape");
+};
+
+template <typename TM, int DP, bool NT>
+__device__ __forceinline__ void tile_load(const TM* __restrict__ M, int64_t ld, int64_t rows,
+                                          int d, int64_t row0,
+                                          uint4 (&buf)[TileCfg<TM, DP>::NCH]) {
+  typedef TileCfg<TM, DP> C;
+#pragma unroll
+  for (int i = 0; i < C::NCH; ++i) {
+    const int ch = i * kBlock + (int)threadIdx.x;
+    const int r = ch / C::CPR, c = (ch % C::CPR) * C::VE;
+    const int64_t gr = row0 + r;
+    // rows are 16-byte aligned (checked at the boundary), so a chunk that starts
+    // before column d lies inside the row's aligned span
+    if (gr < rows && c < d) {
+      typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4* src = (const u32x4*)(M + gr * ld + c);
+      const u32x4 v = NT ? __builtin_nontemporal_load(src) : *src;
+      buf[i] = make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+      buf[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+}
+
+template <typename TM, int DP>
+__device__ __forceinline__ void tile_store(const uint4 (&buf)[TileCfg<TM, DP>::NCH], int d,
+                                           TM* tile) {
+  typedef TileCfg<TM, DP> C;
+#pragma unroll
+  for (int i = 0; i < C::NCH; ++i) {
+    const int ch = i * kBlock + (int)threadIdx.x;
+    const int r = ch / C::CPR, c = (ch % C::CPR) * C::VE;
+    union {
+      uint4 u;
+      TM v[C::VE];
+    } x;
+    x.u = buf[i];
+    if (c + C::VE > d) {
+#pragma unroll
+      for (int e = 0; e < C::VE; ++e)
+        if (c + e >= d) x.v[e] = (TM)0;
+    }
+    *(uint4*)(tile + r * C::LDT + c) = x.u;
+  }
+}
+
 // One pass over rows [0, rows) of M (tiles t = rank, rank + T, ...):
 //   U = C - M_tile V (C from B in ridge mode, 0 otherwise), uu[j] += sum U^2,
 //   Gacc (this wave's d-slice) += M_tile^T U.
 // V is the B operand in registers: Vreg[s] = V[kbase + 4 s + lane/16][lane % 16].
-template <typename TM, int DP>
+// The next tile's global loads are issued before the current tile is computed,
+// so they are in flight during its matrix-core work.
+// With VLDS the B operand is read from the LDS copy xs of V (row-major d x 16,
+// which is the operand order) instead of registers.
+template <typename TM, int DP, bool NT, bool VLDS>
 __device__ __forceinline__ void block_pass(const TM* __restrict__ M, int64_t ld, int64_t rows,
                                            int d, int rank, int T, const double* __restrict__ B,
                                            int64_t ldb, int64_t ldbc, int ncols,
-                                           const double (&Vreg)[DP / 16],
-                                           f64x4 (&Gacc)[DP / 64], double* tile, Shared& sh,
+                                           const double (&Vreg)[DP / 16], const double* xs,
+                                           f64x4 (&Gacc)[DP / 64], void* tile_raw, Shared& sh,
                                            double& uu_lane) {
+  typedef TileCfg<TM, DP> C;
   constexpr int DQ = DP / 4;   // columns per wave
   constexpr int KS = DQ / 4;   // k-steps per wave
   constexpr int NB = DQ / 16;  // 16-column output blocks per wave
-  constexpr int LDT = DP + 1;  // LDS tile row stride (odd: spreads the 16 rows over banks)
+  TM* tile = (TM*)tile_raw;
   const int lane = lane_id(), wave = wave_id();
   const int kbase = wave * DQ;
+  const int rr = threadIdx.x / KR, jj = threadIdx.x % KR;  // (row, column) of U per thread
   const int64_t ntiles = (rows + TROWS - 1) / TROWS;
-  for (int64_t t = rank; t < ntiles; t += T) {
+  uint4 buf[C::NCH];
+  int64_t t = rank;
+  if (t < ntiles) tile_load<TM, DP, NT>(M, ld, rows, d, t * TROWS, buf);
+  for (; t < ntiles; t += T) {
     const int64_t row0 = t * TROWS;
     __syncthreads();  // previous tile fully consumed
-    for (int e = threadIdx.x; e < TROWS * DP; e += kBlock) {
-      const int r = e / DP, c = e % DP;
-      const int64_t gr = row0 + r;
-      tile[r * LDT + c] = (gr < rows && c < d) ? (double)M[gr * ld + c] : 0.0;
-    }
+    tile_store<TM, DP>(buf, d, tile);
+    const int64_t gr = row0 + rr;
+    const double cval = (B && gr < rows && jj < ncols) ? B[gr * ldb + jj * ldbc] : 0.0;
     __syncthreads();
+    if (t + T < ntiles) tile_load<TM, DP, NT>(M, ld, rows, d, (t + T) * TROWS, buf);
     // partial U over this wave's k-range
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (VLDS) {
+      const TM* trow = tile + (lane & 15) * C::LDT + kbase + (lane >> 4);
+      const double* xrow = xs + kbase * KR + lane;
+#pragma unroll 4
+      for (int s = 0; s < KS; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)trow[4 * s], xrow[4 * s * KR], acc,
+                                                   0, 0, 0);
+    } else {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const double a = tile[(lane & 15) * LDT + kbase + 4 * s + (lane >> 4)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
+      for (int s = 0; s < KS; ++s) {
+        const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
+        if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
     }
     // result register r of lane l: row l/16 + 4 r, column l % 16
 #pragma unroll
     for (int r = 0; r < 4; ++r) sh.ured[wave][((lane >> 4) + 4 * r) * KR + (lane & 15)] = acc[r];
     __syncthreads();
     {
-      const int rr = threadIdx.x / KR, j = threadIdx.x % KR;  // one (row, column) per thread
-      double s = 0.0;
+      double su = 0.0;
 #pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) s += sh.ured[w][rr * KR + j];
-      const int64_t gr = row0 + rr;
+      for (int w = 0; w < kWavesPerBlock; ++w) su += sh.ured[w][rr * KR + jj];
       double u = 0.0;
-      if (gr < rows && j < ncols) u = (B ? B[gr * ldb + j * ldbc] : 0.0) - s;
-      sh.ufin[rr * KR + j] = u;
+      if (gr < rows && jj < ncols) u = cval - su;
+      sh.ufin[rr * KR + jj] = u;
       uu_lane += u * u;
     }
     __syncthreads();
@@ -197,11 +275,12 @@ __device__ __forceinline__ void block_pass(const TM* __restrict__ M, int64_t ld,
     for (int b = 0; b < NB; ++b) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int rr = 4 * s + (lane >> 4);
-        const double a = tile[rr * LDT + kbase + 16 * b + (lane & 15)];
-        const double bv = sh.ufin[rr * KR + (lane & 15)];
+        const int r2 = 4 * s + (lane >> 4);
+        const double a = (double)tile[r2 * C::LDT + kbase + 16 * b + (lane & 15)];
+        const double bv = sh.ufin[r2 * KR + (lane & 15)];
         Gacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, Gacc[b], 0, 0, 0);
       }
+      if ((b & 1) == 1) __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -220,13 +299,13 @@ __device__ __forceinline__ void store_block(const f64x4 (&Gacc)[DP / 64], double
     }
 }
 
-template <int DP>
-__device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, double* tile,
-                          Shared& sh) {
+template <int DP, bool VLDS>
+__device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, void* tile,
+                          double* xs, Shared& sh) {
   constexpr int DQ = DP / 4;
   constexpr int KS = DQ / 4;
   constexpr int NB = DQ / 16;
-  const int T = e.tsize;
+  const int T = e.tsize, Tc = e.tcg;
   const int d = e.d;
   const int lane = lane_id(), wave = wave_id();
   const int kbase = wave * DQ;
@@ -235,14 +314,18 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, dou
   double* part = W + L.part;
   double* R = W + L.R;
   double* Z = W + L.Z;
-  double* P[2] = {W + L.P0, W + L.P1};
+  double* Q = W + L.Q;
   double* XP = W + L.XP;
   double* scal = W + L.scal;
   double* myscal = scal + (int64_t)rank * kNScal;
-  const int cpw = (d + T - 1) / T;
-  const int c_lo = min(d, rank * cpw), c_hi = min(d, c_lo + cpw);
+  double* stage = (double*)tile;  // d x 16 vectors (row-major = MFMA B-operand order)
+  const bool cg = rank < Tc;
+  // CG members own 16-aligned column ranges of R, Z, Q, XP and X
+  const int cpw = ((d + Tc - 1) / Tc + 15) / 16 * 16;
+  const int c_lo = cg ? min(d, rank * cpw) : d;
+  const int c_hi = cg ? min(d, c_lo + cpw) : d;
   const int nown = c_hi - c_lo;
-  unsigned epoch = 0;
+  unsigned ep_all = 0, ep_cg = 0;
   int* s_flag = &sh.flag;
   bool alive = true;
 
@@ -269,185 +352,197 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, dou
   }
   __syncthreads();
 
-  int status_all = MIHS_MAX_ITER;
   int64_t outer = 0;
   for (; outer < a.max_outer; ++outer) {
     // ---- A pass: G partial = A^T (C - A X) over this member's tiles
     double Vreg[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int c = kbase + 4 * s + (lane >> 4), j = lane & 15;
-      Vreg[s] = (c < d && j < e.ncols) ? e.X[(int64_t)c * e.ldx + j] : 0.0;
-    }
-    f64x4 Gacc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) Gacc[b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    double uu_lane = 0.0;
-    if (a.a_f32)
-      block_pass<float, DP>((const float*)e.A, e.lda, e.n, d, rank, T, e.B, e.ldb, e.ldbc,
-                            e.ncols, Vreg, Gacc, tile, sh, uu_lane);
-    else
-      block_pass<double, DP>((const double*)e.A, e.lda, e.n, d, rank, T, e.B, e.ldb, e.ldbc,
-                             e.ncols, Vreg, Gacc, tile, sh, uu_lane);
-    store_block<DP>(Gacc, part + (int64_t)rank * DP * KR);
-    if (!(alive = team_sync(e, epoch, a.err, s_flag, a.spin))) break;
-
-    // ---- owners: g = sum of partials + rhs - lambda x; CG start (r = p = g, z = 0)
-    double rr_lane = 0.0;
-    for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
-      const int c = c_lo + idx / KR, j = idx % KR;
-      double g = 0.0;
-      for (int t = 0; t < T; ++t) g += part[((int64_t)t * DP + c) * KR + j];
-      if (j < e.ncols) {
-        if (e.RHS) g += e.RHS[(int64_t)c * e.ldr + j];
-        g -= sh.lam[j] * e.X[(int64_t)c * e.ldx + j];
-      }
-      if (sh.done[j]) g = 0.0;
-      const int64_t o = (int64_t)c * KR + j;
-      R[o] = g;
-      Z[o] = 0.0;
-      P[0][o] = g;
-      rr_lane += g * g;
-    }
-    column_partials(rr_lane, myscal + 0, sh.red);
-    if (!(alive = team_sync(e, epoch, a.err, s_flag, a.spin))) break;
-    team_slot_sums(scal, T, 0, sh.rr0, sh.red);
-    if (threadIdx.x < KR) {
-      const int j = threadIdx.x;
-      sh.rr[j] = sh.rr0[j];
-      sh.gnorm[j] = sh.done[j] ? sh.gnorm[j] : sqrt(sh.rr0[j]);
-      sh.active[j] = (!sh.done[j] && sh.rr0[j] > 0.0) ? 1 : 0;
-      sh.bcg[j] = 0.0;
-      sh.kin[j] = 0;
-      // a column whose gradient is exactly zero sits at its solution
-      if (!sh.done[j] && !(sh.rr0[j] > 0.0)) sh.done[j] = 1;
-    }
-    __syncthreads();
-
-    // ---- lockstep CG
-    int64_t k = 0;
-    while (true) {
-      int any = 0;
-      for (int j = 0; j < KR; ++j) any |= sh.active[j];
-      if (!any || k >= a.max_inner) break;
-      double* pcur = P[k & 1];
-      const double* pprev = P[(k + 1) & 1];
-      // p = r + beta_cg p_prev for this wave's slice (B operand layout); owners store theirs
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int c = kbase + 4 * s + (lane >> 4), j = lane & 15;
-        double v = 0.0;
-        if (c < d) {
-          const int64_t o = (int64_t)c * KR + j;
-          v = (k == 0) ? pcur[o] : (sh.active[j] ? R[o] + sh.bcg[j] * pprev[o] : 0.0);
-          if (k > 0 && c >= c_lo && c < c_hi) pcur[o] = v;
-        }
-        Vreg[s] = v;
-      }
-      // ||p_j||^2 over all d (all four waves' slices)
-      double pp_lane = 0.0;
-#pragma unroll
-      for (int s = 0; s < KS; ++s) pp_lane += Vreg[s] * Vreg[s];
-      // lanes with equal lane % 16 hold column j; combine within the wave, then waves
-      pp_lane += __shfl_xor(pp_lane, 16, kWave);
-      pp_lane += __shfl_xor(pp_lane, 32, kWave);
+    {
+      double* xd = VLDS ? xs : stage;
       __syncthreads();
-      if (lane < KR) sh.ured[wave][lane] = pp_lane;
-      __syncthreads();
-      if (threadIdx.x < KR) {
-        double t = 0.0;
-        for (int w = 0; w < kWavesPerBlock; ++w) t += sh.ured[w][threadIdx.x];
-        sh.acg[threadIdx.x] = t;  // holds ||p_j||^2 until the step length is formed
+#pragma unroll 8
+      for (int i = 0; i < DP * KR / kBlock; ++i) {
+        const int idx = i * kBlock + (int)threadIdx.x;
+        const int c = idx / KR, j = idx % KR;
+        xd[idx] = (c < d && j < e.ncols) ? e.X[(int64_t)c * e.ldx + j] : 0.0;
       }
       __syncthreads();
+      if (!VLDS) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) Vreg[s] = stage[(kbase + 4 * s) * KR + lane];
+      }
+    }
+    {
+      f64x4 Gacc[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) Gacc[b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-      double uu = 0.0;
-      if (a.sa_f32)
-        block_pass<float, DP>((const float*)e.SA, e.ldsa, e.m, d, rank, T, nullptr, 0, 0,
-                              e.ncols, Vreg, Gacc, tile, sh, uu);
+      double uu_lane = 0.0;
+      if (a.a_f32)
+        block_pass<float, DP, true, VLDS>((const float*)e.A, e.lda, e.n, d, rank, T, e.B,
+                                          e.ldb, e.ldbc, e.ncols, Vreg, xs, Gacc, tile, sh,
+                                          uu_lane);
       else
-        block_pass<double, DP>((const double*)e.SA, e.ldsa, e.m, d, rank, T, nullptr, 0, 0,
-                               e.ncols, Vreg, Gacc, tile, sh, uu);
+        block_pass<double, DP, true, VLDS>((const double*)e.A, e.lda, e.n, d, rank, T, e.B,
+                                           e.ldb, e.ldbc, e.ncols, Vreg, xs, Gacc, tile, sh,
+                                           uu_lane);
       store_block<DP>(Gacc, part + (int64_t)rank * DP * KR);
-      column_partials(uu, myscal + KR, sh.red);
-      if (!(alive = team_sync(e, epoch, a.err, s_flag, a.spin))) break;
+    }
+    if (!(alive = group_sync(e.bar, T, ep_all, a.err, s_flag, a.spin))) break;
 
-      // step lengths: p^T q = ||SA p||^2 + lambda ||p||^2
-      team_slot_sums(scal, T, KR, sh.ufin, sh.red);  // ufin[0..15] <- sum ||u_j||^2
-      if (threadIdx.x < KR) {
-        const int j = threadIdx.x;
-        const double pq = sh.ufin[j] + sh.lam[j] * sh.acg[j];
-        double al = 0.0;
-        if (sh.active[j]) {
-          al = sh.rr[j] / pq;
-          if (!(pq > 0.0) || !isfinite(al)) {
-            al = 0.0;
-            sh.active[j] = 0;  // breakdown in this column: keep the current step
-          }
-        }
-        sh.acg[j] = al;
-      }
-      __syncthreads();
-      double rr_lane2 = 0.0;
+    if (cg) {
+      // ---- owners: g = sum of partials + rhs - lambda x; CG start r = g, z = 0
+      double rr_lane = 0.0;
       for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
         const int c = c_lo + idx / KR, j = idx % KR;
-        const int64_t o = (int64_t)c * KR + j;
-        double q = 0.0;
-        for (int t = 0; t < T; ++t) q += part[((int64_t)t * DP + c) * KR + j];
-        q = -q + sh.lam[j] * pcur[o];
-        const double al = sh.acg[j];
-        if (sh.active[j]) {
-          Z[o] += al * pcur[o];
-          R[o] -= al * q;
+        double g = 0.0;
+#pragma unroll 8
+        for (int t = 0; t < T; ++t) g += part[((int64_t)t * DP + c) * KR + j];
+        if (j < e.ncols) {
+          if (e.RHS) g += e.RHS[(int64_t)c * e.ldr + j];
+          g -= sh.lam[j] * e.X[(int64_t)c * e.ldx + j];
         }
-        rr_lane2 += R[o] * R[o];
+        if (sh.done[j]) g = 0.0;
+        const int64_t o = (int64_t)c * KR + j;
+        R[o] = g;
+        Z[o] = 0.0;
+        rr_lane += g * g;
       }
-      column_partials(rr_lane2, myscal + 0, sh.red);
-      if (!(alive = team_sync(e, epoch, a.err, s_flag, a.spin))) break;
-      team_slot_sums(scal, T, 0, sh.ufin, sh.red);  // ufin[0..15] <- new ||r_j||^2
-      ++k;
+      column_partials(rr_lane, myscal + 0, sh.red);
+      if (!(alive = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin))) break;
+      team_slot_sums(scal, Tc, 0, sh.rr0, sh.red);
       if (threadIdx.x < KR) {
         const int j = threadIdx.x;
-        if (sh.active[j]) {
-          const double rn = sh.ufin[j];
-          sh.bcg[j] = rn / sh.rr[j];
-          sh.rr[j] = rn;
-          sh.kin[j] = k;
-          if (rn <= a.eps_sub * a.eps_sub * sh.rr0[j]) sh.active[j] = 0;
-        }
+        sh.rr[j] = sh.rr0[j];
+        sh.gnorm[j] = sh.done[j] ? sh.gnorm[j] : sqrt(sh.rr0[j]);
+        sh.active[j] = (!sh.done[j] && sh.rr0[j] > 0.0) ? 1 : 0;
+        sh.bcg[j] = 0.0;
+        sh.kin[j] = 0;
       }
       __syncthreads();
-    }
-    if (!alive) break;
-    if (threadIdx.x < KR) {
-      const int j = threadIdx.x;
-      if (!sh.done[j]) {
-        sh.inner[j] += sh.kin[j];
-        if (sh.kin[j] > sh.inner_max[j]) sh.inner_max[j] = sh.kin[j];
-      }
-    }
 
-    // ---- heavy-ball update per column (owners) and relative-step partials
-    double s0 = 0.0, s1 = 0.0;
-    for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
-      const int c = c_lo + idx / KR, j = idx % KR;
-      if (j >= e.ncols || sh.done[j]) continue;
-      const int64_t o = (int64_t)c * KR + j;
-      double* xp = e.X + (int64_t)c * e.ldx + j;
-      const double xc = *xp;
-      const double xn = xc + sh.alpha[j] * Z[o] + sh.beta[j] * (xc - XP[o]);
-      XP[o] = xc;
-      *xp = xn;
-      s0 += (xn - xc) * (xn - xc);
-      s1 += xn * xn;
+      // ---- lockstep CG on (H + lambda_j I)
+      int64_t k = 0;
+      while (true) {
+        int any = 0;
+        for (int j = 0; j < KR; ++j) any |= sh.active[j];
+        if (!any || k >= a.max_inner) break;
+        // p = r (first step) or r + beta_cg p over all d, in place in the stage
+        __syncthreads();
+        {
+          const int j = threadIdx.x % KR;  // fixed column per thread
+          const bool act = sh.active[j] != 0;
+          const double bc = sh.bcg[j];
+#pragma unroll 8
+          for (int i = 0; i < DP * KR / kBlock; ++i) {
+            const int idx = i * kBlock + (int)threadIdx.x;
+            const int c = idx / KR;
+            double v = 0.0;
+            if (c < d && act) v = (k == 0) ? R[idx] : R[idx] + bc * stage[idx];
+            stage[idx] = v;
+          }
+        }
+        __syncthreads();
+        // q = H p + lambda p on the owned 16-column blocks; the waves split the
+        // k-range (lane (r, g) walks k = kbase + g KS + s, contiguous in H's row)
+        double pq_lane = 0.0;
+        for (int cb = c_lo; cb < c_hi; cb += 16) {
+          const double* hrow = e.H + (int64_t)(cb + (lane & 15)) * e.ldh + kbase + (lane >> 4) * KS;
+          const double* prow = stage + (kbase + (lane >> 4) * KS) * KR + (lane & 15);
+          f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+          for (int s = 0; s < KS; ++s)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(hrow[s], prow[s * KR], acc, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            sh.ured[wave][((lane >> 4) + 4 * r) * KR + (lane & 15)] = acc[r];
+          __syncthreads();
+          const int rr = threadIdx.x / KR, j = threadIdx.x % KR;
+          const int c = cb + rr;
+          if (c < c_hi) {
+            double qv = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWavesPerBlock; ++w) qv += sh.ured[w][rr * KR + j];
+            const double pv = stage[c * KR + j];
+            qv += sh.lam[j] * pv;
+            Q[(int64_t)c * KR + j] = qv;
+            pq_lane += pv * qv;
+          }
+          __syncthreads();
+        }
+        column_partials(pq_lane, myscal + KR, sh.red);
+        if (!(alive = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin))) break;
+        team_slot_sums(scal, Tc, KR, sh.ufin, sh.red);  // ufin[0..15] <- p_j^T q_j
+        if (threadIdx.x < KR) {
+          const int j = threadIdx.x;
+          const double pq = sh.ufin[j];
+          double al = 0.0;
+          if (sh.active[j]) {
+            al = sh.rr[j] / pq;
+            if (!(pq > 0.0) || !isfinite(al)) {
+              al = 0.0;
+              sh.active[j] = 0;  // breakdown in this column: keep the current step
+            }
+          }
+          sh.acg[j] = al;
+        }
+        __syncthreads();
+        // owners: z += alpha p, r -= alpha q
+        double rr_lane2 = 0.0;
+        for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
+          const int c = c_lo + idx / KR, j = idx % KR;
+          const int64_t o = (int64_t)c * KR + j;
+          if (sh.active[j]) {
+            const double al = sh.acg[j];
+            Z[o] += al * stage[o];
+            R[o] -= al * Q[o];
+          }
+          rr_lane2 += R[o] * R[o];
+        }
+        column_partials(rr_lane2, myscal + 0, sh.red);
+        if (!(alive = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin))) break;
+        team_slot_sums(scal, Tc, 0, sh.ufin, sh.red);  // ufin[0..15] <- new ||r_j||^2
+        ++k;
+        if (threadIdx.x < KR) {
+          const int j = threadIdx.x;
+          if (sh.active[j]) {
+            const double rn = sh.ufin[j];
+            sh.bcg[j] = rn / sh.rr[j];
+            sh.rr[j] = rn;
+            sh.kin[j] = k;
+            if (rn <= a.eps_sub * a.eps_sub * sh.rr0[j]) sh.active[j] = 0;
+          }
+        }
+        __syncthreads();
+      }
+      if (!alive) break;
+      if (threadIdx.x < KR) {
+        const int j = threadIdx.x;
+        if (!sh.done[j]) {
+          sh.inner[j] += sh.kin[j];
+          if (sh.kin[j] > sh.inner_max[j]) sh.inner_max[j] = sh.kin[j];
+        }
+      }
+
+      // ---- heavy-ball update per column (owners) and relative-step partials
+      double s0 = 0.0, s1 = 0.0;
+      for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
+        const int c = c_lo + idx / KR, j = idx % KR;
+        if (j >= e.ncols || sh.done[j]) continue;
+        const int64_t o = (int64_t)c * KR + j;
+        double* xp = e.X + (int64_t)c * e.ldx + j;
+        const double xc = *xp;
+        const double xn = xc + sh.alpha[j] * Z[o] + sh.beta[j] * (xc - XP[o]);
+        XP[o] = xc;
+        *xp = xn;
+        s0 += (xn - xc) * (xn - xc);
+        s1 += xn * xn;
+      }
+      column_partials(s0, myscal + 2 * KR, sh.red);
+      column_partials(s1, myscal + 3 * KR, sh.red);
     }
-    column_partials(s0, myscal + 2 * KR, sh.red);
-    column_partials(s1, myscal + 3 * KR, sh.red);
-    if (!(alive = team_sync(e, epoch, a.err, s_flag, a.spin))) break;
-    team_slot_sums(scal, T, 2 * KR, sh.ufin, sh.red);
-    team_slot_sums(scal, T, 3 * KR, sh.acg, sh.red);
-    int all_done = 1;
+    // members outside the CG sub-team wait here through the whole inner solve
+    if (!(alive = group_sync(e.bar, T, ep_all, a.err, s_flag, cg ? a.spin : a.spin_idle))) break;
+    team_slot_sums(scal, Tc, 2 * KR, sh.ufin, sh.red);
+    team_slot_sums(scal, Tc, 3 * KR, sh.acg, sh.red);
     if (threadIdx.x < KR) {
       const int j = threadIdx.x;
       if (!sh.done[j]) {
@@ -458,9 +553,9 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, dou
       }
     }
     __syncthreads();
+    int all_done = 1;
     for (int j = 0; j < KR; ++j) all_done &= sh.done[j];
     if (all_done) {
-      status_all = MIHS_CONVERGED;
       ++outer;
       break;
     }
@@ -477,14 +572,41 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, dou
                          : ((sh.thr[j] > 0.0 && sh.done[j]) ? MIHS_CONVERGED : MIHS_MAX_ITER);
     inf->reserved = 0;
   }
-  (void)status_all;
   __syncthreads();
+}
+
+// LDS: the tile region (16 rows of the widest entry, FP64 rows of dp + 2
+// elements cover FP32 rows of dp + 4), then, for entries narrow enough, an LDS
+// copy of X (dp x 16 FP64) that feeds the matrix cores in the A pass.
+// Build-time choice of where the A pass keeps X: in registers (0, measured
+// faster on gfx950 for every width) or in LDS (1, fewer registers).
+#ifndef MIHS_X_LDS
+#define MIHS_X_LDS 0
+#endif
+constexpr size_t kLdsBudget = 160 * 1024 - 16 * 1024;
+__host__ __device__ constexpr size_t tile_region(int dp) {
+  return (size_t)TROWS * (dp + 2) * sizeof(double);
+}
+__host__ __device__ constexpr bool x_in_lds(int dpmax, int dp) {
+  if (MIHS_X_LDS == 0) return false;
+  return tile_region(dpmax) + (size_t)dp * KR * sizeof(double) <= kLdsBudget;
+}
+__host__ __device__ constexpr size_t lds_bytes(int dpmax) {
+  return tile_region(dpmax) + (x_in_lds(dpmax, dpmax) ? (size_t)dpmax * KR * sizeof(double) : 0);
+}
+
+template <int DPMAX, int DP>
+__device__ __forceinline__ void run_dp(const BatchArgs& a, const BatchEntry& e, int rank,
+                                       char* lds, Shared& sh) {
+  double* xs = (double*)(lds + tile_region(DPMAX));
+  run_entry<DP, x_in_lds(DPMAX, DP)>(a, e, rank, lds, xs, sh);
 }
 
 template <int DPMAX>
 __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
-  extern __shared__ double tile[];
+  extern __shared__ uint4 lds_raw[];
   __shared__ Shared sh;
+  char* lds = (char*)lds_raw;
   const int* items = a.wg_items + (int64_t)blockIdx.x * a.items_stride;
   for (int i = 0; i < a.items_stride; ++i) {
     const int ei = items[i];
@@ -492,12 +614,78 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
     const BatchEntry e = a.entries[ei];
     const int rank = (int)blockIdx.x - e.team0;
     // each entry runs at its own padded width (<= DPMAX)
-    if (e.dp <= 64) run_entry<64>(a, e, rank, tile, sh);
-    else if (DPMAX >= 128 && e.dp <= 128) run_entry<(DPMAX >= 128 ? 128 : 64)>(a, e, rank, tile, sh);
-    else if (DPMAX >= 256 && e.dp <= 256) run_entry<(DPMAX >= 256 ? 256 : 64)>(a, e, rank, tile, sh);
-    else if (DPMAX >= 512 && e.dp <= 512) run_entry<(DPMAX >= 512 ? 512 : 64)>(a, e, rank, tile, sh);
-    else if (DPMAX >= 1024) run_entry<(DPMAX >= 1024 ? 1024 : 64)>(a, e, rank, tile, sh);
+    if (e.dp <= 64) run_dp<DPMAX, 64>(a, e, rank, lds, sh);
+    else if (DPMAX >= 128 && e.dp <= 128) run_dp<DPMAX, (DPMAX >= 128 ? 128 : 64)>(a, e, rank, lds, sh);
+    else if (DPMAX >= 256 && e.dp <= 256) run_dp<DPMAX, (DPMAX >= 256 ? 256 : 64)>(a, e, rank, lds, sh);
+    else if (DPMAX >= 512 && e.dp <= 512) run_dp<DPMAX, (DPMAX >= 512 ? 512 : 64)>(a, e, rank, lds, sh);
+    else if (DPMAX >= 1024) run_dp<DPMAX, (DPMAX >= 1024 ? 1024 : 64)>(a, e, rank, lds, sh);
   }
+}
+
+// ---- Gram matrices H = M^T M (dp x dp, FP64) on the matrix cores ----------
+struct GramJob {
+  const void* M;
+  int64_t m, ld;
+  double* H;
+  int64_t ldh;
+  int d, bi, bj;
+};
+
+constexpr int kGramRows = 32;
+
+// One 64 x 64 block (bi <= bj) per workgroup: wave w owns rows 16 w.. of the
+// block and all four 16-column blocks; 32-row chunks of M staged in LDS.
+// Off-diagonal blocks are mirrored so H is exactly symmetric.
+template <typename TS>
+__global__ __launch_bounds__(kBlock) void gram_kernel(const GramJob* jobs) {
+  const GramJob J = jobs[blockIdx.x];
+  __shared__ double ti[kGramRows][64 + 1];
+  __shared__ double tj[kGramRows][64 + 1];
+  const TS* M = (const TS*)J.M;
+  const int lane = lane_id(), wave = wave_id();
+  const int ci0 = J.bi * 64, cj0 = J.bj * 64;
+  f64x4 acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int64_t r0 = 0; r0 < J.m; r0 += kGramRows) {
+    double vi[kGramRows * 64 / kBlock], vj[kGramRows * 64 / kBlock];
+#pragma unroll
+    for (int i = 0; i < kGramRows * 64 / kBlock; ++i) {
+      const int e = i * kBlock + (int)threadIdx.x;
+      const int r = e / 64, c = e % 64;
+      const int64_t gr = r0 + r;
+      const bool rok = gr < J.m;
+      vi[i] = (rok && ci0 + c < J.d) ? (double)M[gr * J.ld + ci0 + c] : 0.0;
+      vj[i] = (rok && cj0 + c < J.d) ? (double)M[gr * J.ld + cj0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kGramRows * 64 / kBlock; ++i) {
+      const int e = i * kBlock + (int)threadIdx.x;
+      ti[e / 64][e % 64] = vi[i];
+      tj[e / 64][e % 64] = vj[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kGramRows / 4; ++s) {
+      const int r = 4 * s + (lane >> 4);
+      const double av = ti[r][wave * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, tj[r][b * 16 + (lane & 15)], acc[b],
+                                                      0, 0, 0);
+    }
+  }
+  // result register r of lane l: row l/16 + 4 r, column l % 16
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = ci0 + wave * 16 + (lane >> 4) + 4 * r;
+      const int64_t j = cj0 + b * 16 + (lane & 15);
+      J.H[i * J.ldh + j] = acc[b][r];
+      if (J.bi != J.bj) J.H[j * J.ldh + i] = acc[b][r];
+    }
 }
 
 typedef void (*BatchKernel)(BatchArgs);
@@ -519,22 +707,142 @@ int dp_for(int64_t d) {
   return dp;
 }
 
-size_t tile_bytes(int dp) { return (size_t)TROWS * (dp + 1) * sizeof(double); }
 
 }  // namespace
 
 int block_max_d() { return 1024; }
 
-size_t block_workspace_bytes(const BlockEntryDesc* ents, int64_t count, int num_cu) {
-  // entries + items + per-entry scratch (assume the largest possible team) + barriers
-  size_t total = align_up((size_t)count * sizeof(BatchEntry), 256);
-  total += align_up((size_t)num_cu * (size_t)(count + 1) * sizeof(int), 256);
+namespace {
+
+// Deterministic schedule of the entries over G workgroups (also used to size
+// the workspace): dedicated teams for heavy entries, single-workgroup bins for
+// the rest.
+struct Schedule {
+  std::vector<int> team0, tsize, tcg;
+  std::vector<std::vector<int>> items;
+  size_t stride = 1;
+};
+
+int make_schedule(const BlockEntryDesc* ents, int64_t count, int G, Schedule* S) {
+  // weight: one A pass plus a typical inner solve on H per outer iteration
+  std::vector<double> wgt(count);
+  double total = 0.0;
   for (int64_t i = 0; i < count; ++i) {
-    const int dp = dp_for(ents[i].d);
-    total += align_up(entry_layout(dp, num_cu).total * sizeof(double), 256);
+    const double inner_est = 12.0;
+    wgt[i] = (double)ents[i].n * ents[i].d + inner_est * (double)ents[i].d * ents[i].d;
+    total += wgt[i];
   }
-  total += align_up((size_t)(count + 2) * 128, 256);
-  return total;
+  std::vector<int64_t> order(count);
+  for (int64_t i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t x, int64_t y) { return wgt[x] > wgt[y]; });
+  S->team0.assign(count, 0);
+  S->tsize.assign(count, 1);
+  S->tcg.assign(count, 1);
+  S->items.assign(G, std::vector<int>());
+  // An entry gets a share of the still-free workgroups proportional to its
+  // share of the still-unassigned weight, keeping one workgroup free while
+  // other entries remain; entries worth fewer than two go to the bins.
+  int next = 0;
+  int64_t first_small = count;
+  double left = total;
+  for (int64_t oi = 0; oi < count; ++oi) {
+    const int64_t i = order[oi];
+    const int free_wg = G - next;
+    const int reserve = (oi + 1 < count) ? 1 : 0;
+    int want = (int)std::floor(wgt[i] / left * free_wg + 0.5);
+    want = std::min(want, free_wg - reserve);
+    if (want < 2) {
+      first_small = oi;
+      break;
+    }
+    S->team0[i] = next;
+    S->tsize[i] = want;
+    for (int t = 0; t < want; ++t) S->items[next + t].push_back((int)i);
+    next += want;
+    left -= wgt[i];
+  }
+  std::vector<double> load(G, 0.0);
+  for (int64_t oi = first_small; oi < count; ++oi) {
+    const int64_t i = order[oi];
+    if (next >= G) return MIHS_ERR_UNSUPPORTED;
+    int best = next;
+    for (int g = next; g < G; ++g)
+      if (load[g] < load[best]) best = g;
+    S->team0[i] = best;
+    S->tsize[i] = 1;
+    S->items[best].push_back((int)i);
+    load[best] += wgt[i];
+  }
+  // CG sub-team: about 32 columns of H per member, at most the whole team
+  for (int64_t i = 0; i < count; ++i)
+    S->tcg[i] = std::max(1, std::min(S->tsize[i], (int)((ents[i].d + 31) / 32)));
+  S->stride = 1;
+  for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
+  return MIHS_OK;
+}
+
+// Distinct sketches (by group id) in order of first appearance.
+std::vector<int64_t> group_leaders(const BlockEntryDesc* ents, int64_t count) {
+  std::vector<int64_t> lead;
+  for (int64_t i = 0; i < count; ++i) {
+    bool seen = false;
+    for (int64_t l : lead)
+      if (ents[l].sa_group == ents[i].sa_group) {
+        seen = true;
+        break;
+      }
+    if (!seen) lead.push_back(i);
+  }
+  return lead;
+}
+
+struct BlockLayout {
+  size_t ent_off, item_off, gram_off, bar_off, total;
+  std::vector<size_t> work_off, h_off;
+  std::vector<int> ngram;  // gram jobs per group
+  size_t njobs;
+};
+
+BlockLayout block_layout(const BlockEntryDesc* ents, int64_t count, const Schedule& S, int G) {
+  BlockLayout L;
+  size_t off = 0;
+  L.ent_off = off;
+  off = align_up(off + (size_t)count * sizeof(BatchEntry), 256);
+  L.item_off = off;
+  off = align_up(off + (size_t)G * S.stride * sizeof(int), 256);
+  const std::vector<int64_t> lead = group_leaders(ents, count);
+  L.njobs = 0;
+  for (int64_t l : lead) {
+    const int nb = dp_for(ents[l].d) / 64;
+    L.ngram.push_back(nb * (nb + 1) / 2);
+    L.njobs += (size_t)nb * (nb + 1) / 2;
+  }
+  L.gram_off = off;
+  off = align_up(off + L.njobs * sizeof(GramJob), 256);
+  L.work_off.resize(count);
+  for (int64_t i = 0; i < count; ++i) {
+    L.work_off[i] = off;
+    off = align_up(off + entry_layout(dp_for(ents[i].d), S.tsize[i]).total * sizeof(double), 256);
+  }
+  for (int64_t l : lead) {
+    const size_t dp = (size_t)dp_for(ents[l].d);
+    L.h_off.push_back(off);
+    off = align_up(off + dp * dp * sizeof(double), 256);
+  }
+  L.bar_off = off;
+  off = align_up(off + (size_t)(2 * count + 2) * 128, 256);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count) {
+  if (count <= 0) return 0;
+  Schedule S;
+  if (make_schedule(ents, count, h->num_cu, &S) != MIHS_OK) return 0;
+  return block_layout(ents, count, S, h->num_cu).total;
 }
 
 int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
@@ -549,7 +857,7 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
   }
   BatchKernel kern = pick(dpmax);
   if (!kern) return MIHS_ERR_UNSUPPORTED;
-  const size_t shmem = tile_bytes(dpmax);
+  const size_t shmem = lds_bytes(dpmax);
   if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)shmem) != hipSuccess)
     return MIHS_ERR_HIP;
@@ -557,73 +865,44 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kBlock, shmem) != hipSuccess)
     return MIHS_ERR_HIP;
   if (occ < 1) return MIHS_ERR_UNSUPPORTED;
-  const int G = h->num_cu * std::min(occ, 1);
+  const int G = h->num_cu;  // one workgroup per compute unit
 
-  // ---- schedule: large entries get dedicated teams, small ones share bins
-  std::vector<double> wgt(count);
-  double total = 0.0;
-  for (int64_t i = 0; i < count; ++i) {
-    const double inner_est = 12.0;  // typical inner iterations per outer iteration
-    wgt[i] = (double)ents[i].n * ents[i].d + inner_est * (double)ents[i].m * ents[i].d;
-    total += wgt[i];
-  }
-  std::vector<int64_t> order(count);
-  for (int64_t i = 0; i < count; ++i) order[i] = i;
-  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return wgt[x] > wgt[y]; });
-  std::vector<int> team0(count, 0), tsize(count, 1);
-  std::vector<std::vector<int>> items(G);
-  const double per_wg = total / G;
-  int next = 0;  // next free workgroup for dedicated teams
-  int64_t first_small = count;
-  for (int64_t oi = 0; oi < count; ++oi) {
-    const int64_t i = order[oi];
-    const int want = (int)std::floor(wgt[i] / per_wg);
-    if (want >= 2 && next + want <= G - 1) {
-      team0[i] = next;
-      tsize[i] = want;
-      for (int t = 0; t < want; ++t) items[next + t].push_back((int)i);
-      next += want;
-    } else {
-      first_small = oi;
-      break;
-    }
-  }
-  // remaining entries: greedy bin packing over the free workgroups
-  std::vector<double> load(G, 0.0);
-  for (int64_t oi = first_small; oi < count; ++oi) {
-    const int64_t i = order[oi];
-    int best = next;
-    for (int g = next; g < G; ++g)
-      if (load[g] < load[best]) best = g;
-    if (next >= G) return MIHS_ERR_UNSUPPORTED;
-    team0[i] = best;
-    tsize[i] = 1;
-    items[best].push_back((int)i);
-    load[best] += wgt[i];
-  }
-  size_t stride = 1;
-  for (int g = 0; g < G; ++g) stride = std::max(stride, items[g].size() + 1);
-
-  // ---- workspace: entries, items, per-entry scratch, barrier lines, error flag
+  Schedule S;
+  int rc = make_schedule(ents, count, G, &S);
+  if (rc) return rc;
+  const BlockLayout L = block_layout(ents, count, S, G);
+  if (!ws || L.total > ws_bytes) return MIHS_ERR_WORKSPACE;
   char* base = (char*)ws;
-  size_t off = 0;
-  const size_t ent_off = off;
-  off = align_up(off + (size_t)count * sizeof(BatchEntry), 256);
-  const size_t item_off = off;
-  off = align_up(off + (size_t)G * stride * sizeof(int), 256);
-  std::vector<size_t> work_off(count);
-  for (int64_t i = 0; i < count; ++i) {
-    work_off[i] = off;
-    off = align_up(off + entry_layout(dp_for(ents[i].d), tsize[i]).total * sizeof(double), 256);
+
+  // ---- Gram matrices of the distinct sketches
+  const std::vector<int64_t> lead = group_leaders(ents, count);
+  std::vector<GramJob> jobs;
+  jobs.reserve(L.njobs);
+  for (size_t g = 0; g < lead.size(); ++g) {
+    const BlockEntryDesc& s = ents[lead[g]];
+    const int dp = dp_for(s.d);
+    const int nb = dp / 64;
+    for (int bi = 0; bi < nb; ++bi)
+      for (int bj = bi; bj < nb; ++bj) {
+        GramJob j;
+        j.M = s.SA;
+        j.m = s.m;
+        j.ld = s.ldsa;
+        j.H = (double*)(base + L.h_off[g]);
+        j.ldh = dp;
+        j.d = (int)s.d;
+        j.bi = bi;
+        j.bj = bj;
+        jobs.push_back(j);
+      }
   }
-  const size_t bar_off = off;
-  off = align_up(off + (size_t)(count + 2) * 128, 256);
-  if (!ws || off > ws_bytes) return MIHS_ERR_WORKSPACE;
 
   std::vector<BatchEntry> host(count);
   for (int64_t i = 0; i < count; ++i) {
     const BlockEntryDesc& s = ents[i];
     BatchEntry& e = host[i];
+    size_t g = 0;
+    while (ents[lead[g]].sa_group != s.sa_group) ++g;
     e.A = s.A;
     e.n = s.n;
     e.lda = s.lda;
@@ -632,51 +911,66 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
     e.ldbc = s.ldbc;
     e.RHS = s.RHS;
     e.ldr = s.ldr;
-    e.SA = s.SA;
-    e.m = s.m;
-    e.ldsa = s.ldsa;
+    e.H = (const double*)(base + L.h_off[g]);
+    e.ldh = dp_for(s.d);
     e.X = s.X;
     e.ldx = s.ldx;
     e.lam = s.lam;
     e.alpha = s.alpha;
     e.beta = s.beta;
     e.info = s.info;
-    e.work = (double*)(base + work_off[i]);
-    e.bar = (unsigned*)(base + bar_off + (size_t)(i + 1) * 128);
+    e.work = (double*)(base + L.work_off[i]);
+    e.bar = (unsigned*)(base + L.bar_off + (size_t)(2 * i + 1) * 128);
+    e.bar_cg = (unsigned*)(base + L.bar_off + (size_t)(2 * i + 2) * 128);
     e.d = (int)s.d;
     e.dp = dp_for(s.d);
     e.ncols = s.ncols;
-    e.team0 = team0[i];
-    e.tsize = tsize[i];
+    e.team0 = S.team0[i];
+    e.tsize = S.tsize[i];
+    e.tcg = S.tcg[i];
   }
-  std::vector<int> hitems((size_t)G * stride, -1);
+  std::vector<int> hitems((size_t)G * S.stride, -1);
   for (int g = 0; g < G; ++g)
-    for (size_t k = 0; k < items[g].size(); ++k) hitems[(size_t)g * stride + k] = items[g][k];
+    for (size_t k = 0; k < S.items[g].size(); ++k) hitems[(size_t)g * S.stride + k] = S.items[g][k];
 
-  if (hipMemcpyAsync(base + ent_off, host.data(), (size_t)count * sizeof(BatchEntry),
+  if (hipMemcpyAsync(base + L.ent_off, host.data(), (size_t)count * sizeof(BatchEntry),
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return MIHS_ERR_HIP;
-  if (hipMemcpyAsync(base + item_off, hitems.data(), hitems.size() * sizeof(int),
+  if (hipMemcpyAsync(base + L.item_off, hitems.data(), hitems.size() * sizeof(int),
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return MIHS_ERR_HIP;
-  if (hipMemsetAsync(base + bar_off, 0, (size_t)(count + 2) * 128, st) != hipSuccess)
+  if (hipMemcpyAsync(base + L.gram_off, jobs.data(), jobs.size() * sizeof(GramJob),
+                     hipMemcpyHostToDevice, st) != hipSuccess)
+    return MIHS_ERR_HIP;
+  if (hipMemsetAsync(base + L.bar_off, 0, (size_t)(2 * count + 2) * 128, st) != hipSuccess)
     return MIHS_ERR_HIP;
   // the host tables above are freed when this function returns
   if (hipStreamSynchronize(st) != hipSuccess) return MIHS_ERR_HIP;
 
+  if (!jobs.empty()) {
+    if (sa_f32)
+      gram_kernel<float><<<dim3((unsigned)jobs.size()), dim3(kBlock), 0, st>>>(
+          (const GramJob*)(base + L.gram_off));
+    else
+      gram_kernel<double><<<dim3((unsigned)jobs.size()), dim3(kBlock), 0, st>>>(
+          (const GramJob*)(base + L.gram_off));
+    if (hipGetLastError() != hipSuccess) return MIHS_ERR_HIP;
+  }
+
   BatchArgs a;
-  a.entries = (const BatchEntry*)(base + ent_off);
-  a.wg_items = (const int*)(base + item_off);
-  a.items_stride = (int)stride;
-  a.err = (int*)(base + bar_off);
+  a.entries = (const BatchEntry*)(base + L.ent_off);
+  a.wg_items = (const int*)(base + L.item_off);
+  a.items_stride = (int)S.stride;
+  a.err = (int*)(base + L.bar_off);
   a.a_f32 = a_f32;
-  a.sa_f32 = sa_f32;
   a.eps_sub = eps_sub;
   a.tol = tol;
   a.max_outer = max_outer;
   a.max_inner = max_inner;
   a.spin.limit = 1L << 26;
   a.spin.sleep = 1;
+  a.spin_idle.limit = 1L << 24;
+  a.spin_idle.sleep = 16;
   void* args[] = {&a};
   if (hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(kBlock), args, shmem, st) !=
       hipSuccess)

@@ -66,9 +66,10 @@ struct BlockEntryDesc {
   const double* beta;
   mihs_info_t* info;  // device, ncols records
   int ncols;          // 1..16
+  int64_t sa_group;   // entries with equal sa_group share SA (and its Gram matrix)
 };
 int block_max_d();
-size_t block_workspace_bytes(const BlockEntryDesc* ents, int64_t count, int num_cu);
+size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count);
 int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
                  int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
                  void* ws, size_t ws_bytes, hipStream_t stream);

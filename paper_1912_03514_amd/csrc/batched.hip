@@ -622,72 +622,6 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
   }
 }
 
-// ---- Gram matrices H = M^T M (dp x dp, FP64) on the matrix cores ----------
-struct GramJob {
-  const void* M;
-  int64_t m, ld;
-  double* H;
-  int64_t ldh;
-  int d, bi, bj;
-};
-
-constexpr int kGramRows = 32;
-
-// One 64 x 64 block (bi <= bj) per workgroup: wave w owns rows 16 w.. of the
-// block and all four 16-column blocks; 32-row chunks of M staged in LDS.
-// Off-diagonal blocks are mirrored so H is exactly symmetric.
-template <typename TS>
-__global__ __launch_bounds__(kBlock) void gram_kernel(const GramJob* jobs) {
-  const GramJob J = jobs[blockIdx.x];
-  __shared__ double ti[kGramRows][64 + 1];
-  __shared__ double tj[kGramRows][64 + 1];
-  const TS* M = (const TS*)J.M;
-  const int lane = lane_id(), wave = wave_id();
-  const int ci0 = J.bi * 64, cj0 = J.bj * 64;
-  f64x4 acc[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  for (int64_t r0 = 0; r0 < J.m; r0 += kGramRows) {
-    double vi[kGramRows * 64 / kBlock], vj[kGramRows * 64 / kBlock];
-#pragma unroll
-    for (int i = 0; i < kGramRows * 64 / kBlock; ++i) {
-      const int e = i * kBlock + (int)threadIdx.x;
-      const int r = e / 64, c = e % 64;
-      const int64_t gr = r0 + r;
-      const bool rok = gr < J.m;
-      vi[i] = (rok && ci0 + c < J.d) ? (double)M[gr * J.ld + ci0 + c] : 0.0;
-      vj[i] = (rok && cj0 + c < J.d) ? (double)M[gr * J.ld + cj0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kGramRows * 64 / kBlock; ++i) {
-      const int e = i * kBlock + (int)threadIdx.x;
-      ti[e / 64][e % 64] = vi[i];
-      tj[e / 64][e % 64] = vj[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < kGramRows / 4; ++s) {
-      const int r = 4 * s + (lane >> 4);
-      const double av = ti[r][wave * 16 + (lane & 15)];
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, tj[r][b * 16 + (lane & 15)], acc[b],
-                                                      0, 0, 0);
-    }
-  }
-  // result register r of lane l: row l/16 + 4 r, column l % 16
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t i = ci0 + wave * 16 + (lane >> 4) + 4 * r;
-      const int64_t j = cj0 + b * 16 + (lane & 15);
-      J.H[i * J.ldh + j] = acc[b][r];
-      if (J.bi != J.bj) J.H[j * J.ldh + i] = acc[b][r];
-    }
-}
-
 typedef void (*BatchKernel)(BatchArgs);
 
 BatchKernel pick(int dp) {
@@ -948,13 +882,8 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
   if (hipStreamSynchronize(st) != hipSuccess) return MIHS_ERR_HIP;
 
   if (!jobs.empty()) {
-    if (sa_f32)
-      gram_kernel<float><<<dim3((unsigned)jobs.size()), dim3(kBlock), 0, st>>>(
-          (const GramJob*)(base + L.gram_off));
-    else
-      gram_kernel<double><<<dim3((unsigned)jobs.size()), dim3(kBlock), 0, st>>>(
-          (const GramJob*)(base + L.gram_off));
-    if (hipGetLastError() != hipSuccess) return MIHS_ERR_HIP;
+    rc = launch_gram_jobs((const GramJob*)(base + L.gram_off), (int64_t)jobs.size(), sa_f32, st);
+    if (rc) return rc;
   }
 
   BatchArgs a;

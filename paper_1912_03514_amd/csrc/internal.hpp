@@ -74,6 +74,21 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
                  int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
                  void* ws, size_t ws_bytes, hipStream_t stream);
 
+// ---- Gram matrices H = M^T M (FP64 accumulation on the matrix cores) --------
+// One 64 x 64 block (bi <= bj) of one matrix per job; H is dp x dp with the
+// entries of index >= d set to zero.
+struct GramJob {
+  const void* M;
+  int64_t m, ld;
+  double* H;
+  int64_t ldh;
+  int d, bi, bj;
+};
+int launch_gram_jobs(const GramJob* d_jobs, int64_t njobs, int m_f32, hipStream_t stream);
+// H (ldh >= 64 * ceil(d / 64), FP64 or FP32) = M^T M for M m x d (FP64 or FP32).
+int launch_gram(const void* M, int m_f32, int64_t m, int64_t d, int64_t ld, void* H, int h_f32,
+                int64_t ldh, hipStream_t stream);
+
 // ---- dense helper kernels --------------------------------------------------
 // Y (n x k, row stride ldy) = A (n x d) W (d x k row-major); FP64 accumulation.
 int launch_apply_rows(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,

@@ -63,14 +63,19 @@ struct SolveArgs {
   unsigned* bar_cg;   // 1 line
   int* err;
   int* status;        // decision published by the CG group
+  const void* H;      // Gram matrix (SA)^T SA (TS), dpad x dpad, when the CG uses it
+  int64_t ldh;
   int d, dpad, G, Gc, cpw;
   BarrierSpin spin_fast, spin_idle;
 };
 
+// Rows loaded per wave step: enough bytes in flight for short rows, one row
+// when the row buffer and the EPT accumulators already fill the registers.
 template <typename TM, int EPT>
 struct RowsInFlight {
   static constexpr int kBytes = EPT * (int)sizeof(TM);   // bytes per lane per row
-  static constexpr int value = kBytes >= 512 ? 1 : (kBytes >= 256 ? 2 : 4);
+  static constexpr int value =
+      (kBytes >= 512 || (EPT >= 32 && sizeof(TM) < 8)) ? 1 : (kBytes >= 256 ? 2 : 4);
 };
 
 // One pass over rows [r0, r1) of M: for each row, u = c_row - M_row . v and
@@ -214,7 +219,48 @@ __device__ __forceinline__ void owned_column_sums(const T* __restrict__ P, int K
   }
 }
 
-template <typename TA, typename TS, typename TV, int EPT>
+// out[c - r0] = H[c, :] . v for rows c in [r0, r1) (one row per wave at a time,
+// two when rows are short), in a fixed order.
+template <typename TH, typename TV, int EPT>
+__device__ __forceinline__ void rowdots(const TH* __restrict__ H, int64_t ldh, int r0, int r1,
+                                        int d, const TV* __restrict__ v, double* out) {
+  using L = RowLayout<TH, EPT>;
+  constexpr int R = EPT <= 16 ? 2 : 1;
+  const int lane = lane_id();
+  for (int c = r0 + wave_id() * R; c < r1; c += kWavesPerBlock * R) {
+    TH rv[R][EPT];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      if (c + t < r1) {
+        load_row<TH, EPT, false>(H + (int64_t)(c + t) * ldh, d, lane, rv[t]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) rv[t][e] = TH(0);
+      }
+    }
+    TV dot[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) dot[t] = TV(0);
+#pragma unroll
+    for (int j = 0; j < L::J; ++j) {
+#pragma unroll
+      for (int vv = 0; vv < L::V; ++vv) {
+        const TV xv = v[L::col(j, lane, vv)];
+#pragma unroll
+        for (int t = 0; t < R; ++t) dot[t] += (TV)rv[t][j * L::V + vv] * xv;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const TV sdot = wave_sum(dot[t]);
+      if (lane == 0 && c + t < r1) out[c + t - r0] = (double)sdot;
+    }
+  }
+}
+
+// GRAM: the inner CG applies (SA)^T SA through the precomputed H (owners form
+// their entries of q directly); otherwise through two passes over SA rows.
+template <typename TA, typename TS, typename TV, int EPT, bool GRAM>
 __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   extern __shared__ double smem[];
   const int cpw = a.cpw;
@@ -345,44 +391,76 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           }
           for (int c = NPT * kBlock + threadIdx.x; c < a.dpad; c += kBlock) vp[c] = TV(0);
           __syncthreads();
-          TV ssq = TV(0);
-          {
-            TV acc[EPT];
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) acc[e] = TV(0);
-            rowpass<TS, TV, EPT, false, RS>(SA, a.ldsa, s_r0, s_r1, d, vp, nullptr, acc, ssq);
-            wg_store_partial<TS, TV, EPT>(acc, (TV*)rbuf, partS + (int64_t)w * a.dpad, d);
-            ssq = wg_sum_ssq(ssq, s_red);
-          }
-          double pp = 0.0;
-          for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock) pp += (double)vp[c] * (double)vp[c];
-          pp = block_sum(pp, s_red);
-          if (threadIdx.x == 0) {
-            scal_w[1] = pp;
-            scal_w[2] = (double)ssq;
-          }
-          if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
-
-          // ---- C2: step length (p^T q = ||u||^2 + lambda ||p||^2) and owner updates
-          owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
-          double ppn, uu;
-          sum2_slots(a.scal, Gc, 1, 2, s_red, ppn, uu);
-          const double pq = uu + a.lam * ppn;
-          const double acg = rr / pq;
-          if (!(pq > 0.0) || !isfinite(acg)) {
-            decision = 2;
-            break;
-          }
           double rpart = 0.0;
-          const TV at = (TV)acg, lt = (TV)a.lam;
-          for (int i = threadIdx.x; i < nown; i += kBlock) {
-            const TV pc = vp[c_lo + i];
-            const TV q = (TV)(-colbuf[i]) + lt * pc;
-            own_z[i] = own_z[i] + at * pc;
-            const TV rn = own_r[i] - at * q;
-            own_r[i] = rn;
-            r[c_lo + i] = rn;
-            rpart += (double)rn * (double)rn;
+          if (GRAM) {
+            // q = H p + lambda p on the owned columns (colbuf <- H p)
+            rowdots<TS, TV, EPT>((const TS*)a.H, a.ldh, c_lo, c_hi, d, vp, colbuf);
+            __syncthreads();
+            double pq = 0.0;
+            for (int i = threadIdx.x; i < nown; i += kBlock) {
+              const double pc = (double)vp[c_lo + i];
+              pq += pc * (colbuf[i] + a.lam * pc);
+            }
+            pq = block_sum(pq, s_red);
+            if (threadIdx.x == 0) scal_w[1] = pq;
+            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            double pqs, unused2;
+            sum2_slots(a.scal, Gc, 1, 1, s_red, pqs, unused2);
+            const double acg = rr / pqs;
+            if (!(pqs > 0.0) || !isfinite(acg)) {
+              decision = 2;
+              break;
+            }
+            const TV at = (TV)acg, lt = (TV)a.lam;
+            for (int i = threadIdx.x; i < nown; i += kBlock) {
+              const TV pc = vp[c_lo + i];
+              const TV q = (TV)colbuf[i] + lt * pc;
+              own_z[i] = own_z[i] + at * pc;
+              const TV rn = own_r[i] - at * q;
+              own_r[i] = rn;
+              r[c_lo + i] = rn;
+              rpart += (double)rn * (double)rn;
+            }
+          } else {
+            TV ssq = TV(0);
+            {
+              TV acc[EPT];
+#pragma unroll
+              for (int e = 0; e < EPT; ++e) acc[e] = TV(0);
+              rowpass<TS, TV, EPT, false, RS>(SA, a.ldsa, s_r0, s_r1, d, vp, nullptr, acc, ssq);
+              wg_store_partial<TS, TV, EPT>(acc, (TV*)rbuf, partS + (int64_t)w * a.dpad, d);
+              ssq = wg_sum_ssq(ssq, s_red);
+            }
+            double pp = 0.0;
+            for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock)
+              pp += (double)vp[c] * (double)vp[c];
+            pp = block_sum(pp, s_red);
+            if (threadIdx.x == 0) {
+              scal_w[1] = pp;
+              scal_w[2] = (double)ssq;
+            }
+            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+
+            // ---- C2: step length (p^T q = ||u||^2 + lambda ||p||^2) and owner updates
+            owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
+            double ppn, uu;
+            sum2_slots(a.scal, Gc, 1, 2, s_red, ppn, uu);
+            const double pq = uu + a.lam * ppn;
+            const double acg = rr / pq;
+            if (!(pq > 0.0) || !isfinite(acg)) {
+              decision = 2;
+              break;
+            }
+            const TV at = (TV)acg, lt = (TV)a.lam;
+            for (int i = threadIdx.x; i < nown; i += kBlock) {
+              const TV pc = vp[c_lo + i];
+              const TV q = (TV)(-colbuf[i]) + lt * pc;
+              own_z[i] = own_z[i] + at * pc;
+              const TV rn = own_r[i] - at * q;
+              own_r[i] = rn;
+              r[c_lo + i] = rn;
+              rpart += (double)rn * (double)rn;
+            }
           }
           rpart = block_sum(rpart, s_red);
           if (threadIdx.x == 0) scal_w[3] = rpart;
@@ -460,29 +538,33 @@ __global__ void zero_words(unsigned* p, int count) {
 
 typedef void (*SolveKernel)(SolveArgs);
 
-template <typename TA, typename TS, typename TV>
+template <typename TA, typename TS, typename TV, bool GRAM>
 SolveKernel pick_by_ept(int ept) {
   switch (ept) {
-    case 1: return solve_kernel<TA, TS, TV, 1>;
-    case 2: return solve_kernel<TA, TS, TV, 2>;
-    case 4: return solve_kernel<TA, TS, TV, 4>;
-    case 8: return solve_kernel<TA, TS, TV, 8>;
-    case 16: return solve_kernel<TA, TS, TV, 16>;
-    case 32: return solve_kernel<TA, TS, TV, 32>;
-    case 64: return solve_kernel<TA, TS, TV, 64>;
+    case 1: return solve_kernel<TA, TS, TV, 1, GRAM>;
+    case 2: return solve_kernel<TA, TS, TV, 2, GRAM>;
+    case 4: return solve_kernel<TA, TS, TV, 4, GRAM>;
+    case 8: return solve_kernel<TA, TS, TV, 8, GRAM>;
+    case 16: return solve_kernel<TA, TS, TV, 16, GRAM>;
+    case 32: return solve_kernel<TA, TS, TV, 32, GRAM>;
+    case 64: return solve_kernel<TA, TS, TV, 64, GRAM>;
     default: return nullptr;
   }
 }
 
+template <bool GRAM>
 SolveKernel pick_kernel(int a_f32, int mixed, int ept) {
-  if (!a_f32 && !mixed) return pick_by_ept<double, double, double>(ept);
-  if (!a_f32 && mixed) return pick_by_ept<double, float, float>(ept);
-  if (a_f32 && !mixed) return pick_by_ept<float, double, double>(ept);
-  return pick_by_ept<float, float, float>(ept);
+  if (!a_f32 && !mixed) return pick_by_ept<double, double, double, GRAM>(ept);
+  if (!a_f32 && mixed) return pick_by_ept<double, float, float, GRAM>(ept);
+  if (a_f32 && !mixed) return pick_by_ept<float, double, double, GRAM>(ept);
+  return pick_by_ept<float, float, float, GRAM>(ept);
 }
 
+// The CG goes through the Gram matrix when it is no larger than SA (m >= d).
+bool use_gram(int64_t m, int64_t d) { return m >= d; }
+
 struct SolveLayout {
-  size_t partA, partS, scal, vecs, xp, bar, total;
+  size_t partA, partS, scal, vecs, xp, bar, gram, total;
 };
 
 // Barrier region: line 0 = top counter of the all-workgroup barrier, lines 1-8
@@ -490,7 +572,8 @@ struct SolveLayout {
 // line 11 = status word (128-byte lines).
 constexpr size_t kBarLines = 12;
 
-SolveLayout layout(int G, int Gc, int64_t dpad) {
+// gram_bytes: size of the Gram matrix region (0 when the CG streams SA).
+SolveLayout layout(int G, int Gc, int64_t dpad, size_t gram_bytes) {
   SolveLayout L;
   size_t off = 0;
   L.partA = off; off = align_up(off + (size_t)G * dpad * 8, 256);
@@ -499,8 +582,15 @@ SolveLayout layout(int G, int Gc, int64_t dpad) {
   L.vecs = off;  off = align_up(off + 4 * (size_t)dpad * 8, 256);
   L.xp = off;    off = align_up(off + (size_t)dpad * 8, 256);
   L.bar = off;   off = align_up(off + kBarLines * 128, 256);
+  L.gram = off;  off = align_up(off + gram_bytes, 256);
   L.total = off;
   return L;
+}
+
+size_t gram_bytes_for(int64_t m, int64_t d, int mixed) {
+  if (!use_gram(m, d)) return 0;
+  const size_t dp = (size_t)dpad_for(d);
+  return dp * dp * (mixed ? sizeof(float) : sizeof(double));
 }
 
 int max_grid(const mihs_handle* h) { return h->num_cu * kMaxBlocksPerCU; }
@@ -514,8 +604,9 @@ int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G) {
   if (env && atoi(env) > 0) {
     gc = atoi(env);
   } else {
-    const double mb = (double)m * (double)d * sa_bytes / (1024.0 * 1024.0);
-    gc = mb >= 4.0 ? 64 : (mb >= 1.0 ? 32 : 16);
+    // bytes one CG step streams: the Gram matrix (m >= d) or SA
+    const double mb = (double)(m >= d ? d : m) * (double)d * sa_bytes / (1024.0 * 1024.0);
+    gc = mb >= 64.0 ? 128 : (mb >= 4.0 ? 64 : (mb >= 1.0 ? 32 : 16));
     // each CG workgroup should own at least a few rows
     const int64_t by_rows = (m + 3) / 4;
     if (gc > by_rows) gc = (int)(by_rows < 1 ? 1 : by_rows);
@@ -535,17 +626,17 @@ int ept_for(int64_t d) {
 
 size_t solve_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int mixed) {
   (void)n;
-  (void)m;
-  (void)mixed;
   const int G = max_grid(h);
-  return layout(G, G, dpad_for(d)).total;
+  return layout(G, G, dpad_for(d), gram_bytes_for(m, d, mixed)).total;
 }
 
 int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_bytes,
                  hipStream_t stream) {
   const int ept = ept_for(s.d);
   if (ept > 64) return MIHS_ERR_UNSUPPORTED;
-  SolveKernel kern = pick_kernel(s.a_f32, s.mixed, ept);
+  const bool gram = use_gram(s.m, s.d);
+  SolveKernel kern = gram ? pick_kernel<true>(s.a_f32, s.mixed, ept)
+                          : pick_kernel<false>(s.a_f32, s.mixed, ept);
   if (!kern) return MIHS_ERR_UNSUPPORTED;
   const int64_t dpad = dpad_for(s.d);
   // Pick the grid: try two workgroups per CU, then one; the inner-solve group
@@ -575,7 +666,7 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
     }
   }
   if (G == 0) return MIHS_ERR_UNSUPPORTED;
-  const SolveLayout L = layout(G, Gc, dpad);
+  const SolveLayout L = layout(G, Gc, dpad, gram_bytes_for(s.m, s.d, s.mixed));
   if (ws_bytes < L.total || ws == nullptr) return MIHS_ERR_WORKSPACE;
 
   char* base = (char*)ws;
@@ -622,6 +713,13 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   a.spin_fast.sleep = 1;
   a.spin_idle.limit = 1L << 24;  // ~1000-clock polls while the inner solve runs
   a.spin_idle.sleep = 16;
+  a.H = gram ? (const void*)(base + L.gram) : nullptr;
+  a.ldh = dpad;
+  if (gram) {
+    const int rc = launch_gram(s.SA, s.mixed, s.m, s.d, s.ldsa, base + L.gram, s.mixed, dpad,
+                               stream);
+    if (rc) return rc;
+  }
 
   hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, stream, bar, (int)(kBarLines * 32));
   if (hipGetLastError() != hipSuccess) return MIHS_ERR_HIP;

@@ -39,10 +39,18 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="srht_2p18x2048")
-    ap.add_argument("--tol", type=float, default=5e-11)
+    ap.add_argument("--tol", type=float, default=None,
+                    help="relative-step stop tolerance (default: per workload, chosen so "
+                         "that the result is within 1e-10 of x*)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 15)
     return ap.parse_args()
+
+
+# Stop-rule tolerance per workload: the relative-step rule estimates the error
+# from the Corollary 4 rate sqrt(beta); where the observed rate is slower (the
+# two-stage sketch of the ill-conditioned FP32 workload) the tolerance is tighter.
+DEFAULT_TOL = {"count_2p20x4096": 2e-12}
 
 
 def log(msg):
@@ -134,7 +142,7 @@ def cpu_baseline(w, lam, rows):
     P = W.make_problem(rows, w.d, w.sigma, w.sd_target, w.data_seed + 1)
     t0 = time.perf_counter()
     SA = sketches.sketch(P.A, w.sketch, w.m, w.sketch_seed, w.m2)
-    a, b = O.momentum_cor4(w.sd_target, w.m)
+    a, b = O.momentum_cor4(w.sd_target, w.m_out)
     r = O.mihs(P.A, P.b, lam, SA, a, b, inner="cg", eps_sub=w.eps_sub, tol=1e-10)
     dt = time.perf_counter() - t0
     scale = w.n / rows
@@ -254,7 +262,7 @@ def run_diff(args):
     g = torch.Generator(device=dev).manual_seed(w.data_seed + 1)
     C = torch.randn(128, w.d, generator=g, dtype=torch.float64, device=dev)
     Y = torch.randn(128, w.nrhs, generator=g, dtype=torch.float64, device=dev)
-    alpha, beta = mihs.momentum(w.sd_target, w.m)
+    alpha, beta = mihs.momentum(w.sd_target, w.m_out)
     kw = dict(eps_sub=w.eps_sub, tol=1e-12, max_outer=300)
     ll0 = math.log(lam)
 
@@ -300,7 +308,7 @@ def run_small(args):
     w = W.workload("small_gauss")
     P = w.draw()
     A, b = torch.from_numpy(P.A).to(dev), torch.from_numpy(P.b).to(dev)
-    alpha, beta = mihs.momentum(w.sd_target, w.m)
+    alpha, beta = mihs.momentum(w.sd_target, w.m_out)
     ws = mihs.SolveWorkspace(w.n, w.d, w.m, "plain", dev)
 
     def step():
@@ -325,6 +333,8 @@ def run_small(args):
 
 def main():
     args = parse()
+    if args.tol is None:
+        args.tol = DEFAULT_TOL.get(args.workload, 5e-11)
     if args.workload in ("batched_lambda_path", "diff_2p18x1024", "small_gauss"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -353,7 +363,7 @@ def main():
     dev = torch.device("cuda", 0)
     w = W.workload(args.workload)
     lam = w.lam
-    alpha, beta = mihs.momentum(w.sd_target, w.m)
+    alpha, beta = mihs.momentum(w.sd_target, w.m_out)
 
     log(f"drawing {w.name}: n={w.n} d={w.d} ({w.a_dtype}) on the GPU")
     A, b, _x0, _ = W.make_problem_torch(w.n, w.d, w.sigma, w.sd_target, w.data_seed, dev,
@@ -413,10 +423,12 @@ def main():
     info = mx["infos"][-1]
     s_a = 8 if w.a_dtype == "f64" else 4
     apass_bytes = w.n * w.d * s_a + w.n * 8
-    sa_bytes = w.m * w.d * 4  # mixed: FP32 sketch
+    # one CG step streams the operator once: the Gram matrix (d x d) when the
+    # sketch has at least d rows, else SA; FP32 in the mixed path
+    cg_bytes = min(w.m_out, w.d) * w.d * 4
     outer = info["outer_iters"]
     inner = info["inner_iters_total"]
-    solve_bytes = outer * apass_bytes + inner * sa_bytes
+    solve_bytes = outer * apass_bytes + inner * cg_bytes
     achieved = solve_bytes / (mx["solve_ms"] * 1e-3) / 1e9
     result = {
         "metric": f"time-to-1e-10 rel.err per ridge solve (M-IHS, mixed precision; {w.sketch} sketch + solve)",

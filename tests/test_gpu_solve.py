@@ -28,7 +28,7 @@ def test_small_workload_plain_reaches_1e_10():
     w = W.workload("small_gauss")
     P = w.draw()
     SA = sketches.gaussian_sketch(P.A, w.m, w.sketch_seed)
-    a, b = O.momentum_cor4(w.sd_target, w.m)
+    a, b = O.momentum_cor4(w.sd_target, w.m_out)
     xs = O.ridge_lstsq(P.A, P.b, P.lam)
     ref = O.mihs(P.A, P.b, P.lam, SA, a, b, inner="cg", eps_sub=w.eps_sub, tol=1e-10)
     announce("small_gauss plain solve, oracle SA")
@@ -91,6 +91,29 @@ def test_fp32_matrix_and_mixed_inner():
                                   precision=prec)
         assert info["status"] == 0, (prec, info)
         assert rel(x.cpu().numpy(), xs) <= 1e-10, prec
+
+
+@pytest.mark.parametrize("m", [120, 128, 200])
+@pytest.mark.parametrize("prec", ["plain", "mixed"])
+def test_cg_operator_paths(m, prec):
+    """The inner CG applies (SA)^T SA by streaming SA (m < d) or through the Gram
+    matrix (m >= d): both follow the oracle's trajectory for N fixed steps."""
+    mihs = _mihs()
+    d = 128
+    P = _problem(2600, d, 25.0, seed=33)
+    SA = sketches.gaussian_sketch(P.A, m, 6)
+    a, b = O.momentum_cor4(25.0, m)
+    N = 5
+    ref = O.mihs(P.A, P.b, P.lam, SA, a, b, inner="cg", eps_sub=1e-12 if prec == "plain" else 1e-4,
+                 n_iter=N, max_inner=5000)
+    sa = SA if prec == "plain" else SA.astype(np.float32)
+    announce(f"cg operator path m={m} d={d} {prec}")
+    x, info = mihs.mihs_solve(to_dev(P.A), to_dev(P.b), P.lam, to_dev(sa), a, b,
+                              eps_sub=1e-12 if prec == "plain" else 1e-4, tol=0.0, max_outer=N,
+                              max_inner=5000, precision=prec)
+    assert info["outer_iters"] == N
+    # FP32 CG: each inner solve is accurate to about its tolerance, not to rounding
+    assert rel(x.cpu().numpy(), ref.x) <= (1e-11 if prec == "plain" else 1e-4)
 
 
 def test_warm_start_and_momentum_state():

@@ -78,7 +78,7 @@ def test_rate_matches_characteristic_polynomial():
     w = W.workload("small_gauss")
     P = w.draw()
     SA = sketches.gaussian_sketch(P.A, w.m, w.sketch_seed)
-    a, b = O.momentum_cor4(w.sd_target, w.m)
+    a, b = O.momentum_cor4(w.sd_target, w.m_out)
     xs = O.ridge_lstsq(P.A, P.b, P.lam)
     r = O.mihs(P.A, P.b, P.lam, SA, a, b, inner="exact", n_iter=40, keep_history=True)
     errs = np.array([np.linalg.norm(x - xs) for x in r.history])
@@ -130,7 +130,7 @@ def test_mihs_small_workload_reaches_1e_10(inner):
     w = W.workload("small_gauss")
     P = w.draw()
     SA = sketches.gaussian_sketch(P.A, w.m, w.sketch_seed)
-    a, b = O.momentum_cor4(w.sd_target, w.m)
+    a, b = O.momentum_cor4(w.sd_target, w.m_out)
     xs = O.ridge_lstsq(P.A, P.b, P.lam)
     r = O.mihs(P.A, P.b, P.lam, SA, a, b, inner=inner, eps_sub=w.eps_sub, tol=1e-10)
     assert r.converged

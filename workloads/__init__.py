@@ -162,6 +162,11 @@ class Workload:
     def lam(self) -> float:
         return lambda_for_sd(self.sigma, self.sd_target)
 
+    @property
+    def m_out(self) -> int:
+        """Rows of the sketch the solver sees (the second stage's, when there is one)."""
+        return self.m2 if self.m2 else self.m
+
     def draw(self, n: Optional[int] = None) -> Problem:
         return make_problem(n or self.n, self.d, self.sigma, self.sd_target, self.data_seed,
                             np.float64 if self.a_dtype == "f64" else np.float32, self.nrhs)

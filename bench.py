@@ -44,8 +44,17 @@ def parse():
                          "that the result is within 1e-10 of x*)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 15)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (the reference "
+                         "kernel for scaling HBM byte counters) and exit")
     return ap.parse_args()
 
+
+# HBM bytes per launch of the persistent solve kernel, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE, each scaled by what the counter reads for a
+# plain 1 GiB device copy: x2.000 for FETCH_SIZE, x1.000 for WRITE_SIZE); see
+# profiles/solve_kernel_srht_2p18x2048.md.  Valid for the kernel as profiled.
+MEASURED_TRAFFIC = {("srht_2p18x2048", "mixed"): 155.27e9}
 
 # Stop-rule tolerance per workload: the relative-step rule estimates the error
 # from the Corollary 4 rate sqrt(beta); where the observed rate is slower (the
@@ -331,8 +340,23 @@ def run_small(args):
     }
 
 
+def copy_calibration():
+    """A plain copy of known size: 1 GiB read + 1 GiB written per call."""
+    import torch
+    n = 1 << 27  # doubles
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "calls": 3}))
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.tol is None:
         args.tol = DEFAULT_TOL.get(args.workload, 5e-11)
     if args.workload in ("batched_lambda_path", "diff_2p18x1024", "small_gauss"):
@@ -405,6 +429,25 @@ def main():
             del SA
         return times, sk_ms, sv_ms, infos, xs
 
+    def solve_overhead_ms(precision):
+        """Time of mihs_solve with zero outer iterations (Gram matrix, barrier
+        reset, a kernel that returns at once): subtracted from the solve time to
+        get the persistent kernel's own duration."""
+        ws = mihs.SolveWorkspace(w.n, w.d, w.m, precision, dev)
+        SA = mihs.mihs_sketch(A, w.sketch, w.m, w.sketch_seed, precision=precision, m2=w.m2)
+        ts = []
+        for _ in range(4):
+            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            torch.cuda.synchronize()
+            e0.record(stream)
+            mihs.mihs_solve(A, b, lam, SA, alpha, beta, eps_sub=w.eps_sub, tol=args.tol,
+                            max_outer=0, max_inner=2000, precision=precision, workspace=ws,
+                            sync=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.mean(ts[1:]))
+
     out = {}
     for precision in ("mixed", "plain"):
         log(f"{precision}: warmup {args.warmup}")
@@ -414,7 +457,8 @@ def main():
         times, sk, sv, infos, xs = run(precision, args.steps, True)
         errs = [float(np.linalg.norm(x.cpu().numpy() - x_ref) / np.linalg.norm(x_ref)) for x in xs]
         out[precision] = dict(ms=float(np.mean(times)), sketch_ms=float(np.mean(sk)),
-                              solve_ms=float(np.mean(sv)), infos=infos, errs=errs)
+                              solve_ms=float(np.mean(sv)), infos=infos, errs=errs,
+                              overhead_ms=solve_overhead_ms(precision))
         log(f"  {precision}: {np.mean(times):.2f} ms/solve (sketch {np.mean(sk):.2f}, solve "
             f"{np.mean(sv):.2f}); outer {infos[-1]['outer_iters']}, inner "
             f"{infos[-1]['inner_iters_total']}; max err {max(errs):.2e}")
@@ -429,7 +473,9 @@ def main():
     outer = info["outer_iters"]
     inner = info["inner_iters_total"]
     solve_bytes = outer * apass_bytes + inner * cg_bytes
-    achieved = solve_bytes / (mx["solve_ms"] * 1e-3) / 1e9
+    kernel_ms = mx["solve_ms"] - mx["overhead_ms"]
+    achieved = solve_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = MEASURED_TRAFFIC.get((w.name, "mixed"))
     result = {
         "metric": f"time-to-1e-10 rel.err per ridge solve (M-IHS, mixed precision; {w.sketch} sketch + solve)",
         "value": round(mx["ms"], 3),
@@ -458,7 +504,11 @@ def main():
         "a_pass_bytes": apass_bytes,
         "roofline": {"bound": "hbm", "kernel": "solve_kernel (mixed)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": solve_bytes,
+                     "kernel_ms": round(kernel_ms, 3),
+                     "launch_overhead_ms": round(mx["overhead_ms"], 3)},
         "accuracy_ok": max(mx["errs"]) <= 1e-10 and max(pl["errs"]) <= 1e-10,
     }
     if not args.no_cpu_baseline:

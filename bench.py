@@ -59,7 +59,7 @@ MEASURED_TRAFFIC = {("srht_2p18x2048", "mixed"): 155.27e9}
 # Stop-rule tolerance per workload: the relative-step rule estimates the error
 # from the Corollary 4 rate sqrt(beta); where the observed rate is slower (the
 # two-stage sketch of the ill-conditioned FP32 workload) the tolerance is tighter.
-DEFAULT_TOL = {"count_2p20x4096": 2e-12}
+DEFAULT_TOL = {"count_2p20x4096": 2e-12, "batched_lambda_path": 1e-11}
 
 
 def log(msg):

@@ -32,3 +32,37 @@ def announce(msg):
     """Name the case before any GPU work, flushed, so a fault is attributable."""
     print(f"[gpu-case] {msg}", flush=True)
     sys.stdout.flush()
+
+
+def closed_form_refined(A, b, lam, refine=2, chunk=1 << 16):
+    """x* = (A^T A + lam I)^{-1} A^T b for device tensors too large for the host
+    oracle: FP64 Gram matrix and Cholesky with torch (rocBLAS/rocSOLVER, not the
+    library under test), then `refine` steps of iterative refinement whose
+    gradients A^T (b - A x) - lam x are accumulated on the host in long double.
+    Returns a host FP64 vector."""
+    n, d = A.shape
+    H = torch.zeros(d, d, dtype=torch.float64, device=A.device)
+    Atb = torch.zeros(d, dtype=torch.float64, device=A.device)
+    for r0 in range(0, n, chunk):
+        Ac = A[r0:r0 + chunk].double()
+        H += Ac.T @ Ac
+        Atb += Ac.T @ b[r0:r0 + chunk]
+        del Ac
+    H += lam * torch.eye(d, dtype=torch.float64, device=A.device)
+    L = torch.linalg.cholesky(H)
+    del H
+    x = torch.cholesky_solve(Atb[:, None], L)[:, 0]
+    rows = 1 << 14
+    for _ in range(refine):
+        r = torch.empty(n, dtype=torch.float64, device=A.device)
+        for r0 in range(0, n, chunk):
+            r[r0:r0 + chunk] = b[r0:r0 + chunk] - A[r0:r0 + chunk].double() @ x
+        rh = r.cpu().numpy().astype(np.longdouble)
+        atr = np.zeros(d, dtype=np.longdouble)
+        for r0 in range(0, n, rows):
+            Ac = A[r0:r0 + rows].cpu().numpy().astype(np.longdouble)
+            atr += Ac.T @ rh[r0:r0 + rows]
+        g = atr - np.longdouble(lam) * x.cpu().numpy().astype(np.longdouble)
+        x = x + torch.cholesky_solve(torch.from_numpy(g.astype(np.float64)).to(A.device)[:, None],
+                                     L)[:, 0]
+    return x.cpu().numpy()

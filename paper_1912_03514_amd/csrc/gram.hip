@@ -71,7 +71,10 @@ __device__ __forceinline__ void gram_block(const TS* __restrict__ M, int64_t m, 
 template <typename TS>
 __global__ __launch_bounds__(kBlock) void gram_jobs_kernel(const GramJob* jobs) {
   const GramJob J = jobs[blockIdx.x];
-  gram_block<TS, double>((const TS*)J.M, J.m, J.ld, J.d, J.H, J.ldh, J.bi, J.bj);
+  if (J.h_f32)
+    gram_block<TS, float>((const TS*)J.M, J.m, J.ld, J.d, (float*)J.H, J.ldh, J.bi, J.bj);
+  else
+    gram_block<TS, double>((const TS*)J.M, J.m, J.ld, J.d, (double*)J.H, J.ldh, J.bi, J.bj);
 }
 
 // One matrix, grid (nb, nb); blocks below the diagonal return at once.

@@ -76,13 +76,13 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
 
 // ---- Gram matrices H = M^T M (FP64 accumulation on the matrix cores) --------
 // One 64 x 64 block (bi <= bj) of one matrix per job; H is dp x dp with the
-// entries of index >= d set to zero.
+// entries of index >= d set to zero; accumulation is FP64 either way.
 struct GramJob {
   const void* M;
   int64_t m, ld;
-  double* H;
+  void* H;     // FP64, or FP32 when h_f32
   int64_t ldh;
-  int d, bi, bj;
+  int d, bi, bj, h_f32;
 };
 int launch_gram_jobs(const GramJob* d_jobs, int64_t njobs, int m_f32, hipStream_t stream);
 // H (ldh >= 64 * ceil(d / 64), FP64 or FP32) = M^T M for M m x d (FP64 or FP32).

@@ -28,10 +28,12 @@ def _lam_path(sig, nlam, m):
     return lams, alphas, betas
 
 
-@pytest.mark.parametrize("nlam", [16, 5, 20])
-def test_batched_lambda_paths_match_closed_form(nlam):
+@pytest.mark.parametrize("nlam,sa_dtype", [(16, np.float64), (5, np.float64), (20, np.float64),
+                                           (16, np.float32)])
+def test_batched_lambda_paths_match_closed_form(nlam, sa_dtype):
     """Several problems of different (n, d) -- ragged d, several 16-row tiles and
-    a ragged last tile -- each solved for a lambda path sharing one sketch."""
+    a ragged last tile -- each solved for a lambda path sharing one sketch (FP32
+    sketches: FP32 Gram matrix for the inner CG, FP64 outer loop)."""
     mihs = _mihs()
     shapes = [(1500, 70), (3001, 130), (900, 64), (4000, 300), (2500, 17)]
     problems, refs, lam_rows, a_rows, b_rows = [], [], [], [], []
@@ -39,14 +41,14 @@ def test_batched_lambda_paths_match_closed_form(nlam):
         sig = W.sigma_profile("exp", d, 6.0)
         P = W.make_problem(n, d, sig, d / 4, 100 + i)
         m = min(n, 4 * d)
-        SA = sketches.gaussian_sketch(P.A, m, 30 + i)
+        SA = sketches.gaussian_sketch(P.A, m, 30 + i).astype(sa_dtype)
         lams, alphas, betas = _lam_path(sig, nlam, m)
         problems.append((to_dev(P.A), to_dev(P.b), to_dev(SA)))
         refs.append([O.ridge_lstsq(P.A, P.b, float(l)) for l in lams])
         lam_rows.append(lams)
         a_rows.append(alphas)
         b_rows.append(betas)
-    announce(f"batched lambda paths nlam={nlam}")
+    announce(f"batched lambda paths nlam={nlam} sa={np.dtype(sa_dtype).name}")
     xs, infos = mihs.mihs_solve_batched(problems, to_dev(np.array(lam_rows)),
                                         to_dev(np.array(a_rows)), to_dev(np.array(b_rows)),
                                         eps_sub=1e-2, tol=1e-12, max_outer=600, max_inner=2000)

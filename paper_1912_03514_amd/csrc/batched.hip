@@ -299,14 +299,164 @@ __device__ __forceinline__ void store_block(const f64x4 (&Gacc)[DP / 64], double
     }
 }
 
-// LDS: the tile region, 16 rows of the widest entry (FP64 rows of dp + 2 elements
-// cover FP32 rows of dp + 4; it doubles as the d x 16 vector stage), then the A
-// pass's U reduction scratch (4 x 256 + 256 doubles) after a width's own region.
+// LDS: the tile region (the two DMA tile buffers of 64 KiB, or 16 rows of the
+// widest entry for the register-staged pass; it doubles as the d x 16 vector
+// stage), then the U reduction scratch (4 x 256 + 256 doubles) at a fixed offset.
 __host__ __device__ constexpr size_t tile_region(int dp) {
   return (size_t)TROWS * (dp + 2) * sizeof(double);
 }
+constexpr size_t kDmaRegion = 2 * (65536 + 16 * 64);  // two 64 KiB buffers + row padding
+constexpr size_t kUredOffset = kDmaRegion > 16 * (1024 + 2) * 8 ? kDmaRegion : 16 * (1024 + 2) * 8;
 constexpr size_t kUredBytes = (size_t)(kWavesPerBlock + 1) * TROWS * KR * sizeof(double);
-__host__ __device__ constexpr size_t lds_bytes(int dpmax) { return tile_region(dpmax) + kUredBytes; }
+__host__ __device__ constexpr size_t lds_bytes(int dpmax) {
+  return (dpmax > 0 ? kUredOffset : 0) + kUredBytes;
+}
+
+// Direct-to-LDS tile pipeline (rows of 1-4 KiB): a group of ROWS rows (64 KiB of
+// A) lands in one of two LDS buffers through global_load_lds_dwordx4 (64 lanes
+// x 16 bytes per instruction, no registers), while the other buffer is computed.
+template <typename TM, int DP>
+struct DmaCfg {
+  static constexpr int RB = DP * (int)sizeof(TM);           // row bytes
+  static constexpr bool ok = RB >= 1024 && RB <= 4096;
+  static constexpr int ROWS = ok ? 65536 / RB : TROWS;      // rows per group
+  static constexpr int TB = ROWS / TROWS;                   // 16-row tiles per group
+  static constexpr int CPR = ok ? RB / 1024 : 1;            // 1 KiB chunks per row
+  static constexpr int LDB = RB + 16;                       // LDS row stride (bytes)
+  static constexpr int LDT = LDB / (int)sizeof(TM);         // ... in elements
+  static constexpr int NI = ROWS * CPR / kWavesPerBlock;    // instructions per wave per group
+  static constexpr int BUF = ROWS * LDB;                    // bytes per buffer
+  static_assert(!ok || (NI == 16 && 2 * BUF <= (int)kDmaRegion), "dma layout");
+};
+
+typedef __attribute__((address_space(3))) char lds_char;
+
+// Issue the DMA of rows [row0, row0 + ROWS) into buffer `dst`: lane l of the
+// instruction for (row r, chunk c) moves 16 bytes at column c*1024/s + 16 l/s.
+// Rows past the end and columns past d read finite in-bounds data instead
+// (row rows-1, column 0): their products meet zero operands or are discarded.
+template <typename TM, int DP>
+__device__ __forceinline__ void dma_group(const TM* __restrict__ M, int64_t ld, int64_t rows,
+                                          int d, int64_t row0, lds_char* dst) {
+  typedef DmaCfg<TM, DP> C;
+  const int lane = lane_id(), wave = wave_id();
+#pragma unroll
+  for (int i = 0; i < C::NI; ++i) {
+    const int q = wave * C::NI + i;
+    const int r = q / C::CPR, c = q % C::CPR;
+    const int64_t gr = min(row0 + r, rows - 1);
+    const int col = c * (1024 / (int)sizeof(TM)) + lane * (16 / (int)sizeof(TM));
+    const TM* src = M + gr * ld + (col < d ? col : 0);
+    __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(dst + r * C::LDB + c * 1024), 16, 0, 0);
+  }
+}
+
+// Waits: vmcnt(16) (16 DMA instructions may stay in flight) and lgkmcnt(0)
+// (LDS traffic of this wave done).  Workgroup barriers without the
+// memory fence of __syncthreads (whose release would wait for the DMA in
+// flight); the empty asm statements keep the compiler from moving memory
+// accesses across them.
+__device__ __forceinline__ void wait_vm16() { __builtin_amdgcn_s_waitcnt(0x4F70); }
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+__device__ __forceinline__ void raw_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <typename TM, int DP>
+__device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t ld, int64_t rows,
+                                               int d, int rank, int T,
+                                               const double* __restrict__ B, int64_t ldb,
+                                               int64_t ldbc, int ncols,
+                                               const double (&Vreg)[DP / 16],
+                                               f64x4 (&Gacc)[DP / 64], lds_char* lbase,
+                                               double* ured, double* ufin) {
+  typedef DmaCfg<TM, DP> C;
+  constexpr int DQ = DP / 4, KS = DQ / 4, NB = DQ / 16;
+  constexpr int VE = 16 / (int)sizeof(TM);
+  const int lane = lane_id(), wave = wave_id();
+  const int kbase = wave * DQ;
+  const int rr = threadIdx.x / KR, jj = threadIdx.x % KR;
+  const int64_t ngroups = (rows + C::ROWS - 1) / C::ROWS;
+  const int dz = (d + VE - 1) / VE * VE;  // columns [d, dz) share a 16-byte chunk with d - 1
+  // classic double buffer: group g is computed from one buffer while group g + T
+  // lands in the other; the C values of g + T are loaded just before its DMA, so
+  // no wait inside the computation involves the DMA in flight
+  double cv[2][C::TB];
+  auto load_c = [&](double (&c)[C::TB], int64_t g) {
+#pragma unroll
+    for (int t = 0; t < C::TB; ++t) {
+      const int64_t gr = g * C::ROWS + t * TROWS + rr;
+      c[t] = (g < ngroups && B && gr < rows && jj < ncols) ? B[gr * ldb + jj * ldbc] : 0.0;
+    }
+  };
+  auto step = [&](double (&c)[C::TB], double (&cnext)[C::TB], int64_t g, lds_char* bufg,
+                  lds_char* bufn) {
+    const int64_t row0 = g * C::ROWS;
+    TM* tileg = (TM*)bufg;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this group and its C values
+    raw_barrier();
+    if (dz != d) {  // zero the bytes the last 16-byte chunk carried past d
+      for (int e = threadIdx.x; e < C::ROWS * (dz - d); e += kBlock)
+        tileg[(e / (dz - d)) * C::LDT + d + e % (dz - d)] = TM(0);
+      wait_lgkm0();
+      raw_barrier();
+    }
+    if (g + T < ngroups) {
+      load_c(cnext, g + T);
+      dma_group<TM, DP>(M, ld, rows, d, (g + T) * C::ROWS, bufn);
+    }
+#pragma unroll
+    for (int t = 0; t < C::TB; ++t) {
+      const TM* tile = tileg + t * TROWS * C::LDT;
+      const int64_t gr = row0 + t * TROWS + rr;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
+        if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        ured[wave * TROWS * KR + ((lane >> 4) + 4 * r) * KR + (lane & 15)] = acc[r];
+      wait_lgkm0();
+      raw_barrier();
+      {
+        double su = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) su += ured[w * TROWS * KR + rr * KR + jj];
+        ufin[rr * KR + jj] = (gr < rows && jj < ncols) ? c[t] - su : 0.0;
+      }
+      wait_lgkm0();
+      raw_barrier();
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int r2 = 4 * s + (lane >> 4);
+          const double a = (double)tile[r2 * C::LDT + kbase + 16 * b + (lane & 15)];
+          const double bv = ufin[r2 * KR + (lane & 15)];
+          Gacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, Gacc[b], 0, 0, 0);
+        }
+        if ((b & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+      }
+      wait_lgkm0();
+      raw_barrier();  // ured / ufin (and after the last tile, this buffer) free again
+    }
+  };
+  if (rank < ngroups) {
+    load_c(cv[0], rank);
+    dma_group<TM, DP>(M, ld, rows, d, rank * C::ROWS, lbase);
+  }
+  for (int64_t g = rank; g < ngroups; g += 2 * T) {
+    step(cv[0], cv[1], g, lbase, lbase + C::BUF);
+    if (g + T >= ngroups) break;
+    step(cv[1], cv[0], g + T, lbase + C::BUF, lbase);
+  }
+  __syncthreads();
+}
 
 // The whole A pass of one team member, out of line so that its registers
 // (the X operand, the Gram-block accumulators and the tile in flight) do not
@@ -319,9 +469,9 @@ __device__ __attribute__((noinline)) void a_pass(const TM* __restrict__ M, int64
                                                  int64_t ldbc, int ncols,
                                                  const double* __restrict__ X, int64_t ldx,
                                                  double* __restrict__ part_out) {
-  // dynamic LDS: this width's tile region, then the U reduction scratch
+  // dynamic LDS: the tile region, then the U reduction scratch
   extern __shared__ uint4 lds_raw[];
-  double* ured = (double*)((char*)lds_raw + tile_region(DP));
+  double* ured = (double*)((char*)lds_raw + kUredOffset);
   double* ufin = ured + kWavesPerBlock * TROWS * KR;
   constexpr int DQ = DP / 4;
   constexpr int KS = DQ / 4;
@@ -343,8 +493,12 @@ __device__ __attribute__((noinline)) void a_pass(const TM* __restrict__ M, int64
   f64x4 Gacc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) Gacc[b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  block_pass<TM, DP, true>(M, ld, rows, d, rank, T, B, ldb, ldbc, ncols, Vreg, Gacc, lds_raw,
-                           ured, ufin);
+  if (DmaCfg<TM, DP>::ok)
+    block_pass_dma<TM, DP>(M, ld, rows, d, rank, T, B, ldb, ldbc, ncols, Vreg, Gacc,
+                           (lds_char*)lds_raw, ured, ufin);
+  else
+    block_pass<TM, DP, true>(M, ld, rows, d, rank, T, B, ldb, ldbc, ncols, Vreg, Gacc, lds_raw,
+                             ured, ufin);
   store_block<DP>(Gacc, part_out);
 }
 
@@ -359,7 +513,7 @@ __device__ __attribute__((noinline)) double h_pass(const TH* __restrict__ H, int
                                                    double* __restrict__ Q) {
   extern __shared__ uint4 lds_raw[];
   const double* stage = (const double*)lds_raw;
-  double* ured = (double*)((char*)lds_raw + tile_region(DP));
+  double* ured = (double*)((char*)lds_raw + kUredOffset);
   constexpr int DQ = DP / 4;
   constexpr int KS = DQ / 4;
   constexpr int VE = 16 / (int)sizeof(TH);
@@ -487,11 +641,14 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
                          e.ncols, e.X, e.ldx, part + (int64_t)rank * DP * KR);
     if (!(alive = group_sync(e.bar, T, ep_all, a.err, s_flag, a.spin))) break;
 
-    if (cg) {
-      // ---- owners: g = sum of partials + rhs - lambda x; CG start r = g, z = 0
+    // ---- every member reduces the partials of a slice of columns:
+    // g = sum of partials + rhs - lambda x; CG start r = g, z = 0
+    {
+      const int cpa = (d + T - 1) / T;
+      const int a_lo = min(d, rank * cpa), a_hi = min(d, a_lo + cpa);
       double rr_lane = 0.0;
-      for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
-        const int c = c_lo + idx / KR, j = idx % KR;
+      for (int idx = threadIdx.x; idx < (a_hi - a_lo) * KR; idx += kBlock) {
+        const int c = a_lo + idx / KR, j = idx % KR;
         double g = 0.0;
 #pragma unroll 8
         for (int t = 0; t < T; ++t) g += part[((int64_t)t * DP + c) * KR + j];
@@ -506,8 +663,11 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
         rr_lane += g * g;
       }
       column_partials(rr_lane, myscal + 0, sh.red);
-      if (!(alive = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin))) break;
-      team_slot_sums(scal, Tc, 0, sh.rr0, sh.red);
+    }
+    if (!(alive = group_sync(e.bar, T, ep_all, a.err, s_flag, a.spin))) break;
+
+    if (cg) {
+      team_slot_sums(scal, T, 0, sh.rr0, sh.red);
       if (threadIdx.x < KR) {
         const int j = threadIdx.x;
         sh.rr[j] = sh.rr0[j];

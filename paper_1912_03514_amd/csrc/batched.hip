@@ -105,6 +105,8 @@ struct Shared {
   double step[KR], gnorm[KR];
   int flag;
 };
+// One instance per workgroup, visible to the out-of-line solver phases too.
+static __shared__ Shared g_sh;
 
 __device__ __forceinline__ bool group_sync(unsigned* bar, int size, unsigned& epoch, int* err,
                                            int* s_flag, BarrierSpin spin) {
@@ -503,12 +505,12 @@ __device__ __attribute__((noinline)) void a_pass(const TM* __restrict__ M, int64
 }
 
 // q = H p + lambda p on the owned columns [c_lo, c_hi) (16-aligned blocks), p
-// (d x 16) in the LDS stage; out of line like a_pass.  The waves split the
+// (d x 16) in the LDS stage.  The waves split the
 // k-range: lane (r, g) reads row cb + r of H over k = kbase + g KS + s (contiguous)
 // with 16-byte loads, one block ahead of the matrix-core work.  Returns this
 // thread's share of sum_c p_cj q_cj for its column j = tid % 16.
 template <typename TH, int DP>
-__device__ __attribute__((noinline)) double h_pass(const TH* __restrict__ H, int64_t ldh, int c_lo,
+__device__ __forceinline__ double h_matvec(const TH* __restrict__ H, int64_t ldh, int c_lo,
                                                    int c_hi, const double* lam,
                                                    double* __restrict__ Q) {
   extern __shared__ uint4 lds_raw[];
@@ -575,6 +577,93 @@ __device__ __attribute__((noinline)) double h_pass(const TH* __restrict__ H, int
     step(h1, cb + 16);
   }
   return pq;
+}
+
+// The lockstep CG of one outer iteration on a CG member (out of line, like
+// a_pass: its registers are saved once per outer iteration, not per step).
+// On entry R holds g (the member's columns), Z = 0, g_sh.rr / rr0 / active /
+// bcg are set.  Returns the number of steps taken, or -1 if a barrier timed
+// out; the caller advances its barrier epoch by two per step.
+template <typename TH, int DP>
+__device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, int64_t ldh, int d,
+                                                      int c_lo, int c_hi, double* R, double* Z,
+                                                      double* Q, const double* scal,
+                                                      double* myscal, int Tc, unsigned* bar_cg,
+                                                      unsigned epoch, int* err, BarrierSpin spin,
+                                                      double eps_sub, int64_t max_inner) {
+  extern __shared__ uint4 lds_raw[];
+  double* stage = (double*)lds_raw;
+  Shared& sh = g_sh;
+  const int nown = c_hi - c_lo;
+  int64_t k = 0;
+  while (true) {
+    int any = 0;
+    for (int j = 0; j < KR; ++j) any |= sh.active[j];
+    if (!any || k >= max_inner) break;
+    // p = r (first step) or r + beta_cg p over all d, in place in the stage
+    __syncthreads();
+    {
+      const int j = threadIdx.x % KR;  // fixed column per thread
+      const bool act = sh.active[j] != 0;
+      const double bc = sh.bcg[j];
+#pragma unroll 8
+      for (int i = 0; i < DP * KR / kBlock; ++i) {
+        const int idx = i * kBlock + (int)threadIdx.x;
+        const int c = idx / KR;
+        double v = 0.0;
+        if (c < d && act) v = (k == 0) ? R[idx] : R[idx] + bc * stage[idx];
+        stage[idx] = v;
+      }
+    }
+    __syncthreads();
+    // q = H p + lambda p on the owned 16-column blocks
+    const double pq_lane = h_matvec<TH, DP>(H, ldh, c_lo, c_hi, sh.lam, Q);
+    column_partials(pq_lane, myscal + KR, sh.red);
+    if (!group_sync(bar_cg, Tc, epoch, err, &sh.flag, spin)) return -1;
+    team_slot_sums(scal, Tc, KR, sh.ufin, sh.red);  // ufin[0..15] <- p_j^T q_j
+    if (threadIdx.x < KR) {
+      const int j = threadIdx.x;
+      const double pq = sh.ufin[j];
+      double al = 0.0;
+      if (sh.active[j]) {
+        al = sh.rr[j] / pq;
+        if (!(pq > 0.0) || !isfinite(al)) {
+          al = 0.0;
+          sh.active[j] = 0;  // breakdown in this column: keep the current step
+        }
+      }
+      sh.acg[j] = al;
+    }
+    __syncthreads();
+    // owners: z += alpha p, r -= alpha q
+    double rr_lane = 0.0;
+    for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
+      const int c = c_lo + idx / KR, j = idx % KR;
+      const int64_t o = (int64_t)c * KR + j;
+      if (sh.active[j]) {
+        const double al = sh.acg[j];
+        Z[o] += al * stage[o];
+        R[o] -= al * Q[o];
+      }
+      rr_lane += R[o] * R[o];
+    }
+    column_partials(rr_lane, myscal + 0, sh.red);
+    if (!group_sync(bar_cg, Tc, epoch, err, &sh.flag, spin)) return -1;
+    team_slot_sums(scal, Tc, 0, sh.ufin, sh.red);  // ufin[0..15] <- new ||r_j||^2
+    ++k;
+    if (threadIdx.x < KR) {
+      const int j = threadIdx.x;
+      if (sh.active[j]) {
+        const double rn = sh.ufin[j];
+        sh.bcg[j] = rn / sh.rr[j];
+        sh.rr[j] = rn;
+        sh.kin[j] = k;
+        if (rn <= eps_sub * eps_sub * sh.rr0[j]) sh.active[j] = 0;
+      }
+    }
+    __syncthreads();
+  }
+  return k;
 }
 
 template <int DP>
@@ -679,76 +768,15 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       __syncthreads();
 
       // ---- lockstep CG on (H + lambda_j I)
-      int64_t k = 0;
-      while (true) {
-        int any = 0;
-        for (int j = 0; j < KR; ++j) any |= sh.active[j];
-        if (!any || k >= a.max_inner) break;
-        // p = r (first step) or r + beta_cg p over all d, in place in the stage
-        __syncthreads();
-        {
-          const int j = threadIdx.x % KR;  // fixed column per thread
-          const bool act = sh.active[j] != 0;
-          const double bc = sh.bcg[j];
-#pragma unroll 8
-          for (int i = 0; i < DP * KR / kBlock; ++i) {
-            const int idx = i * kBlock + (int)threadIdx.x;
-            const int c = idx / KR;
-            double v = 0.0;
-            if (c < d && act) v = (k == 0) ? R[idx] : R[idx] + bc * stage[idx];
-            stage[idx] = v;
-          }
-        }
-        __syncthreads();
-        // q = H p + lambda p on the owned 16-column blocks
-        const double pq_lane =
-            a.h_f32 ? h_pass<float, DP>((const float*)e.H, e.ldh, c_lo, c_hi, sh.lam, Q)
-                    : h_pass<double, DP>((const double*)e.H, e.ldh, c_lo, c_hi, sh.lam, Q);
-        column_partials(pq_lane, myscal + KR, sh.red);
-        if (!(alive = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin))) break;
-        team_slot_sums(scal, Tc, KR, sh.ufin, sh.red);  // ufin[0..15] <- p_j^T q_j
-        if (threadIdx.x < KR) {
-          const int j = threadIdx.x;
-          const double pq = sh.ufin[j];
-          double al = 0.0;
-          if (sh.active[j]) {
-            al = sh.rr[j] / pq;
-            if (!(pq > 0.0) || !isfinite(al)) {
-              al = 0.0;
-              sh.active[j] = 0;  // breakdown in this column: keep the current step
-            }
-          }
-          sh.acg[j] = al;
-        }
-        __syncthreads();
-        // owners: z += alpha p, r -= alpha q
-        double rr_lane2 = 0.0;
-        for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
-          const int c = c_lo + idx / KR, j = idx % KR;
-          const int64_t o = (int64_t)c * KR + j;
-          if (sh.active[j]) {
-            const double al = sh.acg[j];
-            Z[o] += al * stage[o];
-            R[o] -= al * Q[o];
-          }
-          rr_lane2 += R[o] * R[o];
-        }
-        column_partials(rr_lane2, myscal + 0, sh.red);
-        if (!(alive = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin))) break;
-        team_slot_sums(scal, Tc, 0, sh.ufin, sh.red);  // ufin[0..15] <- new ||r_j||^2
-        ++k;
-        if (threadIdx.x < KR) {
-          const int j = threadIdx.x;
-          if (sh.active[j]) {
-            const double rn = sh.ufin[j];
-            sh.bcg[j] = rn / sh.rr[j];
-            sh.rr[j] = rn;
-            sh.kin[j] = k;
-            if (rn <= a.eps_sub * a.eps_sub * sh.rr0[j]) sh.active[j] = 0;
-          }
-        }
-        __syncthreads();
-      }
+      const int64_t k =
+          a.h_f32 ? cg_solve<float, DP>((const float*)e.H, e.ldh, d, c_lo, c_hi, R, Z, Q, scal,
+                                        myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin, a.eps_sub,
+                                        a.max_inner)
+                  : cg_solve<double, DP>((const double*)e.H, e.ldh, d, c_lo, c_hi, R, Z, Q, scal,
+                                         myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin, a.eps_sub,
+                                         a.max_inner);
+      alive = k >= 0;
+      if (alive && Tc > 1) ep_cg += 2u * (unsigned)k;
       if (!alive) break;
       if (threadIdx.x < KR) {
         const int j = threadIdx.x;
@@ -814,7 +842,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
 template <int DPMAX>
 __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs a) {
   extern __shared__ uint4 lds_raw[];
-  __shared__ Shared sh;
+  Shared& sh = g_sh;
   void* lds = (void*)lds_raw;
   const int* items = a.wg_items + (int64_t)blockIdx.x * a.items_stride;
   for (int i = 0; i < a.items_stride; ++i) {

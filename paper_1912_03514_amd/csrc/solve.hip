@@ -65,6 +65,7 @@ struct SolveArgs {
   int* status;        // decision published by the CG group
   const void* H;      // Gram matrix (SA)^T SA (TS), dpad x dpad, when the CG uses it
   int64_t ldh;
+  int cg1;            // Gram path: single-reduction CG (one barrier per step)
   int d, dpad, G, Gc, cpw;
   BarrierSpin spin_fast, spin_idle;
 };
@@ -350,122 +351,209 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
         decision = (rr0 == 0.0) ? 1 : 2;  // stationary point, or NaN
       } else {
         const double stop = a.eps_sub * a.eps_sub * rr0;
-        double rr = rr0;
-        TV* vp = (TV*)vbuf;
-        while (true) {
-          // ---- C1: p = r + beta_cg p_prev (k > 0), staged in LDS.  The loads of
-          // r, p_prev and the residual partials are all issued before use.
-          TV* pcur = P[k & 1];
-          const TV* pprev = P[(k + 1) & 1];
-          TV rv[NPT], pv[NPT];
+        if (GRAM && a.cg1) {
+          // Single-reduction CG (Chronopoulos-Gear): with s = M p kept by its own
+          // recurrence, one matrix product (w = M r on the owned rows) and one
+          // fused reduction (r^T r, w^T r) per step, so one barrier per step.
+          // Every CG workgroup keeps full copies of r and s in LDS (identical
+          // arithmetic everywhere), gathers w from global memory (two buffers,
+          // alternating) and owns p and z on its columns.
+          TV* rv = (TV*)vbuf;
+          TV* sv = (TV*)rbuf;
+          const TS* Hm = (const TS*)a.H;
+          const TV lt = (TV)a.lam;
+          for (int c = threadIdx.x; c < a.dpad; c += kBlock) rv[c] = (c < d) ? r[c] : TV(0);
+          __syncthreads();
+          int wb = 0;
+          double mu = rr0, alpha = 0.0, unused2;
+          {
+            rowdots<TS, TV, EPT>(Hm, a.ldh, c_lo, c_hi, d, rv, colbuf);
+            __syncthreads();
+            double nu_part = 0.0;
+            for (int i = threadIdx.x; i < nown; i += kBlock) {
+              const TV rc = rv[c_lo + i];
+              const TV wc = (TV)colbuf[i] + lt * rc;
+              P[wb][c_lo + i] = wc;
+              nu_part += (double)wc * (double)rc;
+            }
+            nu_part = block_sum(nu_part, s_red);
+            if (threadIdx.x == 0) scal_w[1] = nu_part;
+            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            double nu;
+            sum2_slots(a.scal, Gc, 1, 1, s_red, nu, unused2);
+            alpha = mu / nu;
+            if (!(nu > 0.0) || !isfinite(alpha)) decision = 2;
+          }
+          if (decision == 0) {
+            // s = w, p = r
+            for (int c = threadIdx.x; c < a.dpad; c += kBlock) sv[c] = (c < d) ? P[wb][c] : TV(0);
+            for (int i = threadIdx.x; i < nown; i += kBlock) own_r[i] = rv[c_lo + i];
+            __syncthreads();
+            while (true) {
+              const TV at = (TV)alpha;
+              for (int i = threadIdx.x; i < nown; i += kBlock) own_z[i] = own_z[i] + at * own_r[i];
+              for (int c = threadIdx.x; c < a.dpad; c += kBlock) rv[c] = rv[c] - at * sv[c];
+              __syncthreads();
+              ++k;
+              wb ^= 1;
+              rowdots<TS, TV, EPT>(Hm, a.ldh, c_lo, c_hi, d, rv, colbuf);
+              __syncthreads();
+              double mu_p = 0.0, nu_p = 0.0;
+              for (int i = threadIdx.x; i < nown; i += kBlock) {
+                const TV rc = rv[c_lo + i];
+                const TV wc = (TV)colbuf[i] + lt * rc;
+                P[wb][c_lo + i] = wc;
+                mu_p += (double)rc * (double)rc;
+                nu_p += (double)wc * (double)rc;
+              }
+              mu_p = block_sum(mu_p, s_red);
+              nu_p = block_sum(nu_p, s_red);
+              if (threadIdx.x == 0) {
+                scal_w[2] = mu_p;
+                scal_w[3] = nu_p;
+              }
+              if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              double mu_n, nu_n;
+              sum2_slots(a.scal, Gc, 2, 3, s_red, mu_n, nu_n);
+              if (mu_n <= stop || k >= a.max_inner) break;
+              const double bt = mu_n / mu;
+              const double den = nu_n - bt * mu_n / alpha;
+              const double an = mu_n / den;
+              if (!(den > 0.0) || !isfinite(an)) {
+                decision = 2;
+                break;
+              }
+              mu = mu_n;
+              alpha = an;
+              // s = w + beta s (full), p = r + beta p (owned)
+              const TV btt = (TV)bt;
+              for (int c = threadIdx.x; c < a.dpad; c += kBlock)
+                sv[c] = ((c < d) ? P[wb][c] : TV(0)) + btt * sv[c];
+              for (int i = threadIdx.x; i < nown; i += kBlock)
+                own_r[i] = rv[c_lo + i] + btt * own_r[i];
+              __syncthreads();
+            }
+          }
+          if (!alive) break;
+        } else {
+          double rr = rr0;
+          TV* vp = (TV*)vbuf;
+          while (true) {
+            // ---- C1: p = r + beta_cg p_prev (k > 0), staged in LDS.  The loads of
+            // r, p_prev and the residual partials are all issued before use.
+            TV* pcur = P[k & 1];
+            const TV* pprev = P[(k + 1) & 1];
+            TV rv[NPT], pv[NPT];
 #pragma unroll
-          for (int i = 0; i < NPT; ++i) {
-            const int c = threadIdx.x + i * kBlock;
-            rv[i] = TV(0);
-            pv[i] = TV(0);
-            if (c < d) {
-              if (k == 0) {
-                rv[i] = pcur[c];
-              } else {
-                rv[i] = r[c];
-                pv[i] = pprev[c];
+            for (int i = 0; i < NPT; ++i) {
+              const int c = threadIdx.x + i * kBlock;
+              rv[i] = TV(0);
+              pv[i] = TV(0);
+              if (c < d) {
+                if (k == 0) {
+                  rv[i] = pcur[c];
+                } else {
+                  rv[i] = r[c];
+                  pv[i] = pprev[c];
+                }
               }
             }
-          }
-          TV bc = TV(0);
-          if (k > 0) {
-            double rr_new;
-            sum2_slots(a.scal, Gc, 3, 3, s_red, rr_new, unused);
-            if (rr_new <= stop || k >= a.max_inner) break;
-            bc = (TV)(rr_new / rr);
-            rr = rr_new;
-          }
-#pragma unroll
-          for (int i = 0; i < NPT; ++i) {
-            const int c = threadIdx.x + i * kBlock;
-            if (c < a.dpad) {
-              const TV p = (k == 0) ? rv[i] : (TV)(rv[i] + bc * pv[i]);
-              vp[c] = (c < d) ? p : TV(0);
-              if (k > 0 && c >= c_lo && c < c_hi) pcur[c] = p;
+            TV bc = TV(0);
+            if (k > 0) {
+              double rr_new;
+              sum2_slots(a.scal, Gc, 3, 3, s_red, rr_new, unused);
+              if (rr_new <= stop || k >= a.max_inner) break;
+              bc = (TV)(rr_new / rr);
+              rr = rr_new;
             }
-          }
-          for (int c = NPT * kBlock + threadIdx.x; c < a.dpad; c += kBlock) vp[c] = TV(0);
-          __syncthreads();
-          double rpart = 0.0;
-          if (GRAM) {
-            // q = H p + lambda p on the owned columns (colbuf <- H p)
-            rowdots<TS, TV, EPT>((const TS*)a.H, a.ldh, c_lo, c_hi, d, vp, colbuf);
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+              const int c = threadIdx.x + i * kBlock;
+              if (c < a.dpad) {
+                const TV p = (k == 0) ? rv[i] : (TV)(rv[i] + bc * pv[i]);
+                vp[c] = (c < d) ? p : TV(0);
+                if (k > 0 && c >= c_lo && c < c_hi) pcur[c] = p;
+              }
+            }
+            for (int c = NPT * kBlock + threadIdx.x; c < a.dpad; c += kBlock) vp[c] = TV(0);
             __syncthreads();
-            double pq = 0.0;
-            for (int i = threadIdx.x; i < nown; i += kBlock) {
-              const double pc = (double)vp[c_lo + i];
-              pq += pc * (colbuf[i] + a.lam * pc);
-            }
-            pq = block_sum(pq, s_red);
-            if (threadIdx.x == 0) scal_w[1] = pq;
-            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
-            double pqs, unused2;
-            sum2_slots(a.scal, Gc, 1, 1, s_red, pqs, unused2);
-            const double acg = rr / pqs;
-            if (!(pqs > 0.0) || !isfinite(acg)) {
-              decision = 2;
-              break;
-            }
-            const TV at = (TV)acg, lt = (TV)a.lam;
-            for (int i = threadIdx.x; i < nown; i += kBlock) {
-              const TV pc = vp[c_lo + i];
-              const TV q = (TV)colbuf[i] + lt * pc;
-              own_z[i] = own_z[i] + at * pc;
-              const TV rn = own_r[i] - at * q;
-              own_r[i] = rn;
-              r[c_lo + i] = rn;
-              rpart += (double)rn * (double)rn;
-            }
-          } else {
-            TV ssq = TV(0);
-            {
-              TV acc[EPT];
+            double rpart = 0.0;
+            if (GRAM) {
+              // q = H p + lambda p on the owned columns (colbuf <- H p)
+              rowdots<TS, TV, EPT>((const TS*)a.H, a.ldh, c_lo, c_hi, d, vp, colbuf);
+              __syncthreads();
+              double pq = 0.0;
+              for (int i = threadIdx.x; i < nown; i += kBlock) {
+                const double pc = (double)vp[c_lo + i];
+                pq += pc * (colbuf[i] + a.lam * pc);
+              }
+              pq = block_sum(pq, s_red);
+              if (threadIdx.x == 0) scal_w[1] = pq;
+              if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              double pqs, unused2;
+              sum2_slots(a.scal, Gc, 1, 1, s_red, pqs, unused2);
+              const double acg = rr / pqs;
+              if (!(pqs > 0.0) || !isfinite(acg)) {
+                decision = 2;
+                break;
+              }
+              const TV at = (TV)acg, lt = (TV)a.lam;
+              for (int i = threadIdx.x; i < nown; i += kBlock) {
+                const TV pc = vp[c_lo + i];
+                const TV q = (TV)colbuf[i] + lt * pc;
+                own_z[i] = own_z[i] + at * pc;
+                const TV rn = own_r[i] - at * q;
+                own_r[i] = rn;
+                r[c_lo + i] = rn;
+                rpart += (double)rn * (double)rn;
+              }
+            } else {
+              TV ssq = TV(0);
+              {
+                TV acc[EPT];
 #pragma unroll
-              for (int e = 0; e < EPT; ++e) acc[e] = TV(0);
-              rowpass<TS, TV, EPT, false, RS>(SA, a.ldsa, s_r0, s_r1, d, vp, nullptr, acc, ssq);
-              wg_store_partial<TS, TV, EPT>(acc, (TV*)rbuf, partS + (int64_t)w * a.dpad, d);
-              ssq = wg_sum_ssq(ssq, s_red);
-            }
-            double pp = 0.0;
-            for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock)
-              pp += (double)vp[c] * (double)vp[c];
-            pp = block_sum(pp, s_red);
-            if (threadIdx.x == 0) {
-              scal_w[1] = pp;
-              scal_w[2] = (double)ssq;
-            }
-            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+                for (int e = 0; e < EPT; ++e) acc[e] = TV(0);
+                rowpass<TS, TV, EPT, false, RS>(SA, a.ldsa, s_r0, s_r1, d, vp, nullptr, acc, ssq);
+                wg_store_partial<TS, TV, EPT>(acc, (TV*)rbuf, partS + (int64_t)w * a.dpad, d);
+                ssq = wg_sum_ssq(ssq, s_red);
+              }
+              double pp = 0.0;
+              for (int c = c_lo + threadIdx.x; c < c_hi; c += kBlock)
+                pp += (double)vp[c] * (double)vp[c];
+              pp = block_sum(pp, s_red);
+              if (threadIdx.x == 0) {
+                scal_w[1] = pp;
+                scal_w[2] = (double)ssq;
+              }
+              if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
 
-            // ---- C2: step length (p^T q = ||u||^2 + lambda ||p||^2) and owner updates
-            owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
-            double ppn, uu;
-            sum2_slots(a.scal, Gc, 1, 2, s_red, ppn, uu);
-            const double pq = uu + a.lam * ppn;
-            const double acg = rr / pq;
-            if (!(pq > 0.0) || !isfinite(acg)) {
-              decision = 2;
-              break;
+              // ---- C2: step length (p^T q = ||u||^2 + lambda ||p||^2) and owner updates
+              owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
+              double ppn, uu;
+              sum2_slots(a.scal, Gc, 1, 2, s_red, ppn, uu);
+              const double pq = uu + a.lam * ppn;
+              const double acg = rr / pq;
+              if (!(pq > 0.0) || !isfinite(acg)) {
+                decision = 2;
+                break;
+              }
+              const TV at = (TV)acg, lt = (TV)a.lam;
+              for (int i = threadIdx.x; i < nown; i += kBlock) {
+                const TV pc = vp[c_lo + i];
+                const TV q = (TV)(-colbuf[i]) + lt * pc;
+                own_z[i] = own_z[i] + at * pc;
+                const TV rn = own_r[i] - at * q;
+                own_r[i] = rn;
+                r[c_lo + i] = rn;
+                rpart += (double)rn * (double)rn;
+              }
             }
-            const TV at = (TV)acg, lt = (TV)a.lam;
-            for (int i = threadIdx.x; i < nown; i += kBlock) {
-              const TV pc = vp[c_lo + i];
-              const TV q = (TV)(-colbuf[i]) + lt * pc;
-              own_z[i] = own_z[i] + at * pc;
-              const TV rn = own_r[i] - at * q;
-              own_r[i] = rn;
-              r[c_lo + i] = rn;
-              rpart += (double)rn * (double)rn;
-            }
+            rpart = block_sum(rpart, s_red);
+            if (threadIdx.x == 0) scal_w[3] = rpart;
+            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            ++k;
           }
-          rpart = block_sum(rpart, s_red);
-          if (threadIdx.x == 0) scal_w[3] = rpart;
-          if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
-          ++k;
+
         }
         if (!alive) break;
       }
@@ -606,7 +694,7 @@ int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G) {
   } else {
     // bytes one CG step streams: the Gram matrix (m >= d) or SA
     const double mb = (double)(m >= d ? d : m) * (double)d * sa_bytes / (1024.0 * 1024.0);
-    gc = mb >= 64.0 ? 128 : (mb >= 4.0 ? 64 : (mb >= 1.0 ? 32 : 16));
+    gc = mb >= 8.0 ? 128 : (mb >= 4.0 ? 64 : (mb >= 1.0 ? 32 : 16));
     // each CG workgroup should own at least a few rows
     const int64_t by_rows = (m + 3) / 4;
     if (gc > by_rows) gc = (int)(by_rows < 1 ? 1 : by_rows);
@@ -715,6 +803,10 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   a.spin_idle.sleep = 16;
   a.H = gram ? (const void*)(base + L.gram) : nullptr;
   a.ldh = dpad;
+  // One barrier per CG step pays off where the CG is latency-bound; the
+  // two-reduction form keeps fewer steps on very ill-conditioned FP64 solves
+  // (measured: CountSketch workload, kappa ~ 6e8, 22k vs 27-38k steps).
+  a.cg1 = s.mixed ? 1 : 0;
   if (gram) {
     const int rc = launch_gram(s.SA, s.mixed, s.m, s.d, s.ldsa, base + L.gram, s.mixed, dpad,
                                stream);

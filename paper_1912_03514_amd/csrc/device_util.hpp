@@ -63,6 +63,13 @@ struct VecLoad<double, 2, NT> {
   }
 };
 template <bool NT>
+struct VecLoad<double, 4, NT> {
+  static __device__ __forceinline__ void run(const double* p, double* out) {
+    VecLoad<double, 2, NT>::run(p, out);
+    VecLoad<double, 2, NT>::run(p + 2, out + 2);
+  }
+};
+template <bool NT>
 struct VecLoad<float, 4, NT> {
   static __device__ __forceinline__ void run(const float* p, float* out) {
     flt4 v = NT ? __builtin_nontemporal_load((const flt4*)p) : *(const flt4*)p;

@@ -109,7 +109,9 @@ template <typename TA, typename TY>
 __global__ __launch_bounds__(kBlock) void srht_stage1_b512(const TA* __restrict__ A, int64_t lda,
                                                            int64_t d, uint32_t seed,
                                                            TY* __restrict__ Y, int64_t ldy) {
-  constexpr int W = sizeof(TA) == 8 ? 16 : 32;
+  // 32 columns when the transform runs in FP32 (256-byte row segments of FP64 A),
+  // else 16 (the LDS tile stays at ~66 KiB either way)
+  constexpr int W = sizeof(TY) == 4 ? 32 : 16;
   constexpr int C1 = W / 8;   // columns per thread, phase 1
   constexpr int C2 = W / 16;  // columns per thread, phase 2
   constexpr int PAD = 1;
@@ -695,7 +697,7 @@ int run_srht(const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint32_t
   hipLaunchKernelGGL(srht_rows_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, idx, m, n,
                      seed);
   if (logB == 9) {
-    constexpr int W = sizeof(TA) == 8 ? 16 : 32;
+    constexpr int W = sizeof(TY) == 4 ? 32 : 16;
     hipLaunchKernelGGL((srht_stage1_b512<TA, TY>), dim3((unsigned)ceil_div(d, W), (unsigned)nhi),
                        dim3(kBlock), 0, st, A, lda, d, seed, Y, ldy);
   } else {

@@ -35,6 +35,7 @@ namespace mihs {
 namespace {
 
 constexpr int kScal = 8;           // scalar partial slots per workgroup
+constexpr double kCg1MaxCond = 1e5;  // single-reduction CG up to this trace(H)/lambda
 constexpr int kMaxBlocksPerCU = 2;
 
 struct SolveArgs {
@@ -303,6 +304,18 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   }
   __syncthreads();
 
+  // Single-reduction CG only where the sub-problem is well conditioned for its
+  // precision: trace(H) / lambda bounds kappa(H + lambda I) from above.  Every CG
+  // workgroup sums the same diagonal in the same order, so all decide alike.
+  bool cg1 = false;
+  if (GRAM && a.cg1 && in_cg) {
+    const TS* Hm = (const TS*)a.H;
+    double tr = 0.0;
+    for (int c = threadIdx.x; c < d; c += kBlock) tr += (double)Hm[(int64_t)c * a.ldh + c];
+    tr = block_sum(tr, s_red);
+    cg1 = tr <= kCg1MaxCond * a.lam;
+  }
+
   const int64_t a_r0 = a.n * w / G, a_r1 = a.n * (w + 1) / G;
   const int64_t s_r0 = in_cg ? a.m * w / Gc : 0;
   const int64_t s_r1 = in_cg ? a.m * (w + 1) / Gc : 0;
@@ -351,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
         decision = (rr0 == 0.0) ? 1 : 2;  // stationary point, or NaN
       } else {
         const double stop = a.eps_sub * a.eps_sub * rr0;
-        if (GRAM && a.cg1) {
+        if (GRAM && cg1) {
           // Single-reduction CG (Chronopoulos-Gear): with s = M p kept by its own
           // recurrence, one matrix product (w = M r on the owned rows) and one
           // fused reduction (r^T r, w^T r) per step, so one barrier per step.
@@ -804,8 +817,9 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   a.H = gram ? (const void*)(base + L.gram) : nullptr;
   a.ldh = dpad;
   // One barrier per CG step pays off where the CG is latency-bound; the
-  // two-reduction form keeps fewer steps on very ill-conditioned FP64 solves
-  // (measured: CountSketch workload, kappa ~ 6e8, 22k vs 27-38k steps).
+  // two-reduction form keeps fewer steps on very ill-conditioned solves
+  // (measured on the CountSketch workload, kappa ~ 6e8: FP64 22k vs 27-38k
+  // steps; FP32 breaks down), so the kernel also checks trace(H) / lambda.
   a.cg1 = s.mixed ? 1 : 0;
   if (gram) {
     const int rc = launch_gram(s.SA, s.mixed, s.m, s.d, s.ldsa, base + L.gram, s.mixed, dpad,

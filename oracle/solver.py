@@ -19,6 +19,10 @@ Theorem 1 (beta*, alpha* from the embedding accuracy epsilon).
 Inner solvers: exact (Cholesky of the d x d sketched Hessian), conjugate
 gradients stopped on the relative residual eps_sub (Section 3.1's constant
 forcing term), and AAb_Solver (Algorithm 6, Section 3.5).
+
+Dual M-IHS (Section 2, eqs. (intro_dual), (dual_mihs1); Algorithm 2) for
+n <= d iterates on the dual variable nu in R^n with a sketch of A^T and
+recovers x* = A^T nu* (eq. (dual_relation)).
 """
 from __future__ import annotations
 
@@ -261,6 +265,74 @@ def mihs(A: np.ndarray, b: np.ndarray, lam: float, SA: np.ndarray, alpha: float,
             break
     return MihsResult(x=x, outer=it, inner=inner_counts, steps=steps, converged=converged,
                       history=hist)
+
+
+# ----------------------------------------------------------------------------
+# Dual M-IHS (n <= d)
+# ----------------------------------------------------------------------------
+def dual_gradient(A: np.ndarray, b: np.ndarray, lam: float, nu: np.ndarray) -> np.ndarray:
+    """The descent direction of the dual objective g(nu) = 1/2 ||A^T nu||^2 +
+    lambda/2 ||nu||^2 - <b, nu> (eq. (intro_dual)): b - A A^T nu - lambda nu
+    (Algorithm 2's gradient line; it is -grad g)."""
+    A64 = A.astype(np.float64, copy=False)
+    return b - A64 @ (A64.T @ nu) - lam * nu
+
+
+@dataclasses.dataclass
+class DualMihsResult:
+    x: np.ndarray     # primal solution A^T nu
+    nu: np.ndarray    # dual iterate
+    outer: int
+    inner: List[int]
+    steps: List[float]
+    converged: bool
+
+
+def dual_mihs(A: np.ndarray, b: np.ndarray, lam: float, SAt: np.ndarray, alpha: float,
+              beta: float, *, inner: str = "cg", eps_sub: float = 1e-2,
+              max_inner: Optional[int] = None, n_iter: Optional[int] = None,
+              tol: Optional[float] = None, max_outer: int = 500) -> DualMihsResult:
+    """Dual M-IHS (Algorithm 2) for A n x d with n <= d and SAt = S A^T (m x n).
+
+    nu^1 = 0; per iteration
+        g^i       = b - A A^T nu^i - lambda nu^i
+        dnu^i     = ((S A^T)^T S A^T + lambda I)^{-1} g^i     (the sub-problem
+                    of eq. (dual_mihs1), solved by the chosen inner solver)
+        nu^{i+1}  = nu^i + alpha dnu^i + beta (nu^i - nu^{i-1}),  nu^0 = nu^1,
+    and finally x = A^T nu (eq. (dual_relation)).  Runs `n_iter` iterations if
+    given, else stops on the relative-step rule for nu with target `tol`."""
+    n = A.shape[0]
+    nu = np.zeros(n)
+    nu_prev = nu.copy()
+    exact = inner_exact_factory(SAt, lam) if inner == "exact" else None
+    inner_counts: List[int] = []
+    steps: List[float] = []
+    thr = stop_threshold(tol, beta) if tol is not None else None
+    limit = n_iter if n_iter is not None else max_outer
+    converged = False
+    it = 0
+    for it in range(1, limit + 1):
+        g = dual_gradient(A, b, lam, nu)
+        if inner == "exact":
+            dnu, k = exact(g)
+        elif inner == "cg":
+            dnu, k = inner_cg(SAt, g, lam, eps_sub, max_inner)
+        elif inner == "aab":
+            dnu, k = aab_solver(SAt, g, lam, eps_sub, max_inner)
+        else:
+            raise ValueError(inner)
+        inner_counts.append(k)
+        nu_new = nu + alpha * dnu + beta * (nu - nu_prev)
+        nrm = float(np.linalg.norm(nu_new))
+        step = float(np.linalg.norm(nu_new - nu)) / nrm if nrm > 0 else 0.0
+        steps.append(step)
+        nu_prev, nu = nu, nu_new
+        if thr is not None and n_iter is None and step <= thr:
+            converged = True
+            break
+    x = A.astype(np.float64, copy=False).T @ nu
+    return DualMihsResult(x=x, nu=nu, outer=it, inner=inner_counts, steps=steps,
+                          converged=converged)
 
 
 # ----------------------------------------------------------------------------

@@ -207,3 +207,50 @@ def test_planted_mistakes_are_caught(monkeypatch):
     bad2 = O.mihs(P.A, P.b, P.lam, SA, b, a, inner="exact", n_iter=60)  # alpha <-> beta
     e2 = np.linalg.norm(bad2.x - xs) / np.linalg.norm(xs)
     assert e2 > 1e-8 or not np.isfinite(e2)
+
+
+def _wide(n=60, d=400, seed=3):
+    """An under-determined instance: A^T drawn by the same recipe as a tall A."""
+    sig = W.sigma_profile("exp", n, 6.0)
+    P = W.make_problem(d, n, sig, 15.0, seed)   # P.A is d x n (tall): A = P.A^T
+    A = P.A.T.copy()
+    rng = np.random.default_rng(seed + 1)
+    b = A @ (rng.standard_normal(d) / math.sqrt(d)) + 1e-3 * rng.standard_normal(n)
+    return A, b, P.lam
+
+
+def test_dual_mihs_reaches_primal_closed_form():
+    """Dual M-IHS (Algorithm 2) with CG or exact inner solves converges to the
+    primal ridge solution, computed independently by least squares of
+    [A; sqrt(lambda) I] (the problem has n < d)."""
+    A, b, lam = _wide()
+    xs = O.ridge_lstsq(A, b, lam)
+    SAt = sketches.gaussian_sketch(A.T, 120, 4)   # S A^T, m x n
+    a, bt = O.momentum_cor4(15.0, 120)
+    for inner in ("exact", "cg"):
+        r = O.dual_mihs(A, b, lam, SAt, a, bt, inner=inner, eps_sub=1e-10, tol=1e-13)
+        assert r.converged
+        assert np.linalg.norm(r.x - xs) <= 1e-10 * np.linalg.norm(xs), inner
+        # eq. (dual_relation): nu* = (b - A x*) / lambda
+        nu_ref = (b - A @ xs) / lam
+        assert np.linalg.norm(r.nu - nu_ref) <= 1e-9 * np.linalg.norm(nu_ref), inner
+
+
+def test_dual_one_step_with_identity_sketch():
+    """S = I (the sketch of A^T is A^T itself), exact inner solve, alpha = 1,
+    beta = 0: the sub-problem Hessian is A A^T + lambda I, so one step reaches nu*."""
+    A, b, lam = _wide(n=30, d=90, seed=9)
+    r = O.dual_mihs(A, b, lam, A.T.copy(), 1.0, 0.0, inner="exact", n_iter=1)
+    nu_star = np.linalg.solve(A @ A.T + lam * np.eye(A.shape[0]), b)
+    assert np.linalg.norm(r.nu - nu_star) <= 1e-12 * np.linalg.norm(nu_star)
+
+
+def test_dual_planted_mistake_is_caught(monkeypatch):
+    """Dropping the lambda nu term from the dual gradient breaks the pin."""
+    A, b, lam = _wide()
+    xs = O.ridge_lstsq(A, b, lam)
+    SAt = sketches.gaussian_sketch(A.T, 120, 4)
+    a, bt = O.momentum_cor4(15.0, 120)
+    monkeypatch.setattr(O, "dual_gradient", lambda A_, b_, l_, nu: b_ - A_ @ (A_.T @ nu))
+    r = O.dual_mihs(A, b, lam, SAt, a, bt, inner="exact", n_iter=80)
+    assert np.linalg.norm(r.x - xs) > 1e-6 * np.linalg.norm(xs)

@@ -16,7 +16,8 @@ Prints ONE JSON line.  --gpus above 1 is refused: this build measures one GPU.
 Other workloads (opt-in, one JSON line each): --workload small_gauss (4096 x 256,
 Gaussian m = 256), batched_lambda_path (256 problems x 16 lambdas, Gaussian
 sketches, one launch), diff_2p18x1024 (64 right-hand sides, forward + adjoint
-backward through the autograd op).
+backward through the autograd op), count_2p20x4096 (FP32 A, CountSketch ->
+Gaussian), dual_4096x2p16 (under-determined, Dual M-IHS).
 """
 from __future__ import annotations
 
@@ -308,6 +309,67 @@ def run_diff(args):
     }
 
 
+def run_dual(args):
+    """Dual M-IHS (Algorithm 2) on the under-determined workload: A is 4096 x 2^16
+    (A^T stored, FP64), SRHT m = 4096 on A^T; one step = sketch + dual solve +
+    x = A^T nu, mixed and plain; error against the closed form
+    nu* = (A A^T + lambda I)^{-1} b, x* = A^T nu*."""
+    import numpy as np
+    import torch
+    import paper_1912_03514_amd as mihs
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    w = W.workload("dual_4096x2p16")
+    At, b, lam = W.make_dual_problem_torch(w.n, w.d, w.sigma, w.sd_target, w.data_seed, dev,
+                                           w.a_dtype)
+    log("closed form on the host")
+    Ath = At.cpu().numpy()
+    nu_s = np.linalg.solve(Ath.T @ Ath + lam * np.eye(w.n), b.cpu().numpy())
+    xs = Ath @ nu_s
+    alpha, beta = mihs.momentum(w.sd_target, w.m_out)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for prec in ("mixed", "plain"):
+        def step():
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            SAt = mihs.mihs_sketch(At, w.sketch, w.m, w.sketch_seed, precision=prec)
+            e1.record(stream)
+            x, nu, info = mihs.mihs_solve_dual(At, b, lam, SAt, alpha, beta, eps_sub=w.eps_sub,
+                                               tol=args.tol, max_outer=300, max_inner=2000,
+                                               precision=prec, sync=False)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            return x, mihs.info_to_dict(info[0])[0], e0.elapsed_time(e1), e1.elapsed_time(e2)
+        times, outs = timed(step, args.steps, args.warmup, None)
+        x, info, sk, sv = outs[-1]
+        err = float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs))
+        out[prec] = dict(ms=float(np.mean(times)), sketch_ms=sk, solve_ms=sv, info=info, err=err)
+        log(f"  {prec}: {out[prec]['ms']:.2f} ms (sketch {sk:.2f}, solve {sv:.2f}); outer "
+            f"{info['outer_iters']}, inner {info['inner_iters_total']}; err {err:.2e}")
+    mx = out["mixed"]
+    pass_bytes = w.d * w.n * 8
+    cg_bytes = w.n * w.n * 4
+    algo = mx["info"]["outer_iters"] * pass_bytes + mx["info"]["inner_iters_total"] * cg_bytes
+    achieved = algo / (mx["solve_ms"] * 1e-3) / 1e9
+    return {
+        "metric": "time-to-1e-10 rel.err per under-determined ridge solve (Dual M-IHS, mixed; "
+                  "SRHT sketch + solve)",
+        "value": round(mx["ms"], 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(mx["ms"], 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 outer / f32 inner",
+        "data": "synthetic", "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m,
+                                        "sd": w.sd_target, "lambda": lam, "tol": args.tol},
+        "plain_fp64_ms": round(out["plain"]["ms"], 3),
+        "mixed": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in mx.items()},
+        "plain": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in out["plain"].items()},
+        "roofline": {"bound": "hbm", "kernel": "solve_kernel on A^T (mixed)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "accuracy_ok": mx["err"] <= 1e-10 and out["plain"]["err"] <= 1e-10,
+    }
+
+
 def run_small(args):
     import numpy as np
     import torch
@@ -359,14 +421,15 @@ def main():
         return
     if args.tol is None:
         args.tol = DEFAULT_TOL.get(args.workload, 5e-11)
-    if args.workload in ("batched_lambda_path", "diff_2p18x1024", "small_gauss"):
+    if args.workload in ("batched_lambda_path", "diff_2p18x1024", "small_gauss",
+                         "dual_4096x2p16"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
             sys.exit(2)
         import paper_1912_03514_amd as mihs
         mihs.load_library()
         fn = {"batched_lambda_path": run_batched, "diff_2p18x1024": run_diff,
-              "small_gauss": run_small}[args.workload]
+              "small_gauss": run_small, "dual_4096x2p16": run_dual}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:

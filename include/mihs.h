@@ -159,6 +159,36 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
                void* stream);
 
 /* ------------------------------------------------------------------------
+ * Dual M-IHS (Algorithm 2; Section 2, eqs. (intro_dual), (dual_mihs1)) for an
+ * under-determined problem, n <= d.  The dual variable nu lives in R^n; the
+ * caller passes At = A^T (d x n, row-major) -- the tall matrix each iteration
+ * streams -- and SAt = S A^T (m x n) from mihs_sketch on At.  Per iteration:
+ *   g^i      = b - A A^T nu^i - lambda nu^i                (FP64, one pass over At)
+ *   dnu^i    : ((S A^T)^T S A^T + lambda I) dnu = g^i by CG (as in mihs_solve)
+ *   nu^{i+1} = nu^i + alpha dnu^i + beta (nu^i - nu^{i-1})
+ * and finally X = A^T nu (eq. (dual_relation)).  The stop rule is mihs_solve's,
+ * applied to nu; momentum from Corollary 4 with sd(A) and m.
+ *
+ * At      device, d x n (a_dtype), row stride ldat (16-byte aligned rows); n <= d.
+ * b       device, n doubles.
+ * SAt     device, m x n sketch of At with the same `precision`.
+ * NU      device, n doubles: in = nu^1 (zeros for Algorithm 2), out = last iterate.
+ * X       device, d doubles: out = A^T nu.
+ * d_info  device, one mihs_info_t (iteration counts refer to nu).
+ * Errors as mihs_solve (n > d is MIHS_ERR_INVALID).  Workspace from
+ * mihs_solve_dual_workspace_size().
+ * ------------------------------------------------------------------------ */
+int mihs_solve_dual_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                                   mihs_precision_t precision, size_t* bytes);
+
+int mihs_solve_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, int64_t n,
+                    int64_t d, int64_t ldat, const double* b, double lambda, const void* SAt,
+                    int64_t m, int64_t ldsa, mihs_precision_t precision, double alpha,
+                    double beta, double eps_sub, double tol, int64_t max_outer,
+                    int64_t max_inner, double* NU, double* X, mihs_info_t* d_info,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Multi-RHS solve: k right-hand sides B (n x k, row stride ldb) with one
  * lambda, all sharing A and SA.  Algorithm 1 per column, the columns run in
  * blocks of 16 that share each pass over A and SA (FP64 matrix cores); needs

@@ -67,6 +67,10 @@ _SIGS = {
     "mihs_solve_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)]),
     "mihs_solve": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64, _int,
                           _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mihs_solve_dual_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)]),
+    "mihs_solve_dual": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64,
+                               _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp,
+                               _sz, _vp]),
     "mihs_solve_multi_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
                                                ctypes.POINTER(_sz)]),
     "mihs_solve_multi": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _vp,
@@ -246,6 +250,44 @@ def mihs_solve(A: torch.Tensor, b: torch.Tensor, lam: float, SA: torch.Tensor, a
         return x, workspace.info
     torch.cuda.synchronize(dev)
     return x, info_to_dict(workspace.info)[0]
+
+
+def mihs_solve_dual(At: torch.Tensor, b: torch.Tensor, lam: float, SAt: torch.Tensor,
+                    alpha: float, beta: float, eps_sub: float = 1e-2, tol: float = 1e-10,
+                    max_outer: int = 200, max_inner: int = 1000,
+                    nu0: Optional[torch.Tensor] = None, precision: Optional[str] = None,
+                    sync: bool = True):
+    """Dual M-IHS for n <= d (see include/mihs.h).  At is A^T (d x n), SAt its
+    sketch (m x n).  Returns (x, nu, info): x = A^T nu in R^d, nu in R^n."""
+    if precision is None:
+        precision = "mixed" if SAt.dtype == torch.float32 else "plain"
+    p = PRECISIONS[precision]
+    At = _row_aligned(At)
+    SAt = _row_aligned(SAt)
+    d, n = At.shape
+    m = SAt.shape[0]
+    dev = At.device
+    if b.dtype != torch.float64 or b.numel() != n or not b.is_contiguous():
+        raise MihsError("b must be a contiguous float64 vector of length n")
+    nu = torch.zeros(n, dtype=torch.float64, device=dev) if nu0 is None else nu0.clone()
+    x = torch.empty(d, dtype=torch.float64, device=dev)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    lib = load_library()
+    h = handle(dev.index)
+    ws_n = _sz()
+    _check(lib.mihs_solve_dual_workspace_size(h, n, d, m, p, ctypes.byref(ws_n)),
+           "mihs_solve_dual_workspace_size")
+    ws = _workspace(ws_n.value, dev)
+    rc = lib.mihs_solve_dual(h, At.data_ptr(), _dtype_code(At), n, d, At.stride(0), b.data_ptr(),
+                             float(lam), SAt.data_ptr(), m, SAt.stride(0), p, float(alpha),
+                             float(beta), float(eps_sub), float(tol), int(max_outer),
+                             int(max_inner), nu.data_ptr(), x.data_ptr(), info.data_ptr(),
+                             ws.data_ptr(), ws.numel(), _stream(dev))
+    _check(rc, "mihs_solve_dual")
+    if not sync:
+        return x, nu, (info, ws)
+    torch.cuda.synchronize(dev)
+    return x, nu, info_to_dict(info)[0]
 
 
 def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: torch.Tensor,

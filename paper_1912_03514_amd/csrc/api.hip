@@ -166,6 +166,61 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
   return mihs::launch_solve(handle, s, workspace, ws_bytes, as_stream(stream));
 }
 
+int mihs_solve_dual_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
+                                   mihs_precision_t precision, size_t* bytes) {
+  if (!handle || !bytes || n <= 0 || d <= 0 || m <= 0) return MIHS_ERR_INVALID;
+  // the iteration streams A^T (d x n): the tall solve with roles swapped
+  *bytes = mihs::solve_workspace_bytes(handle, d, n, m, precision == MIHS_MIXED);
+  return MIHS_OK;
+}
+
+int mihs_solve_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, int64_t n,
+                    int64_t d, int64_t ldat, const double* b, double lambda, const void* SAt,
+                    int64_t m, int64_t ldsa, mihs_precision_t precision, double alpha,
+                    double beta, double eps_sub, double tol, int64_t max_outer,
+                    int64_t max_inner, double* NU, double* X, mihs_info_t* d_info,
+                    void* workspace, size_t ws_bytes, void* stream) {
+  if (!handle) return MIHS_ERR_INVALID;
+  // A^T is d x n with d >= n: the same checks as a tall solve on A^T
+  int rc = check_solve_common(At, a_dtype, d, n, ldat, lambda, SAt, m, ldsa, precision, alpha,
+                              beta, eps_sub, max_outer, max_inner);
+  if (rc) return rc;
+  if (!b || !NU || !X || !d_info) return MIHS_ERR_INVALID;
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  size_t need = 0;
+  mihs_solve_dual_workspace_size(handle, n, d, m, precision, &need);
+  if (!workspace || ws_bytes < need) return MIHS_ERR_WORKSPACE;
+  hipStream_t st = as_stream(stream);
+  // g = b - A A^T nu - lambda nu is the adjoint-form gradient of the tall
+  // matrix A^T with right-hand side b and no data term
+  mihs::SolveDesc s;
+  s.A = At;
+  s.a_f32 = a_dtype == MIHS_F32;
+  s.n = d;
+  s.d = n;
+  s.lda = ldat;
+  s.b = nullptr;
+  s.rhs = b;
+  s.SA = SAt;
+  s.mixed = precision == MIHS_MIXED;
+  s.m = m;
+  s.ldsa = ldsa;
+  s.lam = lambda;
+  s.alpha = alpha;
+  s.beta = beta;
+  s.eps_sub = eps_sub;
+  s.tol = tol;
+  s.max_outer = max_outer;
+  s.max_inner = max_inner;
+  s.x = NU;
+  s.x_prev = nullptr;
+  s.info = d_info;
+  rc = mihs::launch_solve(handle, s, workspace, ws_bytes, st);
+  if (rc) return rc;
+  // x = A^T nu (eq. (dual_relation)): rows of A^T times nu
+  return mihs::launch_apply_rows(handle, At, a_dtype == MIHS_F32, d, n, ldat, NU, 1, X, 1, st);
+}
+
 static size_t backward_ws_bytes(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
                                 int64_t k, int mixed) {
   const size_t params = align_up(3 * 16 * sizeof(double), 256);

@@ -137,6 +137,37 @@ def make_problem_torch(n: int, d: int, sigma: np.ndarray, sd_target: float, seed
     return A, b.contiguous(), x0, lam
 
 
+def make_dual_problem(n: int, d: int, sigma: np.ndarray, sd_target: float, seed: int,
+                      a_dtype=np.float64):
+    """Under-determined instance (n <= d) for Dual M-IHS: A^T = G diag(sigma) Q with
+    G iid N(0,1)/sqrt(d) (d x n) and Q Haar (n x n) -- the tall recipe with the
+    roles of n and d swapped -- x0 ~ N(0, 1/d), b = A x0 + 1% noise.
+    Returns (At, b, lam) with At = A^T (d x n, row-major)."""
+    P = make_problem(d, n, sigma, sd_target, seed, a_dtype)
+    At = P.A
+    rng = np.random.default_rng(seed + 7919)
+    x0 = rng.standard_normal(d) / math.sqrt(d)
+    Ax0 = At.astype(np.float64).T @ x0
+    noise_var = 1e-4 * float(Ax0 @ Ax0) / n
+    b = Ax0 + rng.standard_normal(n) * math.sqrt(noise_var)
+    return At, b, P.lam
+
+
+def make_dual_problem_torch(n: int, d: int, sigma: np.ndarray, sd_target: float, seed: int,
+                            device, a_dtype: str = "f64"):
+    """The same recipe drawn on a device (sizes where the host draw is slow).
+    Returns (At, b, lam) as torch tensors on `device` (lam a float)."""
+    import torch
+    At, _, _, lam = make_problem_torch(d, n, sigma, sd_target, seed, device, a_dtype)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 7919)
+    x0 = torch.randn(d, generator=g, dtype=torch.float64, device=device) / math.sqrt(d)
+    Ax0 = At.to(torch.float64).T @ x0
+    noise_var = 1e-4 * float((Ax0 * Ax0).sum()) / n
+    b = Ax0 + torch.randn(n, generator=g, dtype=torch.float64, device=device) * math.sqrt(noise_var)
+    return At, b.contiguous(), lam
+
+
 @dataclasses.dataclass
 class Workload:
     name: str
@@ -153,10 +184,11 @@ class Workload:
     data_seed: int = 0
     sketch_seed: int = 7
     nrhs: int = 1
+    dual: bool = False      # under-determined (n <= d): Dual M-IHS on A^T
 
     @property
     def sigma(self) -> np.ndarray:
-        return sigma_profile(self.sigma_kind, self.d, self.sigma_rate)
+        return sigma_profile(self.sigma_kind, min(self.n, self.d), self.sigma_rate)
 
     @property
     def lam(self) -> float:
@@ -172,9 +204,10 @@ class Workload:
                             np.float64 if self.a_dtype == "f64" else np.float32, self.nrhs)
 
 
-# The five workloads: a small one that the oracle finishes in seconds, the
-# headline SRHT one, a CountSketch->Gaussian two-stage one with FP32 A, a
-# batched lambda-path one (see batched_specs) and a multi-RHS differentiation one.
+# The workloads: a small one that the oracle finishes in seconds, the headline
+# SRHT one, a CountSketch->Gaussian two-stage one with FP32 A, a batched
+# lambda-path one (see batched_specs), a multi-RHS differentiation one and an
+# under-determined one for Dual M-IHS.
 WORKLOADS = {
     "small_gauss": Workload("small_gauss", 4096, 256, "f64", "exp", 6.0, 64.0, "gaussian", 256,
                             eps_sub=1e-8, data_seed=0, sketch_seed=7),
@@ -187,6 +220,9 @@ WORKLOADS = {
                                 sketch_seed=9),
     "diff_2p18x1024": Workload("diff_2p18x1024", 1 << 18, 1024, "f32", "exp", 8.0, 256.0, "srht",
                                1024, eps_sub=1e-2, data_seed=4000, sketch_seed=11, nrhs=64),
+    # under-determined, shaped like Figure 4's (n, d, m, sd) = (4000, 2^16, 4000, 462)
+    "dual_4096x2p16": Workload("dual_4096x2p16", 4096, 1 << 16, "f64", "exp", 8.0, 462.0, "srht",
+                               4096, eps_sub=1e-1, data_seed=5000, sketch_seed=12, dual=True),
 }
 
 

@@ -61,6 +61,16 @@ def srht_signs(n: int, seed: int) -> np.ndarray:
     return np.where((h >> np.uint32(31)) != 0, -1.0, 1.0)
 
 
+def rademacher_probes(d: int, T: int, seed: int) -> np.ndarray:
+    """Algorithm 5's probe vectors v^1..v^T in {-1, +1}^d as a d x T matrix:
+    entry (j, l) is -1 iff bit 31 of murmur3(l * d + j, seed) is set (the same
+    counter-based rule as the SRHT signs)."""
+    idx = (np.arange(T, dtype=np.uint64)[None, :] * np.uint64(d)
+           + np.arange(d, dtype=np.uint64)[:, None])
+    h = murmur3_32(idx.ravel(), seed).reshape(d, T)
+    return np.where((h >> np.uint32(31)) != 0, -1.0, 1.0)
+
+
 def srht_rows(m: int, n: int, seed: int) -> np.ndarray:
     if n & (n - 1):
         raise ValueError("SRHT needs n to be a power of two")

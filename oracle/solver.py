@@ -23,6 +23,9 @@ forcing term), and AAb_Solver (Algorithm 6, Section 3.5).
 Dual M-IHS (Section 2, eqs. (intro_dual), (dual_mihs1); Algorithm 2) for
 n <= d iterates on the dual variable nu in R^n with a sketch of A^T and
 recovers x* = A^T nu* (eq. (dual_relation)).
+
+The statistical dimension that sets beta can be estimated from the sketch by
+the inexact Hutchinson trace estimator (Algorithm 5, Section 3.4).
 """
 from __future__ import annotations
 
@@ -265,6 +268,39 @@ def mihs(A: np.ndarray, b: np.ndarray, lam: float, SA: np.ndarray, alpha: float,
             break
     return MihsResult(x=x, outer=it, inner=inner_counts, steps=steps, converged=converged,
                       history=hist)
+
+
+# ----------------------------------------------------------------------------
+# Statistical dimension estimate (Algorithm 5)
+# ----------------------------------------------------------------------------
+def sketched_sd_exact(SA: np.ndarray, lam: float) -> float:
+    """The quantity Algorithm 5 estimates, d - lambda tr(((SA)^T SA + lambda I)^{-1})
+    = sum_i mu_i / (mu_i + lambda) over the eigenvalues mu_i of (SA)^T SA."""
+    mu = np.linalg.eigvalsh(SA.astype(np.float64).T @ SA.astype(np.float64))
+    return float(np.sum(mu / (mu + lam)))
+
+
+def hutchinson_sd(SA: np.ndarray, lam: float, V: np.ndarray, *, inner: str = "aab",
+                  eps_tr: float = 0.5, max_inner: Optional[int] = None) -> float:
+    """Inexact Hutchinson estimate of sd (Algorithm 5): for each probe column v^l
+    of V (d x T), z^l solves ((SA)^T SA + lambda I) z = v^l to relative residual
+    eps_tr (AAb_Solver in the paper; CG or exact here as well); tau accumulates
+    lambda <v^l, z^l>; the estimate is d - tau / T."""
+    d, T = V.shape
+    exact = inner_exact_factory(SA, lam) if inner == "exact" else None
+    tau = 0.0
+    for l in range(T):
+        v = V[:, l]
+        if inner == "exact":
+            z, _ = exact(v)
+        elif inner == "cg":
+            z, _ = inner_cg(SA, v, lam, eps_tr, max_inner)
+        elif inner == "aab":
+            z, _ = aab_solver(SA, v, lam, eps_tr, max_inner)
+        else:
+            raise ValueError(inner)
+        tau += lam * float(v @ z)
+    return d - tau / T
 
 
 # ----------------------------------------------------------------------------

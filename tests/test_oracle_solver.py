@@ -254,3 +254,44 @@ def test_dual_planted_mistake_is_caught(monkeypatch):
     monkeypatch.setattr(O, "dual_gradient", lambda A_, b_, l_, nu: b_ - A_ @ (A_.T @ nu))
     r = O.dual_mihs(A, b, lam, SAt, a, bt, inner="exact", n_iter=80)
     assert np.linalg.norm(r.x - xs) > 1e-6 * np.linalg.norm(xs)
+
+
+def test_hutchinson_exact_with_hadamard_probes():
+    """Hadamard columns as probes (T = d, H H^T = d I): sum_l h_l^T M h_l = d tr(M),
+    so Algorithm 5 with exact inner solves returns d - lambda tr(M^{-1}) exactly.
+    With S = I that is sd(A) = sum sigma^2 / (sigma^2 + lambda) (Section 3.4)."""
+    from scipy.linalg import hadamard
+    P = _small(d=64)
+    d = P.A.shape[1]
+    assert d & (d - 1) == 0
+    H = hadamard(d).astype(np.float64)
+    SA = sketches.gaussian_sketch(P.A, 96, 3)
+    est = O.hutchinson_sd(SA, P.lam, H, inner="exact")
+    assert abs(est - O.sketched_sd_exact(SA, P.lam)) <= 1e-9 * d
+    est_a = O.hutchinson_sd(P.A, P.lam, H, inner="exact")
+    assert abs(est_a - O.statistical_dimension(P.A, P.lam)) <= 1e-9 * d
+
+
+def test_hutchinson_random_probes_are_unbiased():
+    """Rademacher probes from the counter-based rule: +-1 entries, and the mean
+    of many single-probe estimates lies within 4 standard errors of the exact
+    sketched quantity."""
+    P = _small()
+    d = P.A.shape[1]
+    V = sketches.rademacher_probes(d, 400, 11)
+    assert set(np.unique(V)) == {-1.0, 1.0}
+    assert abs(V.mean()) < 0.02
+    SA = sketches.gaussian_sketch(P.A, 96, 3)
+    ests = np.array([O.hutchinson_sd(SA, P.lam, V[:, l:l + 1], inner="exact") for l in range(400)])
+    se = ests.std(ddof=1) / math.sqrt(len(ests))
+    assert abs(ests.mean() - O.sketched_sd_exact(SA, P.lam)) <= 4 * se
+
+
+def test_hutchinson_inexact_inner_solvers_agree():
+    """eps_tr small: AAb_Solver, CG and the exact solve give the same estimate."""
+    P = _small()
+    V = sketches.rademacher_probes(P.A.shape[1], 3, 5)
+    SA = sketches.gaussian_sketch(P.A, 96, 3)
+    ex = O.hutchinson_sd(SA, P.lam, V, inner="exact")
+    for inner in ("aab", "cg"):
+        assert abs(O.hutchinson_sd(SA, P.lam, V, inner=inner, eps_tr=1e-12) - ex) <= 1e-8 * abs(ex)

@@ -526,6 +526,27 @@ def main():
             f"{np.mean(sv):.2f}); outer {infos[-1]['outer_iters']}, inner "
             f"{infos[-1]['inner_iters_total']}; max err {max(errs):.2e}")
 
+    def sd_estimate(precision, T=2, eps_tr=0.5, reps=5):
+        """Algorithm 5 on this workload's sketch (the paper's T = 2, eps_tr = 0.5):
+        the estimate, its inner CG steps and its time next to one outer iteration."""
+        SA = mihs.mihs_sketch(A, w.sketch, w.m, w.sketch_seed, precision=precision, m2=w.m2)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            torch.cuda.synchronize()
+            e0.record(stream)
+            est, infos = mihs.mihs_estimate_sd(SA, lam, T=T, seed=17, eps_tr=eps_tr)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return {"estimate": round(est, 2), "T": T, "eps_tr": eps_tr,
+                "inner_iters": [i["inner_iters_total"] for i in infos],
+                "ms": round(float(np.mean(ts[1:])), 3)}
+
+    log("statistical dimension estimate (Algorithm 5)")
+    sd_est = {p: sd_estimate(p) for p in ("mixed", "plain")}
+    log(f"  {sd_est}")
+
     mx, pl = out["mixed"], out["plain"]
     info = mx["infos"][-1]
     s_a = 8 if w.a_dtype == "f64" else 4
@@ -565,6 +586,9 @@ def main():
                   "inner_iters": pl["infos"][-1]["inner_iters_total"],
                   "max_rel_err": max(pl["errs"])},
         "a_pass_bytes": apass_bytes,
+        "sd_estimate": {"sd_true": w.sd_target, "m": w.m_out,
+                        "mixed_solve_ms_per_outer_iter": round(mx["solve_ms"] / max(1, outer), 3),
+                        **{p: v for p, v in sd_est.items()}},
         "roofline": {"bound": "hbm", "kernel": "solve_kernel (mixed)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

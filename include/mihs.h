@@ -189,6 +189,38 @@ int mihs_solve_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, 
                     void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Statistical dimension estimate from a sketch: the inexact Hutchinson trace
+ * estimator of Section 3.4 (Algorithm 5),
+ *   sd ~ d - (lambda / T) sum_{l<T} <v^l, z^l>,
+ *   ((SA)^T SA + lambda I) z^l = v^l solved to ||r|| <= eps_tr ||v^l||,
+ * which estimates d - lambda tr(((SA)^T SA + lambda I)^{-1}), the statistical
+ * dimension sum sigma_i^2 / (sigma_i^2 + lambda) seen through the sketch; its
+ * value sets beta = sd / m in Corollary 4.  The paper uses T = 2 or 3 and
+ * eps_tr = 0.5.
+ *
+ * SA        m x d, row stride ldsa (device; double for PLAIN_FP64, float for
+ *           MIXED, whose inner CG then runs in float).  Any m >= 1.
+ * T, seed   the probes: entry j of probe l (0 <= j < d, 0 <= l < T) is -1 if
+ *           bit 31 of MurmurHash3_x86_32(l * d + j mod 2^32, seed) is set,
+ *           else +1.  T <= 2^20.
+ * eps_tr    relative residual of each inner CG (conjugate gradients from
+ *           z = 0; the paper's AAb_Solver would stop at a different iterate).
+ * sd        one device double, the estimate.
+ * Z         optional (NULL to skip): T x d row-major doubles, z^l in row l.
+ * d_info    T device records: inner_iters_total = CG steps of probe l,
+ *           status MIHS_CONVERGED or MIHS_BREAKDOWN.
+ * Needs d <= 4096 (MIHS_ERR_UNSUPPORTED otherwise); the workspace size comes
+ * from mihs_estimate_sd_workspace_size().
+ * ------------------------------------------------------------------------ */
+int mihs_estimate_sd_workspace_size(mihs_handle_t handle, int64_t m, int64_t d, int64_t T,
+                                    mihs_precision_t precision, size_t* bytes);
+
+int mihs_estimate_sd(mihs_handle_t handle, const void* SA, int64_t m, int64_t d, int64_t ldsa,
+                     mihs_precision_t precision, double lambda, int64_t T, uint32_t seed,
+                     double eps_tr, int64_t max_inner, double* sd, double* Z,
+                     mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Multi-RHS solve: k right-hand sides B (n x k, row stride ldb) with one
  * lambda, all sharing A and SA.  Algorithm 1 per column, the columns run in
  * blocks of 16 that share each pass over A and SA (FP64 matrix cores); needs

@@ -71,6 +71,10 @@ _SIGS = {
     "mihs_solve_dual": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64,
                                _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp,
                                _sz, _vp]),
+    "mihs_estimate_sd_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int,
+                                               ctypes.POINTER(_sz)]),
+    "mihs_estimate_sd": (_int, [_vp, _vp, _i64, _i64, _i64, _int, _dbl, _i64, ctypes.c_uint32,
+                                _dbl, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "mihs_solve_multi_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
                                                ctypes.POINTER(_sz)]),
     "mihs_solve_multi": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _vp,
@@ -288,6 +292,38 @@ def mihs_solve_dual(At: torch.Tensor, b: torch.Tensor, lam: float, SAt: torch.Te
         return x, nu, (info, ws)
     torch.cuda.synchronize(dev)
     return x, nu, info_to_dict(info)[0]
+
+
+def mihs_estimate_sd(SA: torch.Tensor, lam: float, T: int = 2, seed: int = 0,
+                     eps_tr: float = 0.5, max_inner: int = 1000,
+                     precision: Optional[str] = None, want_z: bool = False):
+    """Inexact Hutchinson estimate of the statistical dimension from a sketch SA
+    (m x d), Algorithm 5 (see include/mihs.h).  Returns (sd, infos) or, with
+    want_z, (sd, Z, infos) where row l of Z (T x d) solves
+    ((SA)^T SA + lambda I) z = v^l."""
+    if precision is None:
+        precision = "mixed" if SA.dtype == torch.float32 else "plain"
+    p = PRECISIONS[precision]
+    SA = _row_aligned(SA)
+    m, d = SA.shape
+    dev = SA.device
+    sd = torch.zeros((), dtype=torch.float64, device=dev)
+    Z = torch.empty((T, d), dtype=torch.float64, device=dev) if want_z else None
+    info = torch.zeros(INFO_BYTES * T, dtype=torch.uint8, device=dev)
+    lib = load_library()
+    h = handle(dev.index)
+    ws_n = _sz()
+    _check(lib.mihs_estimate_sd_workspace_size(h, m, d, int(T), p, ctypes.byref(ws_n)),
+           "mihs_estimate_sd_workspace_size")
+    ws = _workspace(ws_n.value, dev)
+    rc = lib.mihs_estimate_sd(h, SA.data_ptr(), m, d, SA.stride(0), p, float(lam), int(T),
+                              int(seed) & 0xFFFFFFFF, float(eps_tr), int(max_inner),
+                              sd.data_ptr(), Z.data_ptr() if Z is not None else None,
+                              info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))
+    _check(rc, "mihs_estimate_sd")
+    torch.cuda.synchronize(dev)
+    infos = info_to_dict(info)
+    return (float(sd), Z, infos) if want_z else (float(sd), infos)
 
 
 def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: torch.Tensor,

@@ -221,6 +221,32 @@ int mihs_solve_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, 
   return mihs::launch_apply_rows(handle, At, a_dtype == MIHS_F32, d, n, ldat, NU, 1, X, 1, st);
 }
 
+int mihs_estimate_sd_workspace_size(mihs_handle_t handle, int64_t m, int64_t d, int64_t T,
+                                    mihs_precision_t precision, size_t* bytes) {
+  if (!handle || !bytes || m <= 0 || d <= 0 || T <= 0) return MIHS_ERR_INVALID;
+  *bytes = mihs::estimate_workspace_bytes(handle, m, d, T, precision == MIHS_MIXED);
+  return MIHS_OK;
+}
+
+int mihs_estimate_sd(mihs_handle_t handle, const void* SA, int64_t m, int64_t d, int64_t ldsa,
+                     mihs_precision_t precision, double lambda, int64_t T, uint32_t seed,
+                     double eps_tr, int64_t max_inner, double* sd, double* Z,
+                     mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream) {
+  if (!handle) return MIHS_ERR_INVALID;
+  if (precision != MIHS_PLAIN_FP64 && precision != MIHS_MIXED) return MIHS_ERR_INVALID;
+  const int mixed = precision == MIHS_MIXED;
+  if (!valid_matrix(SA, m, d, ldsa, mixed)) return MIHS_ERR_INVALID;
+  if (!(lambda > 0.0) || !isfinite(lambda)) return MIHS_ERR_INVALID;
+  if (T < 1 || T > (int64_t)1 << 20 || !(eps_tr >= 0.0) || !isfinite(eps_tr) || max_inner < 1)
+    return MIHS_ERR_INVALID;
+  if (!sd || !d_info) return MIHS_ERR_INVALID;
+  if (d > 4096) return MIHS_ERR_UNSUPPORTED;
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  return mihs::launch_estimate_sd(handle, SA, m, d, ldsa, mixed, lambda, T, seed, eps_tr,
+                                  max_inner, sd, Z, d_info, workspace, ws_bytes,
+                                  as_stream(stream));
+}
+
 static size_t backward_ws_bytes(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
                                 int64_t k, int mixed) {
   const size_t params = align_up(3 * 16 * sizeof(double), 256);

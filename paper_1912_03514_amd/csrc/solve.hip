@@ -699,14 +699,14 @@ int max_grid(const mihs_handle* h) { return h->num_cu * kMaxBlocksPerCU; }
 // Size of the inner-solve subgroup: enough workgroups to stream SA quickly,
 // few enough that its barrier stays cheap (the barrier cost grows steeply
 // with the number of participants).  MIHS_CG_GROUPS overrides (tuning).
-int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G) {
+int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G, bool gram) {
   const char* env = getenv("MIHS_CG_GROUPS");
   int gc;
   if (env && atoi(env) > 0) {
     gc = atoi(env);
   } else {
     // bytes one CG step streams: the Gram matrix (m >= d) or SA
-    const double mb = (double)(m >= d ? d : m) * (double)d * sa_bytes / (1024.0 * 1024.0);
+    const double mb = (double)(gram ? d : m) * (double)d * sa_bytes / (1024.0 * 1024.0);
     gc = mb >= 8.0 ? 128 : (mb >= 4.0 ? 64 : (mb >= 1.0 ? 32 : 16));
     // each CG workgroup should own at least a few rows
     const int64_t by_rows = (m + 3) / 4;
@@ -725,17 +725,18 @@ int ept_for(int64_t d) {
   return e;
 }
 
-size_t solve_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int mixed) {
+size_t solve_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int mixed,
+                             int no_gram) {
   (void)n;
   const int G = max_grid(h);
-  return layout(G, G, dpad_for(d), gram_bytes_for(m, d, mixed)).total;
+  return layout(G, G, dpad_for(d), no_gram ? 0 : gram_bytes_for(m, d, mixed)).total;
 }
 
 int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_bytes,
                  hipStream_t stream) {
   const int ept = ept_for(s.d);
   if (ept > 64) return MIHS_ERR_UNSUPPORTED;
-  const bool gram = use_gram(s.m, s.d);
+  const bool gram = !s.no_gram && use_gram(s.m, s.d);
   SolveKernel kern = gram ? pick_kernel<true>(s.a_f32, s.mixed, ept)
                           : pick_kernel<false>(s.a_f32, s.mixed, ept);
   if (!kern) return MIHS_ERR_UNSUPPORTED;
@@ -748,7 +749,7 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   for (int occ_try = kMaxBlocksPerCU; occ_try >= 1; --occ_try) {
     int g = h->num_cu * occ_try;
     if ((int64_t)g > g_rows) g = (int)(g_rows < 1 ? 1 : g_rows);
-    const int gc = pick_cg_groups(s.m, s.d, s.mixed ? 4 : 8, g);
+    const int gc = pick_cg_groups(s.m, s.d, s.mixed ? 4 : 8, g, gram);
     const int cp = (int)((s.d + gc - 1) / gc);
     const size_t sh = (2 * (size_t)dpad + 6 * (size_t)cp + kBlock) * sizeof(double);
     if (sh > 160 * 1024) continue;
@@ -767,7 +768,7 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
     }
   }
   if (G == 0) return MIHS_ERR_UNSUPPORTED;
-  const SolveLayout L = layout(G, Gc, dpad, gram_bytes_for(s.m, s.d, s.mixed));
+  const SolveLayout L = layout(G, Gc, dpad, gram ? gram_bytes_for(s.m, s.d, s.mixed) : 0);
   if (ws_bytes < L.total || ws == nullptr) return MIHS_ERR_WORKSPACE;
 
   char* base = (char*)ws;

@@ -60,6 +60,16 @@ typedef enum {
  * outer loop refines the inexact inner steps to full FP64 accuracy. */
 typedef enum { MIHS_PLAIN_FP64 = 0, MIHS_MIXED = 1 } mihs_precision_t;
 
+/* Inner solver of ((SA)^T SA + lambda I) z = g.
+ * CG:  conjugate gradients from z = 0, stopped when ||r|| <= eps ||g||; applied
+ *      through the Gram matrix (SA)^T SA when m >= d, else by streaming SA.
+ * AAB: AAb_Solver (Algorithm 6, Section 3.5): Golub-Kahan bidiagonalisation of
+ *      SA started from g, with the sqrt(lambda) I block folded in by Givens
+ *      rotations; stopped when its residual estimate |phi rhobar| / ||g|| falls
+ *      below eps (the paper's stable alternative to CG on the explicit
+ *      (SA)^T SA, Section 3.1).  Always streams SA (one pass per step). */
+typedef enum { MIHS_INNER_CG = 0, MIHS_INNER_AAB = 1 } mihs_inner_t;
+
 enum {
   MIHS_OK = 0,
   MIHS_ERR_INVALID = -1,
@@ -158,6 +168,16 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
                double* X_prev, mihs_info_t* d_info, void* workspace, size_t ws_bytes,
                void* stream);
 
+/* mihs_solve with a choice of inner solver (mihs_inner_t); MIHS_INNER_CG is
+ * mihs_solve itself.  With MIHS_INNER_AAB, eps_sub bounds AAb_Solver's residual
+ * estimate and d_info's inner counts are AAb steps.  Same workspace size. */
+int mihs_solve_inner(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                     int64_t d, int64_t lda, const double* b, double lambda, const void* SA,
+                     int64_t m, int64_t ldsa, mihs_precision_t precision, mihs_inner_t inner,
+                     double alpha, double beta, double eps_sub, double tol, int64_t max_outer,
+                     int64_t max_inner, double* X, double* X_prev, mihs_info_t* d_info,
+                     void* workspace, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Dual M-IHS (Algorithm 2; Section 2, eqs. (intro_dual), (dual_mihs1)) for an
  * under-determined problem, n <= d.  The dual variable nu lives in R^n; the
@@ -203,11 +223,12 @@ int mihs_solve_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, 
  * T, seed   the probes: entry j of probe l (0 <= j < d, 0 <= l < T) is -1 if
  *           bit 31 of MurmurHash3_x86_32(l * d + j mod 2^32, seed) is set,
  *           else +1.  T <= 2^20.
- * eps_tr    relative residual of each inner CG (conjugate gradients from
- *           z = 0; the paper's AAb_Solver would stop at a different iterate).
+ * inner     the inner solver: MIHS_INNER_AAB is the paper's AAb_Solver (stops
+ *           when its residual estimate falls below eps_tr), MIHS_INNER_CG is
+ *           CG from z = 0 stopped at ||r|| <= eps_tr ||v^l||.
  * sd        one device double, the estimate.
  * Z         optional (NULL to skip): T x d row-major doubles, z^l in row l.
- * d_info    T device records: inner_iters_total = CG steps of probe l,
+ * d_info    T device records: inner_iters_total = inner steps of probe l,
  *           status MIHS_CONVERGED or MIHS_BREAKDOWN.
  * Needs d <= 4096 (MIHS_ERR_UNSUPPORTED otherwise); the workspace size comes
  * from mihs_estimate_sd_workspace_size().
@@ -216,8 +237,8 @@ int mihs_estimate_sd_workspace_size(mihs_handle_t handle, int64_t m, int64_t d, 
                                     mihs_precision_t precision, size_t* bytes);
 
 int mihs_estimate_sd(mihs_handle_t handle, const void* SA, int64_t m, int64_t d, int64_t ldsa,
-                     mihs_precision_t precision, double lambda, int64_t T, uint32_t seed,
-                     double eps_tr, int64_t max_inner, double* sd, double* Z,
+                     mihs_precision_t precision, mihs_inner_t inner, double lambda, int64_t T,
+                     uint32_t seed, double eps_tr, int64_t max_inner, double* sd, double* Z,
                      mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmihs.so")
 F64, F32 = 0, 1
 SKETCH_KINDS = {"gaussian": 0, "srht": 1, "countsketch": 2, "count_gauss": 3}
 PRECISIONS = {"plain": 0, "fp64": 0, "mixed": 1}
+INNER_SOLVERS = {"cg": 0, "aab": 1}
 
 MIHS_OK = 0
 STATUS_NAMES = {0: "converged", 1: "max_iter", -5: "breakdown", -6: "barrier_timeout"}
@@ -67,14 +68,17 @@ _SIGS = {
     "mihs_solve_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)]),
     "mihs_solve": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64, _int,
                           _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mihs_solve_inner": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64,
+                                _int, _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp,
+                                _vp, _sz, _vp]),
     "mihs_solve_dual_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)]),
     "mihs_solve_dual": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64,
                                _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp,
                                _sz, _vp]),
     "mihs_estimate_sd_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int,
                                                ctypes.POINTER(_sz)]),
-    "mihs_estimate_sd": (_int, [_vp, _vp, _i64, _i64, _i64, _int, _dbl, _i64, ctypes.c_uint32,
-                                _dbl, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mihs_estimate_sd": (_int, [_vp, _vp, _i64, _i64, _i64, _int, _int, _dbl, _i64,
+                                ctypes.c_uint32, _dbl, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "mihs_solve_multi_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
                                                ctypes.POINTER(_sz)]),
     "mihs_solve_multi": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _vp,
@@ -225,12 +229,15 @@ def mihs_solve(A: torch.Tensor, b: torch.Tensor, lam: float, SA: torch.Tensor, a
                beta: float, eps_sub: float = 1e-2, tol: float = 1e-10, max_outer: int = 200,
                max_inner: int = 1000, x0: Optional[torch.Tensor] = None,
                x_prev: Optional[torch.Tensor] = None, precision: Optional[str] = None,
-               workspace: Optional[SolveWorkspace] = None, sync: bool = True):
-    """M-IHS on the GPU (see include/mihs.h).  Returns (x, info) where info is a
-    dict (sync=True) or the raw device record (sync=False)."""
+               workspace: Optional[SolveWorkspace] = None, sync: bool = True,
+               inner: str = "cg"):
+    """M-IHS on the GPU (see include/mihs.h); inner is "cg" or "aab" (AAb_Solver,
+    Algorithm 6).  Returns (x, info) where info is a dict (sync=True) or the raw
+    device record (sync=False)."""
     if precision is None:
         precision = "mixed" if SA.dtype == torch.float32 else "plain"
     p = PRECISIONS[precision]
+    inn = INNER_SOLVERS[inner]
     A = _row_aligned(A)
     SA = _row_aligned(SA)
     n, d = A.shape
@@ -242,14 +249,14 @@ def mihs_solve(A: torch.Tensor, b: torch.Tensor, lam: float, SA: torch.Tensor, a
     if workspace is None:
         workspace = SolveWorkspace(n, d, m, precision, dev)
     lib = load_library()
-    rc = lib.mihs_solve(workspace.h, A.data_ptr(), _dtype_code(A), n, d, A.stride(0),
-                        b.data_ptr(), float(lam), SA.data_ptr(), m, SA.stride(0), p,
-                        float(alpha), float(beta), float(eps_sub), float(tol), int(max_outer),
-                        int(max_inner), x.data_ptr(),
-                        x_prev.data_ptr() if x_prev is not None else None,
-                        workspace.info.data_ptr(), workspace.ws.data_ptr(), workspace.ws.numel(),
-                        _stream(dev))
-    _check(rc, "mihs_solve")
+    rc = lib.mihs_solve_inner(workspace.h, A.data_ptr(), _dtype_code(A), n, d, A.stride(0),
+                              b.data_ptr(), float(lam), SA.data_ptr(), m, SA.stride(0), p, inn,
+                              float(alpha), float(beta), float(eps_sub), float(tol),
+                              int(max_outer), int(max_inner), x.data_ptr(),
+                              x_prev.data_ptr() if x_prev is not None else None,
+                              workspace.info.data_ptr(), workspace.ws.data_ptr(),
+                              workspace.ws.numel(), _stream(dev))
+    _check(rc, "mihs_solve_inner")
     if not sync:
         return x, workspace.info
     torch.cuda.synchronize(dev)
@@ -296,14 +303,16 @@ def mihs_solve_dual(At: torch.Tensor, b: torch.Tensor, lam: float, SAt: torch.Te
 
 def mihs_estimate_sd(SA: torch.Tensor, lam: float, T: int = 2, seed: int = 0,
                      eps_tr: float = 0.5, max_inner: int = 1000,
-                     precision: Optional[str] = None, want_z: bool = False):
+                     precision: Optional[str] = None, want_z: bool = False,
+                     inner: str = "aab"):
     """Inexact Hutchinson estimate of the statistical dimension from a sketch SA
-    (m x d), Algorithm 5 (see include/mihs.h).  Returns (sd, infos) or, with
-    want_z, (sd, Z, infos) where row l of Z (T x d) solves
-    ((SA)^T SA + lambda I) z = v^l."""
+    (m x d), Algorithm 5 (see include/mihs.h); inner is "aab" (AAb_Solver, the
+    paper's choice) or "cg".  Returns (sd, infos) or, with want_z, (sd, Z, infos)
+    where row l of Z (T x d) solves ((SA)^T SA + lambda I) z = v^l."""
     if precision is None:
         precision = "mixed" if SA.dtype == torch.float32 else "plain"
     p = PRECISIONS[precision]
+    inn = INNER_SOLVERS[inner]
     SA = _row_aligned(SA)
     m, d = SA.shape
     dev = SA.device
@@ -316,7 +325,7 @@ def mihs_estimate_sd(SA: torch.Tensor, lam: float, T: int = 2, seed: int = 0,
     _check(lib.mihs_estimate_sd_workspace_size(h, m, d, int(T), p, ctypes.byref(ws_n)),
            "mihs_estimate_sd_workspace_size")
     ws = _workspace(ws_n.value, dev)
-    rc = lib.mihs_estimate_sd(h, SA.data_ptr(), m, d, SA.stride(0), p, float(lam), int(T),
+    rc = lib.mihs_estimate_sd(h, SA.data_ptr(), m, d, SA.stride(0), p, inn, float(lam), int(T),
                               int(seed) & 0xFFFFFFFF, float(eps_tr), int(max_inner),
                               sd.data_ptr(), Z.data_ptr() if Z is not None else None,
                               info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))

@@ -135,7 +135,19 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
                double eps_sub, double tol, int64_t max_outer, int64_t max_inner, double* X,
                double* X_prev, mihs_info_t* d_info, void* workspace, size_t ws_bytes,
                void* stream) {
+  return mihs_solve_inner(handle, A, a_dtype, n, d, lda, b, lambda, SA, m, ldsa, precision,
+                          MIHS_INNER_CG, alpha, beta, eps_sub, tol, max_outer, max_inner, X,
+                          X_prev, d_info, workspace, ws_bytes, stream);
+}
+
+int mihs_solve_inner(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                     int64_t d, int64_t lda, const double* b, double lambda, const void* SA,
+                     int64_t m, int64_t ldsa, mihs_precision_t precision, mihs_inner_t inner,
+                     double alpha, double beta, double eps_sub, double tol, int64_t max_outer,
+                     int64_t max_inner, double* X, double* X_prev, mihs_info_t* d_info,
+                     void* workspace, size_t ws_bytes, void* stream) {
   if (!handle) return MIHS_ERR_INVALID;
+  if (inner != MIHS_INNER_CG && inner != MIHS_INNER_AAB) return MIHS_ERR_INVALID;
   int rc = check_solve_common(A, a_dtype, n, d, lda, lambda, SA, m, ldsa, precision, alpha, beta,
                               eps_sub, max_outer, max_inner);
   if (rc) return rc;
@@ -163,6 +175,7 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
   s.x = X;
   s.x_prev = X_prev;
   s.info = d_info;
+  s.aab = inner == MIHS_INNER_AAB;
   return mihs::launch_solve(handle, s, workspace, ws_bytes, as_stream(stream));
 }
 
@@ -229,10 +242,11 @@ int mihs_estimate_sd_workspace_size(mihs_handle_t handle, int64_t m, int64_t d, 
 }
 
 int mihs_estimate_sd(mihs_handle_t handle, const void* SA, int64_t m, int64_t d, int64_t ldsa,
-                     mihs_precision_t precision, double lambda, int64_t T, uint32_t seed,
-                     double eps_tr, int64_t max_inner, double* sd, double* Z,
+                     mihs_precision_t precision, mihs_inner_t inner, double lambda, int64_t T,
+                     uint32_t seed, double eps_tr, int64_t max_inner, double* sd, double* Z,
                      mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream) {
   if (!handle) return MIHS_ERR_INVALID;
+  if (inner != MIHS_INNER_CG && inner != MIHS_INNER_AAB) return MIHS_ERR_INVALID;
   if (precision != MIHS_PLAIN_FP64 && precision != MIHS_MIXED) return MIHS_ERR_INVALID;
   const int mixed = precision == MIHS_MIXED;
   if (!valid_matrix(SA, m, d, ldsa, mixed)) return MIHS_ERR_INVALID;
@@ -242,9 +256,9 @@ int mihs_estimate_sd(mihs_handle_t handle, const void* SA, int64_t m, int64_t d,
   if (!sd || !d_info) return MIHS_ERR_INVALID;
   if (d > 4096) return MIHS_ERR_UNSUPPORTED;
   if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
-  return mihs::launch_estimate_sd(handle, SA, m, d, ldsa, mixed, lambda, T, seed, eps_tr,
-                                  max_inner, sd, Z, d_info, workspace, ws_bytes,
-                                  as_stream(stream));
+  return mihs::launch_estimate_sd(handle, SA, m, d, ldsa, mixed, inner == MIHS_INNER_AAB,
+                                  lambda, T, seed, eps_tr, max_inner, sd, Z, d_info, workspace,
+                                  ws_bytes, as_stream(stream));
 }
 
 static size_t backward_ws_bytes(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,

@@ -4,9 +4,9 @@
 // eps_tr.  The probes come from the counter-based rule the SRHT signs use
 // (entry j of probe l is -1 iff bit 31 of murmur3(l d + j, seed) is set); each
 // system is one step of the persistent solve kernel in right-hand-side mode
-// (matrix SA, x = 0, alpha = 1, beta = 0), whose inner CG streams SA on every
-// step: at eps_tr ~ 0.5 the CG takes a few steps, fewer reads of SA than
-// forming the Gram matrix would cost.
+// (matrix SA, x = 0, alpha = 1, beta = 0) whose inner solver (AAb_Solver as in
+// the paper, or CG) streams SA on every step: at eps_tr ~ 0.5 it takes a few
+// steps, fewer reads of SA than forming the Gram matrix would cost.
 #include "device_util.hpp"
 #include "internal.hpp"
 #include "rng.hpp"
@@ -70,7 +70,7 @@ size_t estimate_workspace_bytes(const mihs_handle* h, int64_t m, int64_t d, int6
 }
 
 int launch_estimate_sd(const mihs_handle* h, const void* SA, int64_t m, int64_t d, int64_t ldsa,
-                       int mixed, double lam, int64_t T, uint32_t seed, double eps_tr,
+                       int mixed, int aab, double lam, int64_t T, uint32_t seed, double eps_tr,
                        int64_t max_inner, double* sd, double* Zout, mihs_info_t* info,
                        void* ws, size_t ws_bytes, hipStream_t stream) {
   const EstLayout L = est_layout(h, m, d, T, mixed);
@@ -106,6 +106,7 @@ int launch_estimate_sd(const mihs_handle* h, const void* SA, int64_t m, int64_t 
     s.x_prev = nullptr;
     s.info = info + l;
     s.no_gram = 1;
+    s.aab = aab;
     const int rc = launch_solve(h, s, base + L.solve, L.total - L.solve, stream);
     if (rc) return rc;
   }

@@ -39,6 +39,8 @@ struct SolveDesc {
   // 1: the inner CG streams SA on every step even where m >= d (no Gram
   // matrix); pays off when the inner solve takes only a few steps.
   int no_gram = 0;
+  // 1: AAb_Solver (Algorithm 6) as the inner solver (streams SA; no Gram matrix)
+  int aab = 0;
 };
 
 size_t solve_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int mixed,
@@ -49,7 +51,7 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
 // ---- statistical dimension estimate ------------------------------------------
 size_t estimate_workspace_bytes(const mihs_handle* h, int64_t m, int64_t d, int64_t T, int mixed);
 int launch_estimate_sd(const mihs_handle* h, const void* SA, int64_t m, int64_t d, int64_t ldsa,
-                       int mixed, double lam, int64_t T, uint32_t seed, double eps_tr,
+                       int mixed, int aab, double lam, int64_t T, uint32_t seed, double eps_tr,
                        int64_t max_inner, double* sd, double* Zout, mihs_info_t* info,
                        void* ws, size_t ws_bytes, hipStream_t stream);
 

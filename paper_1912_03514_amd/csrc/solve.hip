@@ -67,6 +67,8 @@ struct SolveArgs {
   const void* H;      // Gram matrix (SA)^T SA (TS), dpad x dpad, when the CG uses it
   int64_t ldh;
   int cg1;            // Gram path: single-reduction CG (one barrier per step)
+  int aab;            // streaming path: AAb_Solver (Algorithm 6) instead of CG
+  double* yrow;       // AAb: m doubles, -(M v - theta p) of each row of SA
   int d, dpad, G, Gc, cpw;
   BarrierSpin spin_fast, spin_idle;
 };
@@ -80,12 +82,15 @@ struct RowsInFlight {
       (kBytes >= 512 || (EPT >= 32 && sizeof(TM) < 8)) ? 1 : (kBytes >= 256 ? 2 : 4);
 };
 
-// One pass over rows [r0, r1) of M: for each row, u = c_row - M_row . v and
-// acc += u * M_row (acc in this lane's columns), ssq += u^2.
+// One pass over rows [r0, r1) of M: for each row, u = cs c_row - M_row . v and
+// acc += u * M_row (acc in this lane's columns), ssq += u^2; u is also stored
+// to uout[row] when uout is set (uout may alias c: each row is read before it
+// is written, by the same wave).
 template <typename TM, typename TV, int EPT, bool NT, int R>
 __device__ __forceinline__ void rowpass(const TM* __restrict__ M, int64_t ld, int64_t r0,
                                         int64_t r1, int d, const TV* __restrict__ v,
-                                        const double* __restrict__ c, TV (&acc)[EPT], TV& ssq) {
+                                        const double* c, TV (&acc)[EPT], TV& ssq,
+                                        double cs = 1.0, double* uout = nullptr) {
   using L = RowLayout<TM, EPT>;
   const int lane = lane_id();
   for (int64_t row = r0 + (int64_t)wave_id() * R; row < r1; row += (int64_t)kWavesPerBlock * R) {
@@ -116,7 +121,10 @@ __device__ __forceinline__ void rowpass(const TM* __restrict__ M, int64_t ld, in
 #pragma unroll
     for (int t = 0; t < R; ++t) {
       TV u = TV(0);
-      if (row + t < r1) u = (c ? (TV)c[row + t] : TV(0)) - dot[t];
+      if (row + t < r1) {
+        u = (c ? (TV)(cs * c[row + t]) : TV(0)) - dot[t];
+        if (uout && lane == 0) uout[row + t] = (double)u;
+      }
       ssq += u * u;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) acc[e] += u * (TV)rv[t][e];
@@ -364,7 +372,102 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
         decision = (rr0 == 0.0) ? 1 : 2;  // stationary point, or NaN
       } else {
         const double stop = a.eps_sub * a.eps_sub * rr0;
-        if (GRAM && cg1) {
+        if (!GRAM && a.aab) {
+          // AAb_Solver (Algorithm 6) on ((SA)^T SA + lambda I) z = g: Golub-Kahan
+          // bidiagonalisation of M = SA started from v = g / ||g||, the
+          // sqrt(lambda) I block folded in by Givens rotations.  One pass over
+          // the owned rows of M per step gives y = M v - theta p and M^T y
+          // together (p = y_prev / rho_prev is never normalised in memory, the
+          // scale rides on the next pass), then two barriers: one for rho = ||y||
+          // and M^T y, one for theta = ||w||, w = M^T p - rho v.  Every CG
+          // workgroup keeps v in LDS and the same scalars; owners keep the
+          // direction vector (in own_r) and the iterate z on their columns.
+          TV* vp = (TV*)vbuf;
+          TV* wv = r;  // w, exchanged through the residual buffer
+          TV* dv = own_r;
+          const double theta1 = sqrt(rr0);
+          for (int c = threadIdx.x; c < a.dpad; c += kBlock)
+            vp[c] = (c < d) ? (TV)((double)r[c] / theta1) : TV(0);
+          __syncthreads();
+          double theta = 0.0, rho_prev = 1.0, rhobar = 0.0, cs = 0.0, sn = 0.0, phi = 0.0;
+          bool first = true;
+          while (true) {
+            TV ssq = TV(0);
+            {
+              TV acc[EPT];
+#pragma unroll
+              for (int e = 0; e < EPT; ++e) acc[e] = TV(0);
+              // u = -(M v - theta p) = (-theta / rho_prev) y_prev - M v
+              rowpass<TS, TV, EPT, false, RS>(SA, a.ldsa, s_r0, s_r1, d, vp,
+                                              first ? nullptr : a.yrow, acc, ssq,
+                                              -theta / rho_prev, a.yrow);
+              wg_store_partial<TS, TV, EPT>(acc, (TV*)rbuf, partS + (int64_t)w * a.dpad, d);
+              ssq = wg_sum_ssq(ssq, s_red);
+            }
+            if (threadIdx.x == 0) scal_w[1] = (double)ssq;
+            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            // colbuf = -M^T y on the owned columns; rho = ||y||
+            owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
+            double rho2, unused2;
+            sum2_slots(a.scal, Gc, 1, 1, s_red, rho2, unused2);
+            const double rho = sqrt(rho2);
+            double t;
+            if (first) {
+              rhobar = sqrt(rho * rho + a.lam);
+              cs = rho / rhobar;
+              sn = sqrt(a.lam) / rhobar;
+              phi = theta1 / rhobar;
+              for (int i = threadIdx.x; i < nown; i += kBlock) {
+                const TV dn = (TV)((double)vp[c_lo + i] / rhobar);
+                dv[i] = dn;
+                own_z[i] = (TV)(phi * (double)dn);
+              }
+              t = INFINITY;
+              first = false;
+            } else {
+              const double lbar = sqrt(a.lam + (sn * theta) * (sn * theta));
+              const double thetabar = cs * theta;
+              rhobar = sqrt(rho * rho + lbar * lbar);
+              cs = rho / rhobar;
+              sn = lbar / rhobar;
+              phi = -phi * thetabar / rhobar;
+              for (int i = threadIdx.x; i < nown; i += kBlock) {
+                const TV dn =
+                    (TV)(((double)vp[c_lo + i] - thetabar * (double)dv[i]) / rhobar);
+                dv[i] = dn;
+                own_z[i] = own_z[i] + (TV)(phi * (double)dn);
+              }
+              t = fabs(phi * rhobar) / theta1;
+              ++k;
+            }
+            if (!isfinite(phi) || !isfinite(rhobar)) {
+              decision = 2;
+              break;
+            }
+            // stop on the relative residual of the current iterate; rho = 0
+            // ends the Krylov space (the iterate is then exact)
+            if (!(t >= a.eps_sub) || k >= a.max_inner || !(rho > 0.0)) break;
+            // w = M^T p - rho v = (M^T y) / rho - rho v on the owned columns
+            double th_part = 0.0;
+            for (int i = threadIdx.x; i < nown; i += kBlock) {
+              const TV wc = (TV)(-colbuf[i] / rho - rho * (double)vp[c_lo + i]);
+              wv[c_lo + i] = wc;
+              th_part += (double)wc * (double)wc;
+            }
+            th_part = block_sum(th_part, s_red);
+            if (threadIdx.x == 0) scal_w[2] = th_part;
+            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            double th2;
+            sum2_slots(a.scal, Gc, 2, 2, s_red, th2, unused2);
+            theta = sqrt(th2);
+            if (!(theta > 0.0)) break;  // w = 0: the iterate is exact
+            rho_prev = rho;
+            for (int c = threadIdx.x; c < a.dpad; c += kBlock)
+              vp[c] = (c < d) ? (TV)((double)wv[c] / theta) : TV(0);
+            __syncthreads();
+          }
+          if (!alive) break;
+        } else if (GRAM && cg1) {
           // Single-reduction CG (Chronopoulos-Gear): with s = M p kept by its own
           // recurrence, one matrix product (w = M r on the owned rows) and one
           // fused reduction (r^T r, w^T r) per step, so one barrier per step.
@@ -665,7 +768,7 @@ SolveKernel pick_kernel(int a_f32, int mixed, int ept) {
 bool use_gram(int64_t m, int64_t d) { return m >= d; }
 
 struct SolveLayout {
-  size_t partA, partS, scal, vecs, xp, bar, gram, total;
+  size_t partA, partS, scal, vecs, xp, bar, gram, yrow, total;
 };
 
 // Barrier region: line 0 = top counter of the all-workgroup barrier, lines 1-8
@@ -674,7 +777,7 @@ struct SolveLayout {
 constexpr size_t kBarLines = 12;
 
 // gram_bytes: size of the Gram matrix region (0 when the CG streams SA).
-SolveLayout layout(int G, int Gc, int64_t dpad, size_t gram_bytes) {
+SolveLayout layout(int G, int Gc, int64_t dpad, size_t gram_bytes, int64_t m) {
   SolveLayout L;
   size_t off = 0;
   L.partA = off; off = align_up(off + (size_t)G * dpad * 8, 256);
@@ -684,6 +787,7 @@ SolveLayout layout(int G, int Gc, int64_t dpad, size_t gram_bytes) {
   L.xp = off;    off = align_up(off + (size_t)dpad * 8, 256);
   L.bar = off;   off = align_up(off + kBarLines * 128, 256);
   L.gram = off;  off = align_up(off + gram_bytes, 256);
+  L.yrow = off;  off = align_up(off + (size_t)m * 8, 256);
   L.total = off;
   return L;
 }
@@ -729,14 +833,15 @@ size_t solve_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t
                              int no_gram) {
   (void)n;
   const int G = max_grid(h);
-  return layout(G, G, dpad_for(d), no_gram ? 0 : gram_bytes_for(m, d, mixed)).total;
+  return layout(G, G, dpad_for(d), no_gram ? 0 : gram_bytes_for(m, d, mixed), m).total;
 }
 
 int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_bytes,
                  hipStream_t stream) {
   const int ept = ept_for(s.d);
   if (ept > 64) return MIHS_ERR_UNSUPPORTED;
-  const bool gram = !s.no_gram && use_gram(s.m, s.d);
+  // AAb_Solver needs M v and M^T p separately: it always streams SA
+  const bool gram = !s.no_gram && !s.aab && use_gram(s.m, s.d);
   SolveKernel kern = gram ? pick_kernel<true>(s.a_f32, s.mixed, ept)
                           : pick_kernel<false>(s.a_f32, s.mixed, ept);
   if (!kern) return MIHS_ERR_UNSUPPORTED;
@@ -768,7 +873,7 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
     }
   }
   if (G == 0) return MIHS_ERR_UNSUPPORTED;
-  const SolveLayout L = layout(G, Gc, dpad, gram ? gram_bytes_for(s.m, s.d, s.mixed) : 0);
+  const SolveLayout L = layout(G, Gc, dpad, gram ? gram_bytes_for(s.m, s.d, s.mixed) : 0, s.m);
   if (ws_bytes < L.total || ws == nullptr) return MIHS_ERR_WORKSPACE;
 
   char* base = (char*)ws;
@@ -822,6 +927,8 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   // (measured on the CountSketch workload, kappa ~ 6e8: FP64 22k vs 27-38k
   // steps; FP32 breaks down), so the kernel also checks trace(H) / lambda.
   a.cg1 = s.mixed ? 1 : 0;
+  a.aab = s.aab ? 1 : 0;
+  a.yrow = (double*)(base + L.yrow);
   if (gram) {
     const int rc = launch_gram(s.SA, s.mixed, s.m, s.d, s.ldsa, base + L.gram, s.mixed, dpad,
                                stream);

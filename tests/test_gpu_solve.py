@@ -116,6 +116,49 @@ def test_cg_operator_paths(m, prec):
     assert rel(x.cpu().numpy(), ref.x) <= (1e-11 if prec == "plain" else 1e-4)
 
 
+@pytest.mark.parametrize("m", [120, 200])
+def test_aab_inner_follows_oracle_trajectory(m):
+    """AAb_Solver (Algorithm 6) as the inner solver: N fixed outer steps follow
+    the oracle's AAb trajectory (step counts and iterates), m below and above d."""
+    mihs = _mihs()
+    d = 128
+    P = _problem(2600, d, 25.0, seed=34)
+    SA = sketches.gaussian_sketch(P.A, m, 7)
+    a, b = O.momentum_cor4(25.0, m)
+    N = 5
+    for eps in (0.1, 1e-12):
+        ref = O.mihs(P.A, P.b, P.lam, SA, a, b, inner="aab", eps_sub=eps, n_iter=N,
+                     max_inner=5000)
+        announce(f"aab inner m={m} d={d} eps={eps}")
+        x, info = mihs.mihs_solve(to_dev(P.A), to_dev(P.b), P.lam, to_dev(SA), a, b,
+                                  eps_sub=eps, tol=0.0, max_outer=N, max_inner=5000, inner="aab")
+        assert info["outer_iters"] == N
+        # at eps = 1e-12 the residual estimate ends within rounding of the
+        # threshold, so a solve may take one step more or less (a change of
+        # about eps in the step)
+        slack = 0 if eps >= 1e-6 else N
+        assert abs(info["inner_iters_total"] - sum(ref.inner)) <= slack, (info, ref.inner)
+        assert rel(x.cpu().numpy(), ref.x) <= 1e-11, eps
+
+
+@pytest.mark.parametrize("prec", ["plain", "mixed"])
+def test_aab_inner_reaches_1e_10(prec):
+    """The small workload's shape with AAb_Solver at the paper's forcing term 0.1:
+    the FP64 outer loop drives the error to 1e-10 (FP32 AAb in the mixed path)."""
+    mihs = _mihs()
+    P = _problem(4096, 256, 64.0, seed=12)
+    SA = sketches.gaussian_sketch(P.A, 256, 7)
+    a, b = O.momentum_cor4(64.0, 256)
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    sa = SA if prec == "plain" else SA.astype(np.float32)
+    announce(f"aab inner to 1e-10, {prec}")
+    x, info = mihs.mihs_solve(to_dev(P.A), to_dev(P.b), P.lam, to_dev(sa), a, b, eps_sub=0.1,
+                              tol=1e-11, max_outer=300, max_inner=2000, precision=prec,
+                              inner="aab")
+    assert info["status"] == 0, info
+    assert rel(x.cpu().numpy(), xs) <= 1e-10
+
+
 def test_warm_start_and_momentum_state():
     """Two half-length solves chained through X and X_prev equal one long solve."""
     mihs = _mihs()

@@ -361,8 +361,10 @@ def run_dual(args):
         "data": "synthetic", "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m,
                                         "sd": w.sd_target, "lambda": lam, "tol": args.tol},
         "plain_fp64_ms": round(out["plain"]["ms"], 3),
-        "mixed": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in mx.items()},
-        "plain": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in out["plain"].items()},
+        "mixed": {k: (round(v, 3) if isinstance(v, float) and k != "err" else v)
+                  for k, v in mx.items()},
+        "plain": {k: (round(v, 3) if isinstance(v, float) and k != "err" else v)
+                  for k, v in out["plain"].items()},
         "roofline": {"bound": "hbm", "kernel": "solve_kernel on A^T (mixed)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},

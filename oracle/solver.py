@@ -26,6 +26,10 @@ recovers x* = A^T nu* (eq. (dual_relation)).
 
 The statistical dimension that sets beta can be estimated from the sketch by
 the inexact Hutchinson trace estimator (Algorithm 5, Section 3.4).
+
+Primal-Dual M-IHS (Section 2, two-stage sketching, eq. (pd_mihs1); Algorithms 3
+and 4) solves each sub-problem through its dual, approximately, by M-IHS steps
+with a second sketch W (SA)^T of the dual's Hessian.
 """
 from __future__ import annotations
 
@@ -369,6 +373,141 @@ def dual_mihs(A: np.ndarray, b: np.ndarray, lam: float, SAt: np.ndarray, alpha: 
     x = A.astype(np.float64, copy=False).T @ nu
     return DualMihsResult(x=x, nu=nu, outer=it, inner=inner_counts, steps=steps,
                           converged=converged)
+
+
+# ----------------------------------------------------------------------------
+# Primal-Dual M-IHS (two-stage sketching; Section 2, eq. (pd_mihs1); Algorithms 3, 4)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class PrimalDualResult:
+    x: np.ndarray
+    outer: int
+    inner: List[int]       # inner-solver steps summed over the M dual steps of each outer step
+    steps: List[float]
+    converged: bool
+    nu: Optional[np.ndarray] = None
+
+
+def pd_dual_gradient(SM: np.ndarray, c: np.ndarray, lam: float, z: np.ndarray) -> np.ndarray:
+    """Gradient of the sub-problem's dual (Algorithms 3, 4): SM (c - SM^T z) - lambda z."""
+    return SM @ (c - SM.T @ z) - lam * z
+
+
+def _pd_inner(SM: np.ndarray, WSMt: np.ndarray, c: np.ndarray, z: np.ndarray,
+              z_prev: np.ndarray, lam: float, alpha2: float, beta2: float, M: int,
+              inner: str, eps_sub: float, max_inner: Optional[int]):
+    """M M-IHS steps on the dual of the sketched sub-problem,
+        min_z 1/2 ||SM^T z - c||^2 + lambda/2 ||z||^2      (z in R^{m1}),
+    whose Hessian SM SM^T + lambda I is sketched again by WSMt = W SM^T (m2 x m1):
+        g      = SM (c - SM^T z) - lambda z
+        dz     = ((WSMt)^T WSMt + lambda I)^{-1} g          (inner solver)
+        z_next = z + alpha2 dz + beta2 (z - z_prev)."""
+    SM64 = SM.astype(np.float64, copy=False)
+    exact = inner_exact_factory(WSMt, lam) if inner == "exact" else None
+    total = 0
+    for _ in range(M):
+        g = pd_dual_gradient(SM64, c, lam, z)
+        if inner == "exact":
+            dz, k = exact(g)
+        elif inner == "cg":
+            dz, k = inner_cg(WSMt, g, lam, eps_sub, max_inner)
+        elif inner == "aab":
+            dz, k = aab_solver(WSMt, g, lam, eps_sub, max_inner)
+        else:
+            raise ValueError(inner)
+        total += k
+        z, z_prev = z + alpha2 * dz + beta2 * (z - z_prev), z
+    return z, z_prev, total
+
+
+def primal_dual_mihs(A: np.ndarray, b: np.ndarray, lam: float, SA: np.ndarray,
+                     WSAt: np.ndarray, alpha1: float, beta1: float, alpha2: float,
+                     beta2: float, *, M: int, inner: str = "aab", eps_sub: float = 0.1,
+                     max_inner: Optional[int] = None, n_iter: Optional[int] = None,
+                     tol: Optional[float] = None, max_outer: int = 500) -> PrimalDualResult:
+    """Primal Dual M-IHS for n >= d (Algorithm 4).  SA = S A is m1 x d and
+    WSAt = W (SA)^T is m2 x m1.  x^1 = 0, z^{1,1} = z^{1,0} = 0; per outer step
+        b^i      = A^T (b - A x^i) - lambda x^i
+        z        <- M dual M-IHS steps on min 1/2 ||(SA)^T z - b^i||^2 + lambda/2 ||z||^2
+        dx^i     = (b^i - (SA)^T z) / lambda                  (eq. (dual_relation))
+        x^{i+1}  = x^i + alpha1 dx^i + beta1 (x^i - x^{i-1}),  x^0 = x^1.
+    The dual iterate and its momentum state carry over from one outer step to
+    the next (z^{i+1,1} = z^{i,M+1}, and z^{i+1,0} = z^{i,M}).  Runs `n_iter`
+    outer steps if given, else stops on the relative-step rule for x."""
+    A64 = A.astype(np.float64, copy=False)
+    SA64 = SA.astype(np.float64, copy=False)
+    d = A.shape[1]
+    m1 = SA.shape[0]
+    x = np.zeros(d)
+    x_prev = x.copy()
+    z = np.zeros(m1)
+    z_prev = z.copy()
+    inner_counts: List[int] = []
+    steps: List[float] = []
+    thr = stop_threshold(tol, beta1) if tol is not None else None
+    limit = n_iter if n_iter is not None else max_outer
+    converged = False
+    it = 0
+    for it in range(1, limit + 1):
+        bi = gradient(A64, b, lam, x)
+        z, z_prev, k = _pd_inner(SA64, WSAt, bi, z, z_prev, lam, alpha2, beta2, M, inner,
+                                 eps_sub, max_inner)
+        inner_counts.append(k)
+        dx = (bi - SA64.T @ z) / lam
+        x_new = x + alpha1 * dx + beta1 * (x - x_prev)
+        nrm = float(np.linalg.norm(x_new))
+        step = float(np.linalg.norm(x_new - x)) / nrm if nrm > 0 else 0.0
+        steps.append(step)
+        x_prev, x = x, x_new
+        if thr is not None and n_iter is None and step <= thr:
+            converged = True
+            break
+    return PrimalDualResult(x=x, outer=it, inner=inner_counts, steps=steps,
+                            converged=converged)
+
+
+def primal_dual_mihs_wide(A: np.ndarray, b: np.ndarray, lam: float, SAt: np.ndarray,
+                          WASt: np.ndarray, alpha1: float, beta1: float, alpha2: float,
+                          beta2: float, *, M: int, inner: str = "aab", eps_sub: float = 0.1,
+                          max_inner: Optional[int] = None, n_iter: Optional[int] = None,
+                          tol: Optional[float] = None, max_outer: int = 500) -> PrimalDualResult:
+    """Primal Dual M-IHS for n <= d (Algorithm 3).  SAt = S A^T is m1 x n and
+    WASt = W (S A^T)^T is m2 x m1.  nu^1 = 0, z^{1,1} = z^{1,0} = 0; per outer step
+        b^i       = b - A A^T nu^i - lambda nu^i
+        z         <- M dual M-IHS steps on min 1/2 ||(S A^T)^T z - b^i||^2 + lambda/2 ||z||^2
+        dnu^i     = (b^i - (S A^T)^T z) / lambda
+        nu^{i+1}  = nu^i + alpha1 dnu^i + beta1 (nu^i - nu^{i-1}),
+    and finally x = A^T nu.  z carries over as in Algorithm 4."""
+    A64 = A.astype(np.float64, copy=False)
+    SAt64 = SAt.astype(np.float64, copy=False)
+    n = A.shape[0]
+    m1 = SAt.shape[0]
+    nu = np.zeros(n)
+    nu_prev = nu.copy()
+    z = np.zeros(m1)
+    z_prev = z.copy()
+    inner_counts: List[int] = []
+    steps: List[float] = []
+    thr = stop_threshold(tol, beta1) if tol is not None else None
+    limit = n_iter if n_iter is not None else max_outer
+    converged = False
+    it = 0
+    for it in range(1, limit + 1):
+        bi = dual_gradient(A64, b, lam, nu)
+        z, z_prev, k = _pd_inner(SAt64, WASt, bi, z, z_prev, lam, alpha2, beta2, M, inner,
+                                 eps_sub, max_inner)
+        inner_counts.append(k)
+        dnu = (bi - SAt64.T @ z) / lam
+        nu_new = nu + alpha1 * dnu + beta1 * (nu - nu_prev)
+        nrm = float(np.linalg.norm(nu_new))
+        step = float(np.linalg.norm(nu_new - nu)) / nrm if nrm > 0 else 0.0
+        steps.append(step)
+        nu_prev, nu = nu, nu_new
+        if thr is not None and n_iter is None and step <= thr:
+            converged = True
+            break
+    return PrimalDualResult(x=A64.T @ nu, outer=it, inner=inner_counts, steps=steps,
+                            converged=converged, nu=nu)
 
 
 # ----------------------------------------------------------------------------

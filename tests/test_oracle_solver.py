@@ -295,3 +295,78 @@ def test_hutchinson_inexact_inner_solvers_agree():
     ex = O.hutchinson_sd(SA, P.lam, V, inner="exact")
     for inner in ("aab", "cg"):
         assert abs(O.hutchinson_sd(SA, P.lam, V, inner=inner, eps_tr=1e-12) - ex) <= 1e-8 * abs(ex)
+
+
+def _pd_problem(n=1500, d=160, sd=8.0, seed=21, rate=10.0):
+    sig = W.sigma_profile("exp", min(n, d), rate)
+    return W.make_problem(n, d, sig, sd, seed)
+
+
+def test_pd_inner_reaches_dual_subproblem_solution():
+    """Many dual M-IHS steps (exact inner solves) reach
+    z* = (SA SA^T + lambda I)^{-1} SA c, and the recovered step
+    (c - SA^T z*)/lambda is (SA^T SA + lambda I)^{-1} c (push-through identity),
+    both from library solves."""
+    P = _pd_problem()
+    d = P.A.shape[1]
+    SA = sketches.gaussian_sketch(P.A, 40, 5)
+    WSAt = sketches.gaussian_sketch(SA.T.copy(), 40, 6)
+    c = np.random.default_rng(0).standard_normal(d)
+    a2, b2 = O.momentum_cor4(8.0, 40)
+    z, _, _ = O._pd_inner(SA, WSAt, c, np.zeros(40), np.zeros(40), P.lam, a2, b2, 300, "exact",
+                          0.0, None)
+    zs = np.linalg.solve(SA @ SA.T + P.lam * np.eye(40), SA @ c)
+    assert np.linalg.norm(z - zs) <= 1e-10 * np.linalg.norm(zs)
+    dx = (c - SA.T @ z) / P.lam
+    dxs = np.linalg.solve(SA.T @ SA + P.lam * np.eye(d), c)
+    assert np.linalg.norm(dx - dxs) <= 1e-9 * np.linalg.norm(dxs)
+
+
+def test_pd_one_step_with_identity_sketches():
+    """S = I and W = I (the second sketch of A^T is A^T), exact inner solve,
+    M = 1, unit step, no momentum: one outer step from x = 0 reaches x*."""
+    P = _small(n=60, d=20, sd=6.0, seed=4)
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    r = O.primal_dual_mihs(P.A, P.b, P.lam, P.A, P.A.T.copy(), 1.0, 0.0, 1.0, 0.0, M=1,
+                           inner="exact", n_iter=1)
+    assert np.linalg.norm(r.x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("inner", ["aab", "cg"])
+def test_pd_reaches_closed_form_tall_and_wide(inner):
+    """Algorithms 4 (n >= d) and 3 (n <= d) with m1 = m2 = 5 sd, M = 10 dual
+    steps of eps_sub = 0.1 each: the iterate converges to the ridge solution
+    from least squares of [A; sqrt(lambda) I]."""
+    P = _pd_problem()
+    xs = O.ridge_lstsq(P.A, P.b, P.lam)
+    m = 40
+    SA = sketches.gaussian_sketch(P.A, m, 5)
+    WSAt = sketches.gaussian_sketch(SA.T.copy(), m, 6)
+    a, b = O.momentum_cor4(8.0, m)
+    r = O.primal_dual_mihs(P.A, P.b, P.lam, SA, WSAt, a, b, a, b, M=10, inner=inner,
+                           n_iter=80)
+    assert np.linalg.norm(r.x - xs) <= 1e-9 * np.linalg.norm(xs)
+    # the wide problem A^T (d x n with d < n): Algorithm 3 on it
+    Aw = P.A.T.copy()
+    bw = np.random.default_rng(1).standard_normal(Aw.shape[0])
+    xw = O.ridge_lstsq(Aw, bw, P.lam)
+    SAt = sketches.gaussian_sketch(Aw.T.copy(), m, 7)
+    WASt = sketches.gaussian_sketch(SAt.T.copy(), m, 8)
+    rw = O.primal_dual_mihs_wide(Aw, bw, P.lam, SAt, WASt, a, b, a, b, M=10, inner=inner,
+                                 n_iter=80)
+    assert np.linalg.norm(rw.x - xw) <= 1e-9 * np.linalg.norm(xw)
+
+
+def test_pd_planted_mistake_is_caught(monkeypatch):
+    """Dropping the lambda z term of the dual gradient breaks the sub-problem pin."""
+    P = _pd_problem()
+    d = P.A.shape[1]
+    SA = sketches.gaussian_sketch(P.A, 40, 5)
+    WSAt = sketches.gaussian_sketch(SA.T.copy(), 40, 6)
+    c = np.random.default_rng(0).standard_normal(d)
+    a2, b2 = O.momentum_cor4(8.0, 40)
+    monkeypatch.setattr(O, "pd_dual_gradient", lambda SM, cc, lam, z: SM @ (cc - SM.T @ z))
+    z, _, _ = O._pd_inner(SA, WSAt, c, np.zeros(40), np.zeros(40), P.lam, a2, b2, 300, "exact",
+                          0.0, None)
+    zs = np.linalg.solve(SA @ SA.T + P.lam * np.eye(40), SA @ c)
+    assert not (np.linalg.norm(z - zs) <= 1e-6 * np.linalg.norm(zs))

@@ -209,6 +209,66 @@ int mihs_solve_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, 
                     void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Primal-Dual M-IHS (Section 2, two-stage sketching, eq. (pd_mihs1);
+ * Algorithm 4 for n >= d, Algorithm 3 for n <= d).  The outer iteration is
+ * M-IHS; its sub-problem ((SA)^T SA + lambda I) dx = g is solved through its
+ * dual by M M-IHS steps on
+ *     min_z 1/2 ||Q z - g||^2 + lambda/2 ||z||^2,   Q = (S A)^T  (z in R^{m1}),
+ * with the second sketch WQ = W Q, then dx = (g - Q z) / lambda.  The dual
+ * steps use `inner` (AAb_Solver in the paper) with forcing term eps_sub, and
+ * z with its momentum state carries over between outer steps
+ * (z^{i+1,1} = z^{i,M+1}, z^{i+1,0} = z^{i,M}).  Momentum (Corollary 4):
+ * beta_l = sd / m_l, alpha_l = (1 - beta_l)^2 for l = 1 (outer), 2 (dual).
+ * The stop rule is mihs_solve's on the outer iterate with beta1.
+ *
+ * mihs_solve_pd (Algorithm 4, n >= d):
+ *   A    device n x d (a_dtype), row stride lda;  b  device, n doubles.
+ *   Q    device d x m1, (S A)^T: mihs_transpose of an m1 x d sketch of A.
+ *   X    device, d doubles: in = x^1, out = last iterate.
+ * mihs_solve_pd_dual (Algorithm 3, n <= d):
+ *   At   device d x n, A^T (a_dtype), row stride ldat;  b  device, n doubles.
+ *   Q    device n x m1, (S A^T)^T: mihs_transpose of an m1 x n sketch of A^T.
+ *   NU   device, n doubles: in = nu^1 (zeros in Algorithm 3), out = last iterate.
+ *   X    device, d doubles: out = A^T nu.
+ * Both:
+ *   WQ   device m2 x m1: a sketch of Q (mihs_sketch on Q with m2 rows).
+ *   Q and WQ are double for PLAIN_FP64 and float for MIXED.
+ *   M >= 1 dual steps per outer step; the outer dimension (d, resp. n) and m1
+ *   are at most 4096 (MIHS_ERR_UNSUPPORTED otherwise).
+ *   d_info  one record: outer_iters, inner_iters_total (inner-solver steps over
+ *           all dual steps), inner_iters_max (per outer step), rel_step,
+ *           grad_norm (||g|| of the last outer step), status.
+ * The host enqueues max_outer outer steps without waiting; once the stop rule
+ * holds, the remaining enqueued kernels return at once.
+ * ------------------------------------------------------------------------ */
+int mihs_solve_pd_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m1,
+                                 int64_t m2, mihs_precision_t precision, size_t* bytes);
+
+int mihs_solve_pd(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                  int64_t d, int64_t lda, const double* b, double lambda, const void* Q,
+                  int64_t m1, int64_t ldq, const void* WQ, int64_t m2, int64_t ldwq,
+                  mihs_precision_t precision, mihs_inner_t inner, double alpha1, double beta1,
+                  double alpha2, double beta2, int64_t M, double eps_sub, double tol,
+                  int64_t max_outer, int64_t max_inner, double* X, mihs_info_t* d_info,
+                  void* workspace, size_t ws_bytes, void* stream);
+
+int mihs_solve_pd_dual_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m1,
+                                      int64_t m2, mihs_precision_t precision, size_t* bytes);
+
+int mihs_solve_pd_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, int64_t n,
+                       int64_t d, int64_t ldat, const double* b, double lambda, const void* Q,
+                       int64_t m1, int64_t ldq, const void* WQ, int64_t m2, int64_t ldwq,
+                       mihs_precision_t precision, mihs_inner_t inner, double alpha1,
+                       double beta1, double alpha2, double beta2, int64_t M, double eps_sub,
+                       double tol, int64_t max_outer, int64_t max_inner, double* NU, double* X,
+                       mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream);
+
+/* Transpose: dst (cols x rows, row stride ldd) = src^T, src rows x cols with row
+ * stride lds; dtype for both.  Forms Q = (S A)^T for the Primal-Dual solves. */
+int mihs_transpose(mihs_handle_t handle, const void* src, mihs_dtype_t dtype, int64_t rows,
+                   int64_t cols, int64_t lds, void* dst, int64_t ldd, void* stream);
+
+/* ------------------------------------------------------------------------
  * Statistical dimension estimate from a sketch: the inexact Hutchinson trace
  * estimator of Section 3.4 (Algorithm 5),
  *   sd ~ d - (lambda / T) sum_{l<T} <v^l, z^l>,

@@ -72,6 +72,17 @@ _SIGS = {
                                 _int, _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp,
                                 _vp, _sz, _vp]),
     "mihs_solve_dual_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)]),
+    "mihs_solve_pd_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
+                                            ctypes.POINTER(_sz)]),
+    "mihs_solve_pd": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64, _vp,
+                             _i64, _i64, _int, _int, _dbl, _dbl, _dbl, _dbl, _i64, _dbl, _dbl,
+                             _i64, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "mihs_solve_pd_dual_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
+                                                 ctypes.POINTER(_sz)]),
+    "mihs_solve_pd_dual": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64,
+                                  _vp, _i64, _i64, _int, _int, _dbl, _dbl, _dbl, _dbl, _i64,
+                                  _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mihs_transpose": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _vp]),
     "mihs_solve_dual": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64,
                                _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp,
                                _sz, _vp]),
@@ -333,6 +344,108 @@ def mihs_estimate_sd(SA: torch.Tensor, lam: float, T: int = 2, seed: int = 0,
     torch.cuda.synchronize(dev)
     infos = info_to_dict(info)
     return (float(sd), Z, infos) if want_z else (float(sd), infos)
+
+
+def mihs_transpose(M: torch.Tensor) -> torch.Tensor:
+    """M^T as a new row-major tensor, on the library's transpose kernel."""
+    M = _row_aligned(M)
+    rows, cols = M.shape
+    per = 16 // M.element_size()
+    ld = (rows + per - 1) // per * per
+    out = torch.empty((cols, ld), dtype=M.dtype, device=M.device)
+    lib = load_library()
+    _check(lib.mihs_transpose(handle(M.device.index), M.data_ptr(), _dtype_code(M), rows, cols,
+                              M.stride(0), out.data_ptr(), ld, _stream(M.device)),
+           "mihs_transpose")
+    return out[:, :rows]
+
+
+def mihs_sketch_two_stage(M: torch.Tensor, kind1: str, m1: int, seed1: int, kind2: str,
+                          m2: int, seed2: int, precision: str = "plain"):
+    """The two sketches of Primal-Dual M-IHS (Algorithms 3, 4): Q = (S M)^T
+    (cols x m1) and WQ = W Q (m2 x m1), from mihs_sketch and mihs_transpose."""
+    SM = mihs_sketch(M, kind1, m1, seed1, precision=precision)
+    Q = mihs_transpose(SM)
+    WQ = mihs_sketch(Q, kind2, m2, seed2, precision=precision)
+    return Q, WQ
+
+
+def _pd_call(fn_ws, fn, Aop, rows, cols, b, lam, Q, WQ, alpha1, beta1, alpha2, beta2, M,
+             eps_sub, tol, max_outer, max_inner, x, extra, precision, inner, dev):
+    p = PRECISIONS[precision]
+    inn = INNER_SOLVERS[inner]
+    if Q.dim() != 2 or Q.shape[0] != cols:
+        raise MihsError(f"Q must have one row per outer unknown ({cols}), got {tuple(Q.shape)}")
+    if WQ.dim() != 2 or WQ.shape[1] != Q.shape[1]:
+        raise MihsError("WQ must have as many columns as Q")
+    Q = _row_aligned(Q)
+    WQ = _row_aligned(WQ)
+    m1 = Q.shape[1]
+    m2 = WQ.shape[0]
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    lib = load_library()
+    h = handle(dev.index)
+    n_, d_ = (rows, cols) if fn == "mihs_solve_pd" else (cols, rows)
+    ws_n = _sz()
+    _check(getattr(lib, fn_ws)(h, n_, d_, m1, m2, p, ctypes.byref(ws_n)), fn_ws)
+    ws = _workspace(ws_n.value, dev)
+    args = [h, Aop.data_ptr(), _dtype_code(Aop), n_, d_, Aop.stride(0), b.data_ptr(), float(lam),
+            Q.data_ptr(), m1, Q.stride(0), WQ.data_ptr(), m2, WQ.stride(0), p, inn,
+            float(alpha1), float(beta1), float(alpha2), float(beta2), int(M), float(eps_sub),
+            float(tol), int(max_outer), int(max_inner), x.data_ptr()]
+    args += [e.data_ptr() for e in extra]
+    args += [info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)]
+    _check(getattr(lib, fn)(*args), fn)
+    return info, ws
+
+
+def mihs_solve_pd(A: torch.Tensor, b: torch.Tensor, lam: float, Q: torch.Tensor,
+                  WQ: torch.Tensor, alpha1: float, beta1: float, alpha2: float, beta2: float,
+                  M: int = 25, eps_sub: float = 0.1, tol: float = 1e-10, max_outer: int = 100,
+                  max_inner: int = 1000, x0: Optional[torch.Tensor] = None,
+                  precision: Optional[str] = None, inner: str = "aab", sync: bool = True):
+    """Primal-Dual M-IHS for n >= d (Algorithm 4; see include/mihs.h).  Q = (S A)^T
+    (d x m1), WQ = W Q (m2 x m1).  Returns (x, info)."""
+    if precision is None:
+        precision = "mixed" if Q.dtype == torch.float32 else "plain"
+    A = _row_aligned(A)
+    n, d = A.shape
+    dev = A.device
+    if b.dtype != torch.float64 or b.numel() != n or not b.is_contiguous():
+        raise MihsError("b must be a contiguous float64 vector of length n")
+    x = torch.zeros(d, dtype=torch.float64, device=dev) if x0 is None else x0.clone()
+    info, ws = _pd_call("mihs_solve_pd_workspace_size", "mihs_solve_pd", A, n, d, b, lam, Q, WQ,
+                        alpha1, beta1, alpha2, beta2, M, eps_sub, tol, max_outer, max_inner, x,
+                        [], precision, inner, dev)
+    if not sync:
+        return x, (info, ws)
+    torch.cuda.synchronize(dev)
+    return x, info_to_dict(info)[0]
+
+
+def mihs_solve_pd_dual(At: torch.Tensor, b: torch.Tensor, lam: float, Q: torch.Tensor,
+                       WQ: torch.Tensor, alpha1: float, beta1: float, alpha2: float,
+                       beta2: float, M: int = 25, eps_sub: float = 0.1, tol: float = 1e-10,
+                       max_outer: int = 100, max_inner: int = 1000,
+                       precision: Optional[str] = None, inner: str = "aab", sync: bool = True):
+    """Primal-Dual M-IHS for n <= d (Algorithm 3; see include/mihs.h).  At = A^T
+    (d x n), Q = (S A^T)^T (n x m1), WQ = W Q.  Returns (x, nu, info)."""
+    if precision is None:
+        precision = "mixed" if Q.dtype == torch.float32 else "plain"
+    At = _row_aligned(At)
+    d, n = At.shape
+    dev = At.device
+    if b.dtype != torch.float64 or b.numel() != n or not b.is_contiguous():
+        raise MihsError("b must be a contiguous float64 vector of length n")
+    nu = torch.zeros(n, dtype=torch.float64, device=dev)
+    x = torch.empty(d, dtype=torch.float64, device=dev)
+    info, ws = _pd_call("mihs_solve_pd_dual_workspace_size", "mihs_solve_pd_dual", At, d, n, b,
+                        lam, Q, WQ, alpha1, beta1, alpha2, beta2, M, eps_sub, tol, max_outer,
+                        max_inner, nu, [x], precision, inner, dev)
+    if not sync:
+        return x, nu, (info, ws)
+    torch.cuda.synchronize(dev)
+    return x, nu, info_to_dict(info)[0]
 
 
 def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: torch.Tensor,

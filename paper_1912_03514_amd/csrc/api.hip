@@ -234,6 +234,137 @@ int mihs_solve_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, 
   return mihs::launch_apply_rows(handle, At, a_dtype == MIHS_F32, d, n, ldat, NU, 1, X, 1, st);
 }
 
+static int check_pd(const void* A, mihs_dtype_t a_dtype, int64_t rows, int64_t cols,
+                    int64_t lda, double lambda, const void* Q, int64_t m1, int64_t ldq,
+                    const void* WQ, int64_t m2, int64_t ldwq, mihs_precision_t precision,
+                    mihs_inner_t inner, double alpha1, double beta1, double alpha2, double beta2,
+                    int64_t M, double eps_sub, int64_t max_outer, int64_t max_inner) {
+  if (a_dtype != MIHS_F64 && a_dtype != MIHS_F32) return MIHS_ERR_INVALID;
+  if (precision != MIHS_PLAIN_FP64 && precision != MIHS_MIXED) return MIHS_ERR_INVALID;
+  if (inner != MIHS_INNER_CG && inner != MIHS_INNER_AAB) return MIHS_ERR_INVALID;
+  const int mixed = precision == MIHS_MIXED;
+  if (!valid_matrix(A, rows, cols, lda, a_dtype == MIHS_F32)) return MIHS_ERR_INVALID;
+  if (!valid_matrix(Q, cols, m1, ldq, mixed)) return MIHS_ERR_INVALID;
+  if (!valid_matrix(WQ, m2, m1, ldwq, mixed)) return MIHS_ERR_INVALID;
+  if (!(lambda > 0.0) || !isfinite(lambda)) return MIHS_ERR_INVALID;
+  for (double a : {alpha1, alpha2})
+    if (!isfinite(a) || !(a > 0.0)) return MIHS_ERR_INVALID;
+  for (double b : {beta1, beta2})
+    if (!isfinite(b) || b < 0.0 || b >= 1.0) return MIHS_ERR_INVALID;
+  if (M < 1 || !(eps_sub >= 0.0) || max_outer < 0 || max_inner < 1) return MIHS_ERR_INVALID;
+  if (cols > 4096 || m1 > 4096) return MIHS_ERR_UNSUPPORTED;
+  return MIHS_OK;
+}
+
+static mihs::PdDesc pd_desc(const void* A, mihs_dtype_t a_dtype, int64_t rows, int64_t cols,
+                            int64_t lda, const double* c, const double* rhs, double lambda,
+                            const void* Q, int64_t m1, int64_t ldq, const void* WQ, int64_t m2,
+                            int64_t ldwq, mihs_precision_t precision, mihs_inner_t inner,
+                            double alpha1, double beta1, double alpha2, double beta2, int64_t M,
+                            double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+                            double* x, mihs_info_t* info) {
+  mihs::PdDesc p;
+  p.A = A;
+  p.a_f32 = a_dtype == MIHS_F32;
+  p.rows = rows;
+  p.cols = cols;
+  p.lda = lda;
+  p.c = c;
+  p.rhs = rhs;
+  p.Q = Q;
+  p.m1 = m1;
+  p.ldq = ldq;
+  p.WQ = WQ;
+  p.m2 = m2;
+  p.ldwq = ldwq;
+  p.mixed = precision == MIHS_MIXED;
+  p.aab = inner == MIHS_INNER_AAB;
+  p.lam = lambda;
+  p.alpha1 = alpha1;
+  p.beta1 = beta1;
+  p.alpha2 = alpha2;
+  p.beta2 = beta2;
+  p.eps_sub = eps_sub;
+  p.tol = tol;
+  p.M = M;
+  p.max_outer = max_outer;
+  p.max_inner = max_inner;
+  p.x = x;
+  p.info = info;
+  return p;
+}
+
+int mihs_solve_pd_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m1,
+                                 int64_t m2, mihs_precision_t precision, size_t* bytes) {
+  if (!handle || !bytes || n <= 0 || d <= 0 || m1 <= 0 || m2 <= 0) return MIHS_ERR_INVALID;
+  *bytes = mihs::pd_workspace_bytes(handle, n, d, m1, m2, precision == MIHS_MIXED);
+  return MIHS_OK;
+}
+
+int mihs_solve_pd(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                  int64_t d, int64_t lda, const double* b, double lambda, const void* Q,
+                  int64_t m1, int64_t ldq, const void* WQ, int64_t m2, int64_t ldwq,
+                  mihs_precision_t precision, mihs_inner_t inner, double alpha1, double beta1,
+                  double alpha2, double beta2, int64_t M, double eps_sub, double tol,
+                  int64_t max_outer, int64_t max_inner, double* X, mihs_info_t* d_info,
+                  void* workspace, size_t ws_bytes, void* stream) {
+  if (!handle) return MIHS_ERR_INVALID;
+  if (n < d) return MIHS_ERR_INVALID;
+  const int rc = check_pd(A, a_dtype, n, d, lda, lambda, Q, m1, ldq, WQ, m2, ldwq, precision,
+                          inner, alpha1, beta1, alpha2, beta2, M, eps_sub, max_outer, max_inner);
+  if (rc) return rc;
+  if (!b || !X || !d_info) return MIHS_ERR_INVALID;
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  // g = A^T (b - A x) - lambda x: the ridge form of the gradient pass
+  const mihs::PdDesc p = pd_desc(A, a_dtype, n, d, lda, b, nullptr, lambda, Q, m1, ldq, WQ, m2,
+                                 ldwq, precision, inner, alpha1, beta1, alpha2, beta2, M,
+                                 eps_sub, tol, max_outer, max_inner, X, d_info);
+  return mihs::launch_pd(handle, p, workspace, ws_bytes, as_stream(stream));
+}
+
+int mihs_solve_pd_dual_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m1,
+                                      int64_t m2, mihs_precision_t precision, size_t* bytes) {
+  if (!handle || !bytes || n <= 0 || d <= 0 || m1 <= 0 || m2 <= 0) return MIHS_ERR_INVALID;
+  // the outer pass streams A^T (d x n) for the n-dimensional dual variable
+  *bytes = mihs::pd_workspace_bytes(handle, d, n, m1, m2, precision == MIHS_MIXED);
+  return MIHS_OK;
+}
+
+int mihs_solve_pd_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, int64_t n,
+                       int64_t d, int64_t ldat, const double* b, double lambda, const void* Q,
+                       int64_t m1, int64_t ldq, const void* WQ, int64_t m2, int64_t ldwq,
+                       mihs_precision_t precision, mihs_inner_t inner, double alpha1,
+                       double beta1, double alpha2, double beta2, int64_t M, double eps_sub,
+                       double tol, int64_t max_outer, int64_t max_inner, double* NU, double* X,
+                       mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream) {
+  if (!handle) return MIHS_ERR_INVALID;
+  if (n > d) return MIHS_ERR_INVALID;
+  int rc = check_pd(At, a_dtype, d, n, ldat, lambda, Q, m1, ldq, WQ, m2, ldwq, precision, inner,
+                    alpha1, beta1, alpha2, beta2, M, eps_sub, max_outer, max_inner);
+  if (rc) return rc;
+  if (!b || !NU || !X || !d_info) return MIHS_ERR_INVALID;
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  hipStream_t st = as_stream(stream);
+  // g = b - A A^T nu - lambda nu: the right-hand-side form of the pass over A^T
+  const mihs::PdDesc p = pd_desc(At, a_dtype, d, n, ldat, nullptr, b, lambda, Q, m1, ldq, WQ, m2,
+                                 ldwq, precision, inner, alpha1, beta1, alpha2, beta2, M,
+                                 eps_sub, tol, max_outer, max_inner, NU, d_info);
+  rc = mihs::launch_pd(handle, p, workspace, ws_bytes, st);
+  if (rc) return rc;
+  // x = A^T nu (eq. (dual_relation))
+  return mihs::launch_apply_rows(handle, At, a_dtype == MIHS_F32, d, n, ldat, NU, 1, X, 1, st);
+}
+
+int mihs_transpose(mihs_handle_t handle, const void* src, mihs_dtype_t dtype, int64_t rows,
+                   int64_t cols, int64_t lds, void* dst, int64_t ldd, void* stream) {
+  if (!handle || !src || !dst || rows <= 0 || cols <= 0) return MIHS_ERR_INVALID;
+  if (dtype != MIHS_F64 && dtype != MIHS_F32) return MIHS_ERR_INVALID;
+  if (lds < cols || ldd < rows) return MIHS_ERR_INVALID;
+  if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  return mihs::launch_transpose(src, dtype == MIHS_F32, rows, cols, lds, dst, ldd,
+                                as_stream(stream));
+}
+
 int mihs_estimate_sd_workspace_size(mihs_handle_t handle, int64_t m, int64_t d, int64_t T,
                                     mihs_precision_t precision, size_t* bytes) {
   if (!handle || !bytes || m <= 0 || d <= 0 || T <= 0) return MIHS_ERR_INVALID;

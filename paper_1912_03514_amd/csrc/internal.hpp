@@ -41,7 +41,16 @@ struct SolveDesc {
   int no_gram = 0;
   // 1: AAb_Solver (Algorithm 6) as the inner solver (streams SA; no Gram matrix)
   int aab = 0;
+  // device flag: when nonzero at launch time the solve returns at once
+  const int* skip = nullptr;
 };
+
+// g = A^T (c - A x) + rhs - lambda x (c and rhs may be null) for A n x d, d <= 4096;
+// returns at once when *skip is nonzero.  Workspace: grad_workspace_bytes().
+size_t grad_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d);
+int launch_grad(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,
+                int64_t lda, const double* c, const double* rhs, const double* x, double lam,
+                double* g, void* ws, size_t ws_bytes, const int* skip, hipStream_t stream);
 
 size_t solve_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int mixed,
                              int no_gram = 0);
@@ -54,6 +63,31 @@ int launch_estimate_sd(const mihs_handle* h, const void* SA, int64_t m, int64_t 
                        int mixed, int aab, double lam, int64_t T, uint32_t seed, double eps_tr,
                        int64_t max_inner, double* sd, double* Zout, mihs_info_t* info,
                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+// ---- Primal-Dual M-IHS (Algorithms 3, 4) ------------------------------------
+struct PdDesc {
+  const void* A;      // outer matrix streamed by the gradient: A (n x d) or A^T (d x n)
+  int a_f32;
+  int64_t rows, cols, lda;  // its shape; the outer variable has `cols` entries
+  const double* c;    // Algorithm 4: b (rows); Algorithm 3: null
+  const double* rhs;  // Algorithm 3: b (cols); Algorithm 4: null
+  const void* Q;      // transposed first-stage sketch, cols x m1
+  int64_t m1, ldq;
+  const void* WQ;     // second-stage sketch W Q, m2 x m1
+  int64_t m2, ldwq;
+  int mixed, aab;
+  double lam, alpha1, beta1, alpha2, beta2, eps_sub, tol;
+  int64_t M, max_outer, max_inner;
+  double* x;          // outer iterate (cols): in x^1, out the last iterate
+  mihs_info_t* info;
+};
+size_t pd_workspace_bytes(const mihs_handle* h, int64_t rows, int64_t cols, int64_t m1,
+                          int64_t m2, int mixed);
+int launch_pd(const mihs_handle* h, const PdDesc& p, void* ws, size_t ws_bytes,
+              hipStream_t stream);
+// dst (cols x rows, row stride ldd) = src^T for src rows x cols (row stride lds)
+int launch_transpose(const void* src, int f32, int64_t rows, int64_t cols, int64_t lds,
+                     void* dst, int64_t ldd, hipStream_t stream);
 
 // ---- sketches -------------------------------------------------------------
 size_t sketch_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int64_t m2,

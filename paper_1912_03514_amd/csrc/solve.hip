@@ -69,6 +69,7 @@ struct SolveArgs {
   int cg1;            // Gram path: single-reduction CG (one barrier per step)
   int aab;            // streaming path: AAb_Solver (Algorithm 6) instead of CG
   double* yrow;       // AAb: m doubles, -(M v - theta p) of each row of SA
+  const int* skip;    // when set and nonzero the launch returns at once
   int d, dpad, G, Gc, cpw;
   BarrierSpin spin_fast, spin_idle;
 };
@@ -272,6 +273,8 @@ __device__ __forceinline__ void rowdots(const TH* __restrict__ H, int64_t ldh, i
 // their entries of q directly); otherwise through two passes over SA rows.
 template <typename TA, typename TS, typename TV, int EPT, bool GRAM>
 __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
+  // a driver that enqueues several solves ahead stops them once it is done
+  if (a.skip && __hip_atomic_load(a.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   extern __shared__ double smem[];
   const int cpw = a.cpw;
   double* vbuf = smem;                 // x (A pass) or p (CG, as TV)
@@ -736,6 +739,86 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   }
 }
 
+// The gradient pass of Algorithm 1 on its own: partial A^T (c - A x) of one row
+// block per workgroup (c = b, or none), then a fixed-order column sum that adds
+// rhs and subtracts lambda x.  Used by drivers whose inner step is not CG.
+template <typename TA, int EPT>
+__global__ __launch_bounds__(kBlock) void grad_partial_kernel(const TA* A, int64_t n, int64_t lda,
+                                                              int d, int dpad, const double* c,
+                                                              const double* x, double* part,
+                                                              const int* skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  extern __shared__ double smem[];
+  double* vbuf = smem;
+  double* rbuf = smem + dpad;
+  for (int k = threadIdx.x; k < dpad; k += kBlock) vbuf[k] = (k < d) ? x[k] : 0.0;
+  __syncthreads();
+  const int64_t G = gridDim.x, w = blockIdx.x;
+  const int64_t r0 = n * w / G, r1 = n * (w + 1) / G;
+  double acc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) acc[e] = 0.0;
+  double ssq = 0.0;
+  rowpass<TA, double, EPT, true, RowsInFlight<TA, EPT>::value>(A, lda, r0, r1, d, vbuf, c, acc,
+                                                                 ssq);
+  wg_store_partial<TA, double, EPT>(acc, rbuf, part + w * dpad, d);
+}
+
+__global__ __launch_bounds__(kBlock) void grad_finish_kernel(const double* part, int G, int dpad,
+                                                             int d, const double* rhs,
+                                                             const double* x, double lam,
+                                                             double* g, const int* skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= d) return;
+  double s = 0.0;
+  for (int t = 0; t < G; ++t) s += part[(int64_t)t * dpad + k];
+  if (rhs) s += rhs[k];
+  g[k] = s - lam * x[k];
+}
+
+template <typename TA, int EPT>
+int launch_grad_partial(int G, size_t shmem, hipStream_t stream, const TA* A, int64_t n,
+                        int64_t lda, int d, int dpad, const double* c, const double* x,
+                        double* part, const int* skip) {
+  if (hipFuncSetAttribute((const void*)grad_partial_kernel<TA, EPT>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
+    return MIHS_ERR_HIP;
+  hipLaunchKernelGGL((grad_partial_kernel<TA, EPT>), dim3(G), dim3(kBlock), shmem, stream, A, n,
+                     lda, d, dpad, c, x, part, skip);
+  return MIHS_OK;
+}
+
+template <typename TA>
+int launch_grad_partial_ept(int ept, int G, size_t shmem, hipStream_t stream, const TA* A,
+                            int64_t n, int64_t lda, int d, int dpad, const double* c,
+                            const double* x, double* part, const int* skip) {
+  switch (ept) {
+    case 1:
+      return launch_grad_partial<TA, 1>(G, shmem, stream, A, n, lda, d, dpad, c, x, part,
+                                          skip);
+    case 2:
+      return launch_grad_partial<TA, 2>(G, shmem, stream, A, n, lda, d, dpad, c, x, part,
+                                          skip);
+    case 4:
+      return launch_grad_partial<TA, 4>(G, shmem, stream, A, n, lda, d, dpad, c, x, part,
+                                          skip);
+    case 8:
+      return launch_grad_partial<TA, 8>(G, shmem, stream, A, n, lda, d, dpad, c, x, part,
+                                          skip);
+    case 16:
+      return launch_grad_partial<TA, 16>(G, shmem, stream, A, n, lda, d, dpad, c, x, part,
+                                          skip);
+    case 32:
+      return launch_grad_partial<TA, 32>(G, shmem, stream, A, n, lda, d, dpad, c, x, part,
+                                          skip);
+    case 64:
+      return launch_grad_partial<TA, 64>(G, shmem, stream, A, n, lda, d, dpad, c, x, part,
+                                          skip);
+    default: return MIHS_ERR_UNSUPPORTED;
+  }
+}
+
 __global__ void zero_words(unsigned* p, int count) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0u;
 }
@@ -836,6 +919,38 @@ size_t solve_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_t
   return layout(G, G, dpad_for(d), no_gram ? 0 : gram_bytes_for(m, d, mixed), m).total;
 }
 
+int grad_partials(const mihs_handle* h, int64_t n, int64_t d) {
+  int64_t g = (int64_t)h->num_cu * kMaxBlocksPerCU;
+  const int64_t by_rows = (n + 63) / 64;
+  if (g > by_rows) g = by_rows < 1 ? 1 : by_rows;
+  (void)d;
+  return (int)g;
+}
+
+size_t grad_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d) {
+  return align_up((size_t)grad_partials(h, n, d) * (size_t)dpad_for(d) * 8, 256);
+}
+
+int launch_grad(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64_t d,
+                int64_t lda, const double* c, const double* rhs, const double* x, double lam,
+                double* g, void* ws, size_t ws_bytes, const int* skip, hipStream_t stream) {
+  const int ept = ept_for(d);
+  if (ept > 64) return MIHS_ERR_UNSUPPORTED;
+  if (ws_bytes < grad_workspace_bytes(h, n, d) || ws == nullptr) return MIHS_ERR_WORKSPACE;
+  const int dpad = (int)dpad_for(d);
+  const size_t shmem = 2 * (size_t)dpad * sizeof(double);
+  const int G = grad_partials(h, n, d);
+  double* part = (double*)ws;
+  const int rc = a_f32 ? launch_grad_partial_ept<float>(ept, G, shmem, stream, (const float*)A, n,
+                                                        lda, (int)d, dpad, c, x, part, skip)
+                       : launch_grad_partial_ept<double>(ept, G, shmem, stream, (const double*)A,
+                                                         n, lda, (int)d, dpad, c, x, part, skip);
+  if (rc) return rc;
+  hipLaunchKernelGGL(grad_finish_kernel, dim3((unsigned)((d + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, stream, part, G, dpad, (int)d, rhs, x, lam, g, skip);
+  return hipGetLastError() == hipSuccess ? MIHS_OK : MIHS_ERR_HIP;
+}
+
 int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_bytes,
                  hipStream_t stream) {
   const int ept = ept_for(s.d);
@@ -929,6 +1044,7 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   a.cg1 = s.mixed ? 1 : 0;
   a.aab = s.aab ? 1 : 0;
   a.yrow = (double*)(base + L.yrow);
+  a.skip = s.skip;
   if (gram) {
     const int rc = launch_gram(s.SA, s.mixed, s.m, s.d, s.ldsa, base + L.gram, s.mixed, dpad,
                                stream);

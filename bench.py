@@ -11,13 +11,14 @@ until the stop rule fires.  The timed region covers K steps of the mixed path
 the plain FP64 path; each result's error against the closed-form solution is
 checked to be <= 1e-10 after timing.
 
-Prints ONE JSON line.  --gpus above 1 is refused: this build measures one GPU.
+Prints ONE JSON line.  --gpus above 1 is refused: the solver runs on one GPU.
 
 Other workloads (opt-in, one JSON line each): --workload small_gauss (4096 x 256,
 Gaussian m = 256), batched_lambda_path (256 problems x 16 lambdas, Gaussian
 sketches, one launch), diff_2p18x1024 (64 right-hand sides, forward + adjoint
 backward through the autograd op), count_2p20x4096 (FP32 A, CountSketch ->
-Gaussian), dual_4096x2p16 (under-determined, Dual M-IHS).
+Gaussian), dual_4096x2p16 (under-determined, Dual M-IHS), pd_16384x4096
+(square-like, Primal-Dual M-IHS).
 """
 from __future__ import annotations
 
@@ -372,6 +373,72 @@ def run_dual(args):
     }
 
 
+def run_pd(args):
+    """Primal-Dual M-IHS (Algorithm 4) on the square-like workload: A 16384 x 4096
+    (FP64), SRHT m1 = 2048 of A, SRHT m2 = 2048 of Q = (SA)^T, M = 25 dual steps
+    with AAb_Solver (eps_sub = 0.1) per outer step; one step = both sketches +
+    the solve; error against the closed form."""
+    import numpy as np
+    import torch
+    import paper_1912_03514_amd as mihs
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    w = W.workload("pd_16384x4096")
+    A, b, _x0, _ = W.make_problem_torch(w.n, w.d, w.sigma, w.sd_target, w.data_seed, dev,
+                                        w.a_dtype)
+    lam = w.lam
+    log("closed-form reference")
+    xs = ref_ridge_device(A, b, lam)
+    a1, b1 = mihs.momentum(w.sd_target, w.m)
+    a2, b2 = mihs.momentum(w.sd_target, w.m2)
+    M = 25
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for prec in ("plain", "mixed"):
+        def step():
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            Q, WQ = mihs.mihs_sketch_two_stage(A, w.sketch, w.m, w.sketch_seed, w.sketch,
+                                               w.m2, w.sketch_seed + 1, precision=prec)
+            e1.record(stream)
+            x, info = mihs.mihs_solve_pd(A, b, lam, Q, WQ, a1, b1, a2, b2, M=M,
+                                         eps_sub=w.eps_sub, tol=args.tol, max_outer=60,
+                                         precision=prec, sync=False)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            return x, mihs.info_to_dict(info[0])[0], e0.elapsed_time(e1), e1.elapsed_time(e2)
+        times, outs = timed(step, args.steps, args.warmup, None)
+        x, info, sk, sv = outs[-1]
+        err = float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs))
+        out[prec] = dict(ms=float(np.mean(times)), sketch_ms=sk, solve_ms=sv, info=info, err=err)
+        log(f"  {prec}: {out[prec]['ms']:.2f} ms (sketches {sk:.2f}, solve {sv:.2f}); outer "
+            f"{info['outer_iters']}, AAb steps {info['inner_iters_total']}; err {err:.2e}")
+    pl = out["plain"]
+    outer = pl["info"]["outer_iters"]
+    # per outer step: A and b once; per dual step: Q (d x m1) once; per AAb step: WQ once
+    # (M v and M^T y come from the same pass over its rows)
+    algo = (outer * (w.n * w.d * 8 + w.n * 8) + outer * M * (w.d * w.m * 8)
+            + pl["info"]["inner_iters_total"] * (w.m2 * w.m * 8))
+    achieved = algo / (pl["solve_ms"] * 1e-3) / 1e9
+    rnd = lambda dct: {k: (round(v, 3) if isinstance(v, float) and k != "err" else v)
+                       for k, v in dct.items()}
+    return {
+        "metric": "time-to-1e-10 rel.err per square-like ridge solve (Primal-Dual M-IHS, "
+                  "FP64; two-stage SRHT + solve)",
+        "value": round(pl["ms"], 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(pl["ms"], 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "m1": w.m, "m2": w.m2, "M": M,
+                   "sd": w.sd_target, "lambda": lam, "tol": args.tol, "inner": "aab"},
+        "plain": rnd(pl), "mixed": rnd(out["mixed"]),
+        "roofline": {"bound": "hbm", "kernel": "Primal-Dual solve (all kernels, plain)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": algo},
+        "accuracy_ok": pl["err"] <= 1e-10 and out["mixed"]["err"] <= 1e-10,
+    }
+
+
 def run_small(args):
     import numpy as np
     import torch
@@ -424,18 +491,19 @@ def main():
     if args.tol is None:
         args.tol = DEFAULT_TOL.get(args.workload, 5e-11)
     if args.workload in ("batched_lambda_path", "diff_2p18x1024", "small_gauss",
-                         "dual_4096x2p16"):
+                         "dual_4096x2p16", "pd_16384x4096"):
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
             sys.exit(2)
         import paper_1912_03514_amd as mihs
         mihs.load_library()
         fn = {"batched_lambda_path": run_batched, "diff_2p18x1024": run_diff,
-              "small_gauss": run_small, "dual_4096x2p16": run_dual}[args.workload]
+              "small_gauss": run_small, "dual_4096x2p16": run_dual,
+              "pd_16384x4096": run_pd}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -220,6 +220,10 @@ WORKLOADS = {
                                 sketch_seed=9),
     "diff_2p18x1024": Workload("diff_2p18x1024", 1 << 18, 1024, "f32", "exp", 8.0, 256.0, "srht",
                                1024, eps_sub=1e-2, data_seed=4000, sketch_seed=11, nrhs=64),
+    # square-like, shaped like Figure 5's (max/min = 5e4/1e4, sd/min ~ 0.07, m1 = m2 = 8 sd)
+    # within the 4096-column limit: Primal-Dual M-IHS (Algorithm 4), M = 25 dual steps
+    "pd_16384x4096": Workload("pd_16384x4096", 1 << 14, 4096, "f64", "exp", 8.0, 256.0, "srht",
+                              2048, m2=2048, eps_sub=1e-1, data_seed=6000, sketch_seed=13),
     # under-determined, shaped like Figure 4's (n, d, m, sd) = (4000, 2^16, 4000, 462)
     "dual_4096x2p16": Workload("dual_4096x2p16", 4096, 1 << 16, "f64", "exp", 8.0, 462.0, "srht",
                                4096, eps_sub=1e-1, data_seed=5000, sketch_seed=12, dual=True),

@@ -37,6 +37,7 @@ namespace {
 constexpr int kScal = 8;           // scalar partial slots per workgroup
 constexpr double kCg1MaxCond = 1e5;  // single-reduction CG up to this trace(H)/lambda
 constexpr int kMaxBlocksPerCU = 2;
+constexpr int kQuarterRows = 4;    // rows per group in rowpass_quarters
 
 struct SolveArgs {
   const void* A;
@@ -131,6 +132,104 @@ __device__ __forceinline__ void rowpass(const TM* __restrict__ M, int64_t ld, in
       for (int e = 0; e < EPT; ++e) acc[e] += u * (TV)rv[t][e];
     }
   }
+}
+
+// Workgroup barrier without the memory fence of __syncthreads, whose release
+// would wait for every load in flight (here: the next rows, fetched ahead).
+// The caller waits for its own LDS writes first (lgkmcnt(0)); the empty asm
+// statements keep the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// The gradient pass for rows too long for one wave's registers (d > 2048): the
+// four waves split every row into quarters of 64 * EQ columns, each lane holding
+// EQ entries of its wave's quarter.  Per group of R rows every wave forms its
+// partial dot products, they meet in LDS (double-buffered, one barrier per
+// group), and each wave accumulates u_i * A_i on its own quarter, so no
+// cross-wave reduction is needed at the end.  The next group's rows are loaded
+// before the current group is processed.  u_i = c_i - A_i . v (c may be null).
+template <typename TM, int EQ, bool NT, int R>
+__device__ __forceinline__ void rowpass_quarters(const TM* __restrict__ M, int64_t ld, int64_t r0,
+                                                 int64_t r1, int d, const double* __restrict__ v,
+                                                 const double* __restrict__ c, double (&acc)[EQ],
+                                                 double* s_part) {
+  using L = RowLayout<TM, EQ>;
+  // fetch the next group during this one only while both fit in registers
+  constexpr bool PF = R * EQ * (int)sizeof(TM) <= 256;
+  const int lane = lane_id(), w = wave_id();
+  const int q0 = w * kWave * EQ;  // first column of this wave's quarter
+  const int dq = d - q0;          // valid columns from q0 (may be <= 0)
+  double vr[EQ];
+#pragma unroll
+  for (int j = 0; j < L::J; ++j)
+#pragma unroll
+    for (int vv = 0; vv < L::V; ++vv) vr[j * L::V + vv] = v[q0 + L::col(j, lane, vv)];
+  auto load_group = [&](int64_t row0, TM (&buf)[R][EQ]) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      if (row0 + t < r1) {
+        load_row<TM, EQ, NT>(M + (row0 + t) * ld + q0, dq, lane, buf[t]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < EQ; ++e) buf[t][e] = TM(0);
+      }
+    }
+  };
+  TM cur[R][EQ];
+  if constexpr (PF) load_group(r0, cur);
+  int buf = 0;
+  for (int64_t row = r0; row < r1; row += R) {
+    TM nxt[R][EQ];
+    if constexpr (PF) load_group(row + R, nxt);
+    else load_group(row, cur);
+    double dot[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      dot[t] = 0.0;
+#pragma unroll
+      for (int e = 0; e < EQ; ++e) dot[t] += (double)cur[t][e] * vr[e];
+      dot[t] = wave_sum(dot[t]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) s_part[(buf * R + t) * kWavesPerBlock + w] = dot[t];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const double* sp = s_part + (buf * R + t) * kWavesPerBlock;
+      const double total = ((sp[0] + sp[1]) + sp[2]) + sp[3];
+      const double u = (row + t < r1) ? ((c ? c[row + t] : 0.0) - total) : 0.0;
+#pragma unroll
+      for (int e = 0; e < EQ; ++e) acc[e] += u * (double)cur[t][e];
+    }
+    buf ^= 1;
+    if constexpr (PF) {
+#pragma unroll
+      for (int t = 0; t < R; ++t)
+#pragma unroll
+        for (int e = 0; e < EQ; ++e) cur[t][e] = nxt[t][e];
+    }
+  }
+}
+
+// Store a wave's quarter of the partial vector (rowpass_quarters layout).
+template <typename TM, int EQ>
+__device__ __forceinline__ void store_quarters(const double (&acc)[EQ], double* out, int d) {
+  using L = RowLayout<TM, EQ>;
+  const int lane = lane_id();
+  const int q0 = wave_id() * kWave * EQ;
+#pragma unroll
+  for (int j = 0; j < L::J; ++j)
+#pragma unroll
+    for (int vv = 0; vv < L::V; ++vv) {
+      const int col = q0 + L::col(j, lane, vv);
+      if (col < d) out[col] = acc[j * L::V + vv];
+    }
 }
 
 // Combine the four waves' per-lane partial vectors (fixed wave order) and
@@ -287,6 +386,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   TV* own_r = (TV*)(own_rhs + cpw);
   TV* own_z = (TV*)(own_rhs + 2 * cpw);
   __shared__ double s_red[2 * kWavesPerBlock];
+  __shared__ double s_part[2 * kQuarterRows * kWavesPerBlock];  // rowpass_quarters exchange
   __shared__ int s_flag;
 
   const int w = blockIdx.x;
@@ -340,7 +440,14 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
     // ---- A1 (all): partial A^T (b - A x) over this workgroup's rows
     for (int c = threadIdx.x; c < a.dpad; c += kBlock) vbuf[c] = (c < d) ? a.x[c] : 0.0;
     __syncthreads();
-    {
+    if constexpr (EPT == 64) {
+      double acc[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+      rowpass_quarters<TA, 16, true, kQuarterRows>(A, a.lda, a_r0, a_r1, d, vbuf, a.b, acc, s_part);
+      store_quarters<TA, 16>(acc, a.partA + (int64_t)w * a.dpad, d);
+      __syncthreads();
+    } else {
       double acc[EPT];
 #pragma unroll
       for (int e = 0; e < EPT; ++e) acc[e] = 0.0;
@@ -755,13 +862,22 @@ __global__ __launch_bounds__(kBlock) void grad_partial_kernel(const TA* A, int64
   __syncthreads();
   const int64_t G = gridDim.x, w = blockIdx.x;
   const int64_t r0 = n * w / G, r1 = n * (w + 1) / G;
-  double acc[EPT];
+  if constexpr (EPT == 64) {
+    __shared__ double s_part[2 * kQuarterRows * kWavesPerBlock];
+    double acc[16];
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) acc[e] = 0.0;
-  double ssq = 0.0;
-  rowpass<TA, double, EPT, true, RowsInFlight<TA, EPT>::value>(A, lda, r0, r1, d, vbuf, c, acc,
-                                                                 ssq);
-  wg_store_partial<TA, double, EPT>(acc, rbuf, part + w * dpad, d);
+    for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+    rowpass_quarters<TA, 16, true, kQuarterRows>(A, lda, r0, r1, d, vbuf, c, acc, s_part);
+    store_quarters<TA, 16>(acc, part + w * dpad, d);
+  } else {
+    double acc[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) acc[e] = 0.0;
+    double ssq = 0.0;
+    rowpass<TA, double, EPT, true, RowsInFlight<TA, EPT>::value>(A, lda, r0, r1, d, vbuf, c,
+                                                                   acc, ssq);
+    wg_store_partial<TA, double, EPT>(acc, rbuf, part + w * dpad, d);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void grad_finish_kernel(const double* part, int G, int dpad,
@@ -848,7 +964,12 @@ SolveKernel pick_kernel(int a_f32, int mixed, int ept) {
 }
 
 // The CG goes through the Gram matrix when it is no larger than SA (m >= d).
-bool use_gram(int64_t m, int64_t d) { return m >= d; }
+// MIHS_GRAM=0/1 forces the choice (tuning).
+bool use_gram(int64_t m, int64_t d) {
+  const char* env = getenv("MIHS_GRAM");
+  if (env && (env[0] == '0' || env[0] == '1')) return env[0] == '1';
+  return m >= d;
+}
 
 struct SolveLayout {
   size_t partA, partS, scal, vecs, xp, bar, gram, yrow, total;

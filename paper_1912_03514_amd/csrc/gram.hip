@@ -86,6 +86,114 @@ __global__ __launch_bounds__(kBlock) void gram_one_kernel(const TS* M, int64_t m
   gram_block<TS, TH>(M, m, ld, d, H, ldh, bi, bj);
 }
 
+// One 128 x 128 tile (bi <= bj) of H per workgroup for the single-matrix case:
+// the four waves form a 2 x 2 grid of 64 x 64 quarters (4 x 4 MFMA blocks of
+// 16 x 16 each).  16-row chunks of M are loaded with 16-byte vector loads one
+// chunk ahead into registers, converted to FP64 and stored to LDS (double-
+// buffered, one barrier per chunk).  Entries of index >= d come out zero; only
+// entries below hn (the padded size of H) are written; off-diagonal tiles are
+// mirrored.
+constexpr int kT = 128;       // tile edge
+constexpr int kKC = 16;       // rows of M per chunk
+constexpr int kLdt = kT + 4;  // LDS row stride (doubles)
+
+template <typename TS>
+struct ChunkLoad {
+  // thread t: chunk row t / 16, columns c0 + 8 (t % 16) .. + 8 of one tile
+  static constexpr int kVec = 16 / (int)sizeof(TS);
+  static constexpr int kN = 8 / kVec;  // 16-byte loads per thread per tile
+  typedef TS vec_t __attribute__((ext_vector_type(kVec)));
+  static __device__ __forceinline__ void run(const TS* __restrict__ M, int64_t m, int64_t ld,
+                                             int d, int64_t r0, int c0, double (&out)[8]) {
+    const int t = threadIdx.x;
+    const int64_t r = r0 + t / 16;
+    const int c = c0 + 8 * (t % 16);
+    if (r < m && c + 8 <= d) {
+      const TS* p = M + r * ld + c;
+#pragma unroll
+      for (int i = 0; i < kN; ++i) {
+        const vec_t v = *(const vec_t*)(p + i * kVec);
+#pragma unroll
+        for (int e = 0; e < kVec; ++e) out[i * kVec + e] = (double)v[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) out[e] = (r < m && c + e < d) ? (double)M[r * ld + c + e] : 0.0;
+    }
+  }
+};
+
+template <typename TS, typename TH>
+__global__ __launch_bounds__(kBlock) void gram_tile128_kernel(const TS* M, int64_t m, int64_t ld,
+                                                              int d, TH* H, int64_t ldh, int hn) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  __shared__ double tl[2][2][kKC][kLdt];  // [buffer][i or j tile][row][col]
+  const int lane = lane_id(), wave = wave_id();
+  const int wr = wave >> 1, wc = wave & 1;
+  const int ci0 = bi * kT, cj0 = bj * kT;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  const int srow = threadIdx.x / 16, scol = 8 * (threadIdx.x % 16);
+  double gi[8], gj[8];
+  ChunkLoad<TS>::run(M, m, ld, d, 0, ci0, gi);
+  ChunkLoad<TS>::run(M, m, ld, d, 0, cj0, gj);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    tl[0][0][srow][scol + e] = gi[e];
+    tl[0][1][srow][scol + e] = gj[e];
+  }
+  __syncthreads();
+  const int64_t nchunks = (m + kKC - 1) / kKC;
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int cur = (int)(ch & 1);
+    const bool more = ch + 1 < nchunks;
+    if (more) {
+      ChunkLoad<TS>::run(M, m, ld, d, (ch + 1) * kKC, ci0, gi);
+      ChunkLoad<TS>::run(M, m, ld, d, (ch + 1) * kKC, cj0, gj);
+    }
+#pragma unroll
+    for (int ks = 0; ks < kKC / 4; ++ks) {
+      const int r = 4 * ks + (lane >> 4);
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = tl[cur][0][r][wr * 64 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = tl[cur][1][r][wc * 64 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        tl[cur ^ 1][0][srow][scol + e] = gi[e];
+        tl[cur ^ 1][1][srow][scol + e] = gj[e];
+      }
+    }
+    __syncthreads();
+  }
+  // result register r of lane l: row l/16 + 4 r, column l % 16 of each 16 x 16 block
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ci0 + wr * 64 + a * 16 + (lane >> 4) + 4 * r;
+        const int j = cj0 + wc * 64 + b * 16 + (lane & 15);
+        if (i < hn && j < hn) {
+          H[(int64_t)i * ldh + j] = (TH)acc[a][b][r];
+          if (bi != bj) H[(int64_t)j * ldh + i] = (TH)acc[a][b][r];
+        }
+      }
+}
+
 }  // namespace
 
 int launch_gram_jobs(const GramJob* d_jobs, int64_t njobs, int m_f32, hipStream_t st) {
@@ -101,6 +209,25 @@ int launch_gram(const void* M, int m_f32, int64_t m, int64_t d, int64_t ld, void
                 int64_t ldh, hipStream_t st) {
   const unsigned nb = (unsigned)((d + 63) / 64);
   if (ldh < 64 * (int64_t)nb) return MIHS_ERR_INVALID;
+  const int hn = 64 * (int)nb;
+  if (d > 64) {
+    // 128 x 128 tiles: a quarter of the 64 x 64 form's reloads of M
+    const unsigned nt = (unsigned)((d + kT - 1) / kT);
+    const dim3 grid(nt, nt);
+    if (m_f32 && h_f32)
+      gram_tile128_kernel<float, float><<<grid, dim3(kBlock), 0, st>>>(
+          (const float*)M, m, ld, (int)d, (float*)H, ldh, hn);
+    else if (m_f32)
+      gram_tile128_kernel<float, double><<<grid, dim3(kBlock), 0, st>>>(
+          (const float*)M, m, ld, (int)d, (double*)H, ldh, hn);
+    else if (h_f32)
+      gram_tile128_kernel<double, float><<<grid, dim3(kBlock), 0, st>>>(
+          (const double*)M, m, ld, (int)d, (float*)H, ldh, hn);
+    else
+      gram_tile128_kernel<double, double><<<grid, dim3(kBlock), 0, st>>>(
+          (const double*)M, m, ld, (int)d, (double*)H, ldh, hn);
+    return hipGetLastError() == hipSuccess ? MIHS_OK : MIHS_ERR_HIP;
+  }
   const dim3 grid(nb, nb);
   if (m_f32 && h_f32)
     gram_one_kernel<float, float><<<grid, dim3(kBlock), 0, st>>>((const float*)M, m, ld, (int)d,

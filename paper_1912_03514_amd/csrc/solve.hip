@@ -880,17 +880,29 @@ __global__ __launch_bounds__(kBlock) void grad_partial_kernel(const TA* A, int64
   }
 }
 
+// 32 columns per workgroup; the 8 thread rows of a column sum interleaved
+// partials (t = q, q + 8, ...) and meet in LDS in a fixed order.
+constexpr int kFinCols = 32;
 __global__ __launch_bounds__(kBlock) void grad_finish_kernel(const double* part, int G, int dpad,
                                                              int d, const double* rhs,
                                                              const double* x, double lam,
                                                              double* g, const int* skip) {
   if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k >= d) return;
+  __shared__ double red[kBlock / kFinCols][kFinCols];
+  constexpr int Q = kBlock / kFinCols;
+  const int cl = threadIdx.x % kFinCols, q = threadIdx.x / kFinCols;
+  const int k = blockIdx.x * kFinCols + cl;
   double s = 0.0;
-  for (int t = 0; t < G; ++t) s += part[(int64_t)t * dpad + k];
-  if (rhs) s += rhs[k];
-  g[k] = s - lam * x[k];
+  if (k < d)
+    for (int t = q; t < G; t += Q) s += part[(int64_t)t * dpad + k];
+  red[q][cl] = s;
+  __syncthreads();
+  if (q == 0 && k < d) {
+    double tot = red[0][cl];
+    for (int i = 1; i < Q; ++i) tot += red[i][cl];
+    if (rhs) tot += rhs[k];
+    g[k] = tot - lam * x[k];
+  }
 }
 
 template <typename TA, int EPT>
@@ -1067,8 +1079,8 @@ int launch_grad(const mihs_handle* h, const void* A, int a_f32, int64_t n, int64
                        : launch_grad_partial_ept<double>(ept, G, shmem, stream, (const double*)A,
                                                          n, lda, (int)d, dpad, c, x, part, skip);
   if (rc) return rc;
-  hipLaunchKernelGGL(grad_finish_kernel, dim3((unsigned)((d + kBlock - 1) / kBlock)), dim3(kBlock),
-                     0, stream, part, G, dpad, (int)d, rhs, x, lam, g, skip);
+  hipLaunchKernelGGL(grad_finish_kernel, dim3((unsigned)((d + kFinCols - 1) / kFinCols)),
+                     dim3(kBlock), 0, stream, part, G, dpad, (int)d, rhs, x, lam, g, skip);
   return hipGetLastError() == hipSuccess ? MIHS_OK : MIHS_ERR_HIP;
 }
 

@@ -265,6 +265,25 @@ __device__ __forceinline__ TV wg_sum_ssq(TV ssq, double* s_red) {
   return (TV)t;
 }
 
+// Two workgroup sums at once (fixed wave order, the same result as two
+// block_sum calls, with one pair of barriers).
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* s_red2) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if (lane_id() == 0) {
+    s_red2[2 * wave_id()] = a;
+    s_red2[2 * wave_id() + 1] = b;
+  }
+  __syncthreads();
+  a = s_red2[0];
+  b = s_red2[1];
+  for (int w = 1; w < kWavesPerBlock; ++w) {
+    a += s_red2[2 * w];
+    b += s_red2[2 * w + 1];
+  }
+}
+
 // Two scalar sums over K workgroups' slots (fixed order), returned to every thread.
 __device__ __forceinline__ void sum2_slots(const double* scal, int K, int s0, int s1,
                                            double* s_red2, double& o0, double& o1) {
@@ -329,13 +348,15 @@ __device__ __forceinline__ void owned_column_sums(const T* __restrict__ P, int K
   }
 }
 
-// out[c - r0] = H[c, :] . v for rows c in [r0, r1) (one row per wave at a time,
-// two when rows are short), in a fixed order.
+// out[c - r0] = H[c, :] . v for rows c in [r0, r1), in a fixed order.  Each
+// wave loads up to 512 bytes per lane of rows (at most 4 rows) before using
+// any: a CG workgroup owns few rows, so this is usually one round trip.
 template <typename TH, typename TV, int EPT>
 __device__ __forceinline__ void rowdots(const TH* __restrict__ H, int64_t ldh, int r0, int r1,
                                         int d, const TV* __restrict__ v, double* out) {
   using L = RowLayout<TH, EPT>;
-  constexpr int R = EPT <= 16 ? 2 : 1;
+  constexpr int RB = 512 / (EPT * (int)sizeof(TH));
+  constexpr int R = RB < 1 ? 1 : (RB > 4 ? 4 : RB);
   const int lane = lane_id();
   for (int c = r0 + wave_id() * R; c < r1; c += kWavesPerBlock * R) {
     TH rv[R][EPT];
@@ -413,6 +434,11 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
     own_xp[i] = a.xp_from_x ? a.x[c] : a.xp[c];
     own_rhs[i] = a.rhs ? a.rhs[c] : 0.0;
   }
+  // this workgroup's rows of the CG operator H (read from L2 / Infinity Cache
+  // on every step; keeping them in LDS measured slower: the step is bound by
+  // its barrier and round trips, not by these reads)
+  const TS* Hrows = (GRAM && in_cg) ? (const TS*)a.H + (int64_t)c_lo * a.ldh : nullptr;
+  const int64_t ldhr = a.ldh;
   __syncthreads();
 
   // Single-reduction CG only where the sub-problem is well conditioned for its
@@ -586,14 +612,13 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           // alternating) and owns p and z on its columns.
           TV* rv = (TV*)vbuf;
           TV* sv = (TV*)rbuf;
-          const TS* Hm = (const TS*)a.H;
           const TV lt = (TV)a.lam;
           for (int c = threadIdx.x; c < a.dpad; c += kBlock) rv[c] = (c < d) ? r[c] : TV(0);
           __syncthreads();
           int wb = 0;
           double mu = rr0, alpha = 0.0, unused2;
           {
-            rowdots<TS, TV, EPT>(Hm, a.ldh, c_lo, c_hi, d, rv, colbuf);
+            rowdots<TS, TV, EPT>(Hrows, ldhr, 0, nown, d, rv, colbuf);
             __syncthreads();
             double nu_part = 0.0;
             for (int i = threadIdx.x; i < nown; i += kBlock) {
@@ -622,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
               __syncthreads();
               ++k;
               wb ^= 1;
-              rowdots<TS, TV, EPT>(Hm, a.ldh, c_lo, c_hi, d, rv, colbuf);
+              rowdots<TS, TV, EPT>(Hrows, ldhr, 0, nown, d, rv, colbuf);
               __syncthreads();
               double mu_p = 0.0, nu_p = 0.0;
               for (int i = threadIdx.x; i < nown; i += kBlock) {
@@ -632,13 +657,20 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 mu_p += (double)rc * (double)rc;
                 nu_p += (double)wc * (double)rc;
               }
-              mu_p = block_sum(mu_p, s_red);
-              nu_p = block_sum(nu_p, s_red);
+              block_sum2(mu_p, nu_p, s_red);
               if (threadIdx.x == 0) {
                 scal_w[2] = mu_p;
                 scal_w[3] = nu_p;
               }
               if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              // fetch w (written by every CG workgroup before the barrier) while
+              // the scalar partials are summed
+              TV wpre[NPT];
+#pragma unroll
+              for (int i = 0; i < NPT; ++i) {
+                const int c = threadIdx.x + i * kBlock;
+                wpre[i] = (c < d) ? P[wb][c] : TV(0);
+              }
               double mu_n, nu_n;
               sum2_slots(a.scal, Gc, 2, 3, s_red, mu_n, nu_n);
               if (mu_n <= stop || k >= a.max_inner) break;
@@ -653,8 +685,11 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
               alpha = an;
               // s = w + beta s (full), p = r + beta p (owned)
               const TV btt = (TV)bt;
-              for (int c = threadIdx.x; c < a.dpad; c += kBlock)
-                sv[c] = ((c < d) ? P[wb][c] : TV(0)) + btt * sv[c];
+#pragma unroll
+              for (int i = 0; i < NPT; ++i) {
+                const int c = threadIdx.x + i * kBlock;
+                if (c < a.dpad) sv[c] = wpre[i] + btt * sv[c];
+              }
               for (int i = threadIdx.x; i < nown; i += kBlock)
                 own_r[i] = rv[c_lo + i] + btt * own_r[i];
               __syncthreads();
@@ -706,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
             double rpart = 0.0;
             if (GRAM) {
               // q = H p + lambda p on the owned columns (colbuf <- H p)
-              rowdots<TS, TV, EPT>((const TS*)a.H, a.ldh, c_lo, c_hi, d, vp, colbuf);
+              rowdots<TS, TV, EPT>(Hrows, ldhr, 0, nown, d, vp, colbuf);
               __syncthreads();
               double pq = 0.0;
               for (int i = threadIdx.x; i < nown; i += kBlock) {

@@ -617,6 +617,31 @@ def main():
     sd_est = {p: sd_estimate(p) for p in ("mixed", "plain")}
     log(f"  {sd_est}")
 
+    def aab_solve(precision, reps=3):
+        """The same solve with AAb_Solver (Algorithm 6) as the inner solver (it
+        streams SA on every step; no Gram matrix)."""
+        SA = mihs.mihs_sketch(A, w.sketch, w.m, w.sketch_seed, precision=precision, m2=w.m2)
+        ws = mihs.SolveWorkspace(w.n, w.d, w.m, precision, dev)
+        ts, info, x = [], None, None
+        for _ in range(reps):
+            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            torch.cuda.synchronize()
+            e0.record(stream)
+            x, info = mihs.mihs_solve(A, b, lam, SA, alpha, beta, eps_sub=w.eps_sub, tol=args.tol,
+                                      max_outer=300, max_inner=2000, precision=precision,
+                                      workspace=ws, sync=False, inner="aab")
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        inf = mihs.info_to_dict(info)[0]
+        err = float(np.linalg.norm(x.cpu().numpy() - x_ref) / np.linalg.norm(x_ref))
+        return {"solve_ms": round(float(np.mean(ts[1:])), 3), "outer_iters": inf["outer_iters"],
+                "inner_iters": inf["inner_iters_total"], "rel_err": err}
+
+    log("AAb_Solver as the inner solver (Algorithm 6)")
+    aab = {p: aab_solve(p) for p in ("mixed", "plain")}
+    log(f"  {aab}")
+
     mx, pl = out["mixed"], out["plain"]
     info = mx["infos"][-1]
     s_a = 8 if w.a_dtype == "f64" else 4
@@ -656,6 +681,7 @@ def main():
                   "inner_iters": pl["infos"][-1]["inner_iters_total"],
                   "max_rel_err": max(pl["errs"])},
         "a_pass_bytes": apass_bytes,
+        "aab_inner": aab,
         "sd_estimate": {"sd_true": w.sd_target, "m": w.m_out,
                         "mixed_solve_ms_per_outer_iter": round(mx["solve_ms"] / max(1, outer), 3),
                         **{p: v for p, v in sd_est.items()}},

@@ -215,7 +215,8 @@ int mihs_solve_dual(mihs_handle_t handle, const void* At, mihs_dtype_t a_dtype, 
  * dual by M M-IHS steps on
  *     min_z 1/2 ||Q z - g||^2 + lambda/2 ||z||^2,   Q = (S A)^T  (z in R^{m1}),
  * with the second sketch WQ = W Q, then dx = (g - Q z) / lambda.  The dual
- * steps use `inner` (AAb_Solver in the paper) with forcing term eps_sub, and
+ * steps use `inner` (AAb_Solver in the paper; CG goes through the Gram matrix
+ * of WQ, formed once per call, when m2 >= m1) with forcing term eps_sub, and
  * z with its momentum state carries over between outer steps
  * (z^{i+1,1} = z^{i,M+1}, z^{i+1,0} = z^{i,M}).  Momentum (Corollary 4):
  * beta_l = sd / m_l, alpha_l = (1 - beta_l)^2 for l = 1 (outer), 2 (dual).

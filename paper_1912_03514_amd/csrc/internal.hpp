@@ -43,6 +43,9 @@ struct SolveDesc {
   int aab = 0;
   // device flag: when nonzero at launch time the solve returns at once
   const int* skip = nullptr;
+  // 1: the Gram matrix of SA is already in this workspace (an earlier call with
+  // the same SA and workspace formed it)
+  int gram_ready = 0;
 };
 
 // g = A^T (c - A x) + rhs - lambda x (c and rhs may be null) for A n x d, d <= 4096;

@@ -12,8 +12,8 @@
 // Per outer step the host enqueues, on one stream and without waiting:
 //   gradient pass over the outer matrix     (two kernels)
 //   the dual steps: one persistent solve on Q in ridge mode with b = g,
-//     sketch WQ, M iterations, AAb_Solver or CG inner, warm-started from
-//     (z, z_prev)                            (solve kernel)
+//     sketch WQ, M iterations, AAb_Solver or CG inner (CG through the Gram
+//     matrix of WQ, formed once), warm-started from (z, z_prev)  (solve kernel)
 //   t = Q z                                  (row dot products)
 //   dx, heavy-ball update, relative-step test (one workgroup)
 // The update kernel raises a device flag once the stop rule holds or the inner
@@ -153,7 +153,7 @@ PdLayout pd_layout(const mihs_handle* h, int64_t rows, int64_t cols, int64_t m1,
   L.z = off;     off += vm;
   L.zp = off;    off += vm;
   L.grad = off;  off += grad_workspace_bytes(h, rows, cols);
-  L.solve = off; off += solve_workspace_bytes(h, cols, m1, m2, mixed, /*no_gram=*/1);
+  L.solve = off; off += solve_workspace_bytes(h, cols, m1, m2, mixed, /*no_gram=*/0);
   L.total = off;
   return L;
 }
@@ -207,7 +207,9 @@ int launch_pd(const mihs_handle* h, const PdDesc& p, void* ws, size_t ws_bytes,
   s.x = z;
   s.x_prev = zp;
   s.info = iinfo;
-  s.no_gram = 1;  // WQ is small; the Gram matrix would be rebuilt every outer step
+  // AAb_Solver streams WQ; CG goes through the Gram matrix of WQ when m2 >= m1,
+  // formed by the first outer step and reused by the later ones
+  s.no_gram = p.aab ? 1 : 0;
   s.aab = p.aab;
   s.skip = done;
   const unsigned mv_blocks = (unsigned)ceil_div(p.cols, kWavesPerBlock);
@@ -215,6 +217,7 @@ int launch_pd(const mihs_handle* h, const PdDesc& p, void* ws, size_t ws_bytes,
     int rc = launch_grad(h, p.A, p.a_f32, p.rows, p.cols, p.lda, p.c, p.rhs, p.x, p.lam, g,
                          base + L.grad, L.solve - L.grad, done, stream);
     if (rc) return rc;
+    s.gram_ready = i > 0 ? 1 : 0;
     rc = launch_solve(h, s, base + L.solve, L.total - L.solve, stream);
     if (rc) return rc;
     if (p.mixed)

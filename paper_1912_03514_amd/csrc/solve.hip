@@ -1133,7 +1133,11 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   // size (and with it the LDS request) depends on the grid.
   int G = 0, Gc = 0, cpw = 0;
   size_t shmem = 0;
-  const int64_t g_rows = (s.n + 63) / 64;  // keep >= ~64 rows of A per workgroup
+  // keep >= ~64 rows of A per workgroup (MIHS_ROWS_PER_WG overrides; tuning)
+  int64_t rows_per_wg = 64;
+  if (const char* env = getenv("MIHS_ROWS_PER_WG"))
+    if (atoi(env) > 0) rows_per_wg = atoi(env);
+  const int64_t g_rows = (s.n + rows_per_wg - 1) / rows_per_wg;
   for (int occ_try = kMaxBlocksPerCU; occ_try >= 1; --occ_try) {
     int g = h->num_cu * occ_try;
     if ((int64_t)g > g_rows) g = (int)(g_rows < 1 ? 1 : g_rows);
@@ -1213,7 +1217,7 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   a.aab = s.aab ? 1 : 0;
   a.yrow = (double*)(base + L.yrow);
   a.skip = s.skip;
-  if (gram) {
+  if (gram && !s.gram_ready) {
     const int rc = launch_gram(s.SA, s.mixed, s.m, s.d, s.ldsa, base + L.gram, s.mixed, dpad,
                                stream);
     if (rc) return rc;

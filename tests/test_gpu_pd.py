@@ -38,14 +38,14 @@ def test_transpose_is_exact(rows, cols, dt):
     assert np.array_equal(T, M.T)
 
 
-@pytest.mark.parametrize("inner", ["aab", "cg"])
-def test_tall_follows_oracle_trajectory(inner):
+@pytest.mark.parametrize("inner,m1,m2", [("aab", 70, 66), ("cg", 70, 66), ("cg", 64, 72)])
+def test_tall_follows_oracle_trajectory(inner, m1, m2):
     """Algorithm 4, N = 6 outer steps of M = 5 dual steps each (ragged sizes):
     the GPU iterate equals the oracle's up to rounding and every inner count
-    matches."""
+    matches (CG streams WQ for m2 < m1 and goes through its Gram matrix, formed
+    once per solve, for m2 >= m1)."""
     mihs = _mihs()
     P = _tall(3001, 300, 15.0, seed=41)
-    m1, m2 = 70, 66
     SA, WQ = _sketches(P.A, m1, m2, 5)
     a, b = O.momentum_cor4(15.0, m1)
     a2, b2 = O.momentum_cor4(15.0, m2)

@@ -182,7 +182,11 @@ def timed(fn, steps, warmup, stream):
 def run_batched(args):
     """256 problems x 16 lambdas (n_k in [4096, 65536], d_k in [64, 512], FP64 A),
     one Gaussian sketch per problem (mixed: BF16 on the matrix cores), then all
-    4096 lambda-path solves in one launch of the block kernel."""
+    4096 lambda-path solves in one launch of the block kernel.  The launch shape
+    is chosen by the library's autotuner (untimed, once); one step (the 256
+    sketches, x^1 = 0 and the batched launch) is captured in a HIP graph and the
+    timed steps are graph replays.  The same step run eagerly is reported beside
+    it."""
     import numpy as np
     import torch
     import paper_1912_03514_amd as mihs
@@ -190,11 +194,20 @@ def run_batched(args):
     dev = torch.device("cuda", 0)
     specs = W.batched_specs()
     log(f"drawing {len(specs)} problems on the GPU")
-    probs = []
+    probs, sks = [], []
+    ws_bytes = 0
     for s in specs:
         sig = W.sigma_profile("exp", s.d, 6.0)
         A, b, _, _ = W.make_problem_torch(s.n, s.d, sig, s.d / 2, s.seed, dev, "f64")
-        probs.append((A, b))
+        ld = (s.d + 1) // 2 * 2  # 16-byte rows, so nothing is copied inside the step
+        Ab = torch.zeros((s.n, ld), dtype=torch.float64, device=dev)
+        Ab[:, :s.d] = A
+        del A
+        lds = (s.d + 3) // 4 * 4
+        sks.append(torch.zeros((s.m, lds), dtype=torch.float32, device=dev)[:, :s.d])
+        probs.append((Ab[:, :s.d], b))
+        ws_bytes = max(ws_bytes, mihs.sketch_workspace_bytes(s.n, s.d, s.m, "gaussian", "mixed"))
+    sk_ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     nlam = len(specs[0].lambdas)
     lam = np.stack([s.lambdas for s in specs])
@@ -208,21 +221,50 @@ def run_batched(args):
     be_d = torch.as_tensor(betas, device=dev)
     eps_sub = 0.1
 
-    def step():
-        sk = [mihs.mihs_sketch(A, "gaussian", s.m, 10 + i, precision="mixed")
-              for i, ((A, b), s) in enumerate(zip(probs, specs))]
-        ev = torch.cuda.Event(enable_timing=True)
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        xs, infos = mihs.mihs_solve_batched([(A, b, SA) for (A, b), SA in zip(probs, sk)],
-                                            lam_d, al_d, be_d, eps_sub=eps_sub, tol=args.tol,
-                                            max_outer=400, max_inner=2000)
-        ev.record()
-        torch.cuda.synchronize()
-        return xs, infos, ev0.elapsed_time(ev)
+    def sketch_all():
+        for i, ((A, b), s) in enumerate(zip(probs, specs)):
+            mihs.mihs_sketch(A, "gaussian", s.m, 10 + i, precision="mixed", out=sks[i],
+                             workspace=sk_ws)
 
-    times, outs = timed(step, args.steps, args.warmup, None)
-    xs, infos, solve_ms = outs[-1]
+    sketch_all()
+    solver = mihs.BatchedSolver([(A, b, SA) for (A, b), SA in zip(probs, sks)], lam_d, al_d,
+                                be_d, eps_sub=eps_sub, tol=args.tol, max_outer=400,
+                                max_inner=2000)
+    log("autotuning the launch shape (8 outer iterations per trial)")
+    t0 = time.perf_counter()
+    tune = solver.tune(trial_outer=8)
+    tune["wall_s"] = round(time.perf_counter() - t0, 2)
+    log(f"  {tune}")
+
+    def step():
+        sketch_all()
+        solver.run()
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def eager_step():
+        ev[0].record()
+        sketch_all()
+        ev[1].record()
+        solver.run()
+        ev[2].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+
+    eager_times, eager_outs = timed(eager_step, 1, 1, None)
+    sketch_ms, solve_ms = eager_outs[-1]
+    log("capturing one step (256 sketches + batched launch) in a HIP graph")
+    graph = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream(device=dev)
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(graph, stream=cs):
+            step()
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    times, _ = timed(graph.replay, args.steps, args.warmup, None)
+    infos = solver.infos()
+    xs = solver.xs
     # sampled accuracy against the closed form (host)
     errs = []
     for i in (0, 97, 255):
@@ -234,22 +276,30 @@ def run_batched(args):
     outer = np.array([[r["outer_iters"] for r in inf] for inf in infos])
     inner = np.array([[r["inner_iters_total"] for r in inf] for inf in infos])
     status = np.array([[r["status"] for r in inf] for inf in infos])
+    elapsed = np.array([inf[0]["elapsed_us"] for inf in infos]) * 1e-3
+    slow = np.argsort(-elapsed)[:5]
     apass = sum(s.n * s.d * 8 for s in specs)
-    rounds = int(outer.max(axis=1).sum())  # passes over each A (one per outer round)
     achieved = sum(s.n * s.d * 8 * int(outer[i].max()) for i, s in enumerate(specs)) / (solve_ms * 1e-3) / 1e9
     flops = sum(4.0 * s.n * s.d * 16 * int(outer[i].max()) for i, s in enumerate(specs))
+    value = float(np.mean(times))
     return {
         "metric": "time to solve 256 ridge problems x 16 lambdas to 1e-10 (sketch + batched M-IHS)",
-        "value": round(float(np.mean(times)), 3), "unit": "ms", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(float(np.mean(times)), 3),
+        "value": round(value, 3), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(value, 3),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 (BF16 sketches)", "data": "synthetic",
         "config": {"workload": "batched_lambda_path", "problems": len(specs), "nlam": nlam,
                    "n_range": [4096, 65536], "d_range": [64, 512], "eps_sub": eps_sub,
                    "tol": args.tol, "a_bytes_total": apass},
-        "solve_ms": round(solve_ms, 3), "sketch_ms": round(float(np.mean(times)) - solve_ms, 3),
+        "timing": "HIP-graph replay of one step (256 sketches + batched launch)",
+        "eager_step_ms": round(float(np.mean(eager_times)), 3),
+        "solve_ms": round(solve_ms, 3), "sketch_ms": round(sketch_ms, 3),
+        "tuning": tune,
         "outer_iters_max": int(outer.max()), "outer_iters_mean": float(outer.mean()),
         "inner_iters_mean": float(inner.mean()), "all_converged": bool((status == 0).all()),
+        "slowest_entries": [{"problem": int(i), "n": specs[i].n, "d": specs[i].d,
+                             "ms": round(float(elapsed[i]), 2),
+                             "outer_max": int(outer[i].max())} for i in slow],
         "sampled_max_rel_err": max(errs),
         "roofline": {"bound": "mfma", "kernel": "batched_kernel", "achieved": round(flops / (solve_ms * 1e-3) / 1e12, 2),
                      "peak": 78.6, "unit": "TFLOP/s", "frac": round(flops / (solve_ms * 1e-3) / 1e12 / 78.6, 4),

@@ -93,7 +93,9 @@ typedef struct {
   double rel_step;            /* last ||x^{i+1} - x^i|| / ||x^{i+1}|| */
   double grad_norm;           /* ||g|| at the last outer iteration */
   int32_t status;             /* MIHS_CONVERGED, MIHS_MAX_ITER, ... */
-  int32_t reserved;
+  int32_t elapsed_us;         /* batched and multi-RHS solves: wall time of the
+                                 record's entry (its group of up to 16 columns)
+                                 on its workgroups, in microseconds; 0 elsewhere */
 } mihs_info_t;
 
 /* Create a handle bound to HIP device `device` (it queries the CU count and
@@ -334,7 +336,8 @@ int mihs_solve_multi(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, 
  * per pass).  h_problems is the host copy of the table the call schedules
  * from (large problems get teams of workgroups, small ones share one);
  * d_problems may be NULL.  The call copies its schedule to the workspace and
- * waits for that copy before it returns.
+ * waits for that copy before it returns (mihs_batched_plan_create and
+ * mihs_batched_plan_run below split the two halves).
  * ------------------------------------------------------------------------ */
 typedef struct {
   const void* A;    /* n x d, row stride lda (double) */
@@ -355,6 +358,83 @@ int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
                        mihs_precision_t precision, double eps_sub, double tol,
                        int64_t max_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
                        void* stream);
+
+/* ------------------------------------------------------------------------
+ * Tunable shape of the batched launch (not in the paper; the schedule and the
+ * tiling of the one persistent launch above).
+ *   cg_cols       columns of the Gram matrix owned by one workgroup of a
+ *                 problem's inner-CG sub-team (16, 32 or 64): the sub-team has
+ *                 ceil(d / cg_cols) members, at most the problem's team;
+ *   a_dma         1: each pass over A moves 64 KiB groups of rows straight
+ *                 into LDS (rows of 1-4 KiB); 0: 16-row tiles staged through
+ *                 registers;
+ *   inner_weight  the expected inner-CG cost per outer iteration, in passes
+ *                 over H per column group, used to size the teams (team size
+ *                 proportional to n d + inner_weight d^2; 1 to 10000).
+ * mihs_batched_default_tuning() fills the defaults (32, 1, 100).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t cg_cols;
+  int32_t a_dma;
+  double inner_weight;
+} mihs_batched_tuning_t;
+
+void mihs_batched_default_tuning(mihs_batched_tuning_t* tuning);
+
+/* ------------------------------------------------------------------------
+ * The batched solve split into a plan and a launch, for callers that capture
+ * the launch in a HIP graph or repeat it (same problems, new data in b, SA or
+ * X at the same addresses).
+ *
+ * mihs_batched_plan_create  validates the problems as mihs_solve_batched does,
+ *   schedules them, writes the schedule tables into `workspace` (which must
+ *   stay allocated and untouched for the plan's lifetime; its size comes from
+ *   mihs_solve_batched_workspace_size) and waits for that copy.  `tuning`
+ *   NULL takes the handle's tuned choice for this problem set (see
+ *   mihs_tune_batched) or the defaults.  The host pointers in h_problems,
+ *   lambdas, alphas and betas are device addresses recorded in the plan.
+ * mihs_batched_plan_run  enqueues the solve on `stream`: a fill kernel that
+ *   clears the barrier words, the Gram matrices of the sketches, then the
+ *   persistent kernel.  It does not synchronise, allocate, copy from the host
+ *   or issue a memset, so it may be captured in a HIP graph; under capture the
+ *   persistent kernel goes in as an ordinary launch of one workgroup per
+ *   compute unit (the plan checked that one fits per unit; every wait is
+ *   bounded and ends in MIHS_BARRIER_TIMEOUT).  X is read as the start x^1
+ *   and overwritten; reset it between runs to restart from zero.  Runs of one
+ *   plan, or of plans sharing a workspace, must not overlap.
+ * mihs_batched_plan_destroy  frees the plan (not the workspace).
+ * ------------------------------------------------------------------------ */
+typedef struct mihs_batched_plan* mihs_batched_plan_t;
+
+int mihs_batched_plan_create(mihs_handle_t handle, const mihs_problem_t* h_problems,
+                             int64_t nprob, const double* lambdas, const double* alphas,
+                             const double* betas, int64_t nlam, mihs_precision_t precision,
+                             double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+                             const mihs_batched_tuning_t* tuning, void* workspace,
+                             size_t ws_bytes, void* stream, mihs_batched_plan_t* plan);
+int mihs_batched_plan_run(mihs_batched_plan_t plan, void* stream);
+int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
+
+/* ------------------------------------------------------------------------
+ * Autotuner of the batched launch shape.  Times trial solves of the given
+ * problems (each from X = 0, at most trial_outer outer iterations, HIP events
+ * on `stream`) over candidate shapes by coordinate descent: inner_weight in
+ * {25, 100, 400}, then cg_cols in {16, 32, 64}, then a_dma in {1, 0}.  The best
+ * shape is returned in *best and kept in the handle, keyed by the problem set's
+ * shapes (n, d, m of every problem and nlam); later mihs_solve_batched and
+ * mihs_batched_plan_create calls on an equal set use it.  cand_ms (nullable,
+ * room for MIHS_TUNE_MAX_CANDIDATES floats) receives each trial's time in
+ * candidate order and *ncand their count (nullable).  The trials overwrite X
+ * and info: initialise X after tuning.  Blocks until the trials end.
+ * ------------------------------------------------------------------------ */
+#define MIHS_TUNE_MAX_CANDIDATES 16
+
+int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, int64_t nprob,
+                      const double* lambdas, const double* alphas, const double* betas,
+                      int64_t nlam, mihs_precision_t precision, double eps_sub, double tol,
+                      int64_t trial_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
+                      void* stream, mihs_batched_tuning_t* best, float* cand_ms,
+                      int32_t* ncand);
 
 /* ------------------------------------------------------------------------
  * Backward of x*_j = (A^T A + lambda I)^{-1} A^T b_j for k right-hand sides.

@@ -10,7 +10,8 @@ device memory and the current HIP stream.
     x, info = mihs.mihs_solve(A, b, lam, SA, alpha, beta)  # Algorithm 1
 """
 from ._binding import (  # noqa: F401
-    EXPORTED, INFO_BYTES, LIB_PATH, MihsError, SolveWorkspace, handle, info_to_dict,
+    EXPORTED, INFO_BYTES, LIB_PATH, BatchedSolver, MihsError, SolveWorkspace, handle,
+    info_to_dict, sketch_workspace_bytes,
     load_library, mihs_estimate_sd, mihs_sketch, mihs_sketch_two_stage, mihs_solve,
     mihs_solve_backward, mihs_solve_batched, mihs_solve_dual, mihs_solve_multi, mihs_solve_pd,
     mihs_solve_pd_dual, mihs_transpose, MIHSRidge, momentum,

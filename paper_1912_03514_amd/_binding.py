@@ -38,11 +38,22 @@ class Info(ctypes.Structure):
         ("rel_step", ctypes.c_double),
         ("grad_norm", ctypes.c_double),
         ("status", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("elapsed_us", ctypes.c_int32),
     ]
 
 
 INFO_BYTES = ctypes.sizeof(Info)  # 48
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("cg_cols", ctypes.c_int32), ("a_dma", ctypes.c_int32),
+                ("inner_weight", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"cg_cols": self.cg_cols, "a_dma": self.a_dma, "inner_weight": self.inner_weight}
+
+
+TUNE_MAX_CANDIDATES = 16
 
 
 class Problem(ctypes.Structure):
@@ -98,6 +109,13 @@ _SIGS = {
     "mihs_solve_batched_workspace_size": (_int, [_vp, _vp, _i64, _i64, _int, ctypes.POINTER(_sz)]),
     "mihs_solve_batched": (_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl,
                                   _i64, _i64, _vp, _sz, _vp]),
+    "mihs_batched_default_tuning": (None, [_vp]),
+    "mihs_batched_plan_create": (_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl,
+                                        _i64, _i64, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "mihs_batched_plan_run": (_int, [_vp, _vp]),
+    "mihs_batched_plan_destroy": (_int, [_vp]),
+    "mihs_tune_batched": (_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl, _i64,
+                                 _i64, _vp, _sz, _vp, _vp, _vp, _vp]),
     "mihs_solve_backward_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
                                                   ctypes.POINTER(_sz)]),
     "mihs_solve_backward": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _int,
@@ -186,9 +204,13 @@ def momentum(sd: float, m: int) -> Tuple[float, float]:
 
 
 def mihs_sketch(A: torch.Tensor, kind: str, m: int, seed: int, precision: str = "plain",
-                m2: int = 0) -> torch.Tensor:
+                m2: int = 0, out: Optional[torch.Tensor] = None,
+                workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """SA = S A on the GPU (see include/mihs.h).  Returns an (m or m2) x d tensor,
-    float64 for the plain path and float32 for the mixed path."""
+    float64 for the plain path and float32 for the mixed path.  `out` (rows x d of
+    that type, 16-byte aligned rows) and `workspace` (uint8, at least
+    sketch_workspace_bytes) may be given to run without allocating, e.g. inside a
+    captured graph."""
     if A.dim() != 2 or not A.is_cuda:
         raise MihsError("A must be a 2-D device tensor")
     A = _row_aligned(A)
@@ -199,12 +221,22 @@ def mihs_sketch(A: torch.Tensor, kind: str, m: int, seed: int, precision: str = 
     p = PRECISIONS[precision]
     rows = m2 if kind == "count_gauss" else m
     sa_dtype = torch.float32 if p == 1 else torch.float64
-    ld = (d + 3) // 4 * 4
-    SA = torch.zeros((rows, ld), dtype=sa_dtype, device=A.device)[:, :d]
+    if out is None:
+        ld = (d + 3) // 4 * 4
+        SA = torch.zeros((rows, ld), dtype=sa_dtype, device=A.device)[:, :d]
+    else:
+        if out.shape != (rows, d) or out.dtype != sa_dtype or out.stride(1) != 1:
+            raise MihsError(f"out must be a {rows} x {d} {sa_dtype} tensor with unit column stride")
+        SA = out
     ws_n = _sz()
     _check(lib.mihs_sketch_workspace_size(h, n, d, m, m2, k, _dtype_code(A), p, ctypes.byref(ws_n)),
            "mihs_sketch_workspace_size")
-    ws = _workspace(ws_n.value, A.device)
+    if workspace is None:
+        ws = _workspace(ws_n.value, A.device)
+    else:
+        if workspace.numel() < ws_n.value:
+            raise MihsError("sketch workspace too small")
+        ws = workspace
     _check(lib.mihs_sketch(h, A.data_ptr(), _dtype_code(A), n, d, A.stride(0), k, m, m2,
                            seed & 0xFFFFFFFF, p, SA.data_ptr(), SA.stride(0), ws.data_ptr(),
                            ws.numel(), _stream(A.device)), "mihs_sketch")
@@ -219,7 +251,8 @@ def info_to_dict(raw: torch.Tensor) -> list:
         out.append({"outer_iters": s.outer_iters, "inner_iters_total": s.inner_iters_total,
                     "inner_iters_max": s.inner_iters_max, "rel_step": s.rel_step,
                     "grad_norm": s.grad_norm, "status": s.status,
-                    "status_name": STATUS_NAMES.get(s.status, str(s.status))})
+                    "status_name": STATUS_NAMES.get(s.status, str(s.status)),
+                    "elapsed_us": s.elapsed_us})
     return out
 
 
@@ -537,6 +570,143 @@ def mihs_solve_batched(problems, lambdas: torch.Tensor, alphas: torch.Tensor,
         return xs, infos, (keep, ws)
     torch.cuda.synchronize(dev)
     return xs, [info_to_dict(t) for t in infos]
+
+
+def sketch_workspace_bytes(n: int, d: int, m: int, kind: str, precision: str = "plain",
+                           a_dtype: torch.dtype = torch.float64, m2: int = 0,
+                           device: Optional[int] = None) -> int:
+    """Workspace bytes of one mihs_sketch call of this shape."""
+    lib = load_library()
+    h = handle(device)
+    ws_n = _sz()
+    _check(lib.mihs_sketch_workspace_size(h, n, d, m, m2, SKETCH_KINDS[kind],
+                                          F32 if a_dtype == torch.float32 else F64,
+                                          PRECISIONS[precision], ctypes.byref(ws_n)),
+           "mihs_sketch_workspace_size")
+    return ws_n.value
+
+
+class BatchedSolver:
+    """A planned batched lambda-path solve (mihs_batched_plan_create/run).
+
+    problems: list of (A, b, SA) device tensors as for mihs_solve_batched.  The
+    plan records their addresses: new values may be written into A, b or SA in
+    place between runs.  run() zeroes X (x^1 = 0) and enqueues the solve on the
+    current stream without synchronising or allocating, so it can be captured
+    (capture() returns a replayable torch.cuda.CUDAGraph).  tune() runs the
+    library's autotuner on these problems and re-plans with its choice."""
+
+    def __init__(self, problems, lambdas: torch.Tensor, alphas: torch.Tensor,
+                 betas: torch.Tensor, eps_sub: float = 1e-2, tol: float = 1e-10,
+                 max_outer: int = 300, max_inner: int = 1000, precision: Optional[str] = None,
+                 tuning: Optional[dict] = None):
+        nprob = len(problems)
+        if lambdas.dim() != 2 or lambdas.shape[0] != nprob:
+            raise MihsError("lambdas must be nprob x nlam")
+        self.nprob, self.nlam = nprob, lambdas.shape[1]
+        if precision is None:
+            precision = "mixed" if problems[0][2].dtype == torch.float32 else "plain"
+        self.precision = PRECISIONS[precision]
+        self.dev = problems[0][0].device
+        self.params = (float(eps_sub), float(tol), int(max_outer), int(max_inner))
+        self.lam = lambdas.to(torch.float64).contiguous()
+        self.alp = alphas.to(torch.float64).contiguous()
+        self.bet = betas.to(torch.float64).contiguous()
+        ds = [int(A.shape[1]) for A, _, _ in problems]
+        # every X in one buffer (one fill restarts them all), every info record in another
+        self.X_all = torch.zeros(sum(ds) * self.nlam, dtype=torch.float64, device=self.dev)
+        self.info_all = torch.zeros(INFO_BYTES * self.nlam * nprob, dtype=torch.uint8,
+                                    device=self.dev)
+        self.xs, self._keep = [], []
+        self.table = (Problem * nprob)()
+        off = 0
+        for i, (A, b, SA) in enumerate(problems):
+            A = _row_aligned(A)
+            SA = _row_aligned(SA)
+            if A.dtype != torch.float64:
+                raise MihsError("batched problems take float64 A")
+            n, d = A.shape
+            X = self.X_all[off:off + d * self.nlam].view(d, self.nlam)
+            off += d * self.nlam
+            info = self.info_all[i * INFO_BYTES * self.nlam:(i + 1) * INFO_BYTES * self.nlam]
+            self._keep += [A, b, SA]
+            self.xs.append(X)
+            self.table[i] = Problem(A.data_ptr(), b.data_ptr(), SA.data_ptr(), X.data_ptr(),
+                                    info.data_ptr(), n, d, A.stride(0), SA.shape[0],
+                                    SA.stride(0))
+        lib = load_library()
+        self.h = handle(self.dev.index)
+        ws_n = _sz()
+        _check(lib.mihs_solve_batched_workspace_size(self.h, ctypes.cast(self.table, _vp), nprob,
+                                                     self.nlam, self.precision,
+                                                     ctypes.byref(ws_n)),
+               "mihs_solve_batched_workspace_size")
+        self.ws = _workspace(ws_n.value, self.dev)
+        self.plan = None
+        self._make_plan(tuning)
+
+    def _make_plan(self, tuning: Optional[dict]):
+        lib = load_library()
+        if self.plan is not None:
+            lib.mihs_batched_plan_destroy(self.plan)
+            self.plan = None
+        tn = None
+        if tuning is not None:
+            tn = Tuning(int(tuning["cg_cols"]), int(tuning["a_dma"]), float(tuning["inner_weight"]))
+        eps_sub, tol, max_outer, max_inner = self.params
+        plan = _vp()
+        _check(lib.mihs_batched_plan_create(
+            self.h, ctypes.cast(self.table, _vp), self.nprob, self.lam.data_ptr(),
+            self.alp.data_ptr(), self.bet.data_ptr(), self.nlam, self.precision, eps_sub, tol,
+            max_outer, max_inner, ctypes.byref(tn) if tn is not None else None,
+            self.ws.data_ptr(), self.ws.numel(), _stream(self.dev), ctypes.byref(plan)),
+            "mihs_batched_plan_create")
+        self.plan = plan
+
+    def tune(self, trial_outer: int = 8) -> dict:
+        """Autotune the launch shape on these problems (blocking; overwrites X)
+        and re-plan with the choice.  Returns the choice and the trial times."""
+        lib = load_library()
+        eps_sub, tol, _, max_inner = self.params
+        best = Tuning()
+        times = (ctypes.c_float * TUNE_MAX_CANDIDATES)()
+        nc = ctypes.c_int32()
+        _check(lib.mihs_tune_batched(
+            self.h, ctypes.cast(self.table, _vp), self.nprob, self.lam.data_ptr(),
+            self.alp.data_ptr(), self.bet.data_ptr(), self.nlam, self.precision, eps_sub, tol,
+            int(trial_outer), max_inner, self.ws.data_ptr(), self.ws.numel(), _stream(self.dev),
+            ctypes.byref(best), times, ctypes.byref(nc)), "mihs_tune_batched")
+        self._make_plan(best.as_dict())
+        return {"best": best.as_dict(), "trial_ms": [round(times[i], 3) for i in range(nc.value)]}
+
+    def run(self):
+        """x^1 = 0 and the solve, enqueued on the current stream (no sync)."""
+        self.X_all.zero_()
+        _check(load_library().mihs_batched_plan_run(self.plan, _stream(self.dev)),
+               "mihs_batched_plan_run")
+
+    def capture(self) -> "torch.cuda.CUDAGraph":
+        """Capture run() in a graph (warm it up eagerly first)."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream(device=self.dev)
+        s.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self.run()
+        torch.cuda.current_stream(self.dev).wait_stream(s)
+        return g
+
+    def infos(self) -> list:
+        raw = info_to_dict(self.info_all)
+        return [raw[i * self.nlam:(i + 1) * self.nlam] for i in range(self.nprob)]
+
+    def __del__(self):
+        try:
+            if self.plan is not None and _lib is not None:
+                _lib.mihs_batched_plan_destroy(self.plan)
+                self.plan = None
+        except Exception:
+            pass
 
 
 def mihs_solve_multi(A: torch.Tensor, B: torch.Tensor, lam: float, SA: torch.Tensor,

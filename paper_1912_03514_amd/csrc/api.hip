@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <new>
 #include <vector>
 
 #include "internal.hpp"
@@ -38,17 +39,21 @@ int mihs_create(mihs_handle_t* handle, int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return MIHS_ERR_HIP;
   if (!prop.cooperativeLaunch) return MIHS_ERR_UNSUPPORTED;
-  mihs_handle* h = (mihs_handle*)calloc(1, sizeof(mihs_handle));
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess)
+    wall_khz = 0;
+  mihs_handle* h = new (std::nothrow) mihs_handle();
   if (!h) return MIHS_ERR_INVALID;
   h->device = device;
   h->num_cu = prop.multiProcessorCount;
+  h->wall_khz = wall_khz;
   strncpy(h->arch, prop.gcnArchName, sizeof(h->arch) - 1);
   *handle = h;
   return MIHS_OK;
 }
 
 int mihs_destroy(mihs_handle_t handle) {
-  free(handle);
+  delete handle;
   return MIHS_OK;
 }
 
@@ -637,13 +642,10 @@ int mihs_solve_batched_workspace_size(mihs_handle_t handle, const mihs_problem_t
   return MIHS_OK;
 }
 
-int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
-                       const mihs_problem_t* h_problems, int64_t nprob, const double* lambdas,
-                       const double* alphas, const double* betas, int64_t nlam,
-                       mihs_precision_t precision, double eps_sub, double tol,
-                       int64_t max_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
-                       void* stream) {
-  (void)d_problems;
+static int check_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, int64_t nprob,
+                         const double* lambdas, const double* alphas, const double* betas,
+                         int64_t nlam, mihs_precision_t precision, double eps_sub,
+                         int64_t max_outer, int64_t max_inner) {
   if (!handle || !h_problems || nprob < 1 || nlam < 1 || !lambdas || !alphas || !betas)
     return MIHS_ERR_INVALID;
   if (precision != MIHS_PLAIN_FP64 && precision != MIHS_MIXED) return MIHS_ERR_INVALID;
@@ -656,11 +658,178 @@ int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
     if (q.d > mihs::block_max_d()) return MIHS_ERR_UNSUPPORTED;
   }
   if (hipSetDevice(handle->device) != hipSuccess) return MIHS_ERR_HIP;
+  return MIHS_OK;
+}
+
+int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
+                       const mihs_problem_t* h_problems, int64_t nprob, const double* lambdas,
+                       const double* alphas, const double* betas, int64_t nlam,
+                       mihs_precision_t precision, double eps_sub, double tol,
+                       int64_t max_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
+                       void* stream) {
+  (void)d_problems;
+  int rc = check_batched(handle, h_problems, nprob, lambdas, alphas, betas, nlam, precision,
+                         eps_sub, max_outer, max_inner);
+  if (rc) return rc;
   std::vector<mihs::BlockEntryDesc> ents;
   batched_entries(h_problems, nprob, lambdas, alphas, betas, nlam, &ents);
   return mihs::launch_block(handle, ents.data(), (int64_t)ents.size(), 0,
                             precision == MIHS_MIXED, eps_sub, tol, max_outer, max_inner, workspace,
                             ws_bytes, as_stream(stream));
+}
+
+}  // extern "C"
+
+struct mihs_batched_plan {
+  mihs::BlockPlan* plan;
+  int device;
+};
+
+extern "C" {
+
+int mihs_batched_plan_create(mihs_handle_t handle, const mihs_problem_t* h_problems,
+                             int64_t nprob, const double* lambdas, const double* alphas,
+                             const double* betas, int64_t nlam, mihs_precision_t precision,
+                             double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+                             const mihs_batched_tuning_t* tuning, void* workspace,
+                             size_t ws_bytes, void* stream, mihs_batched_plan_t* plan) {
+  if (!plan) return MIHS_ERR_INVALID;
+  *plan = nullptr;
+  int rc = check_batched(handle, h_problems, nprob, lambdas, alphas, betas, nlam, precision,
+                         eps_sub, max_outer, max_inner);
+  if (rc) return rc;
+  if (tuning && !mihs::block_tuning_valid(*tuning)) return MIHS_ERR_INVALID;
+  std::vector<mihs::BlockEntryDesc> ents;
+  batched_entries(h_problems, nprob, lambdas, alphas, betas, nlam, &ents);
+  const int64_t count = (int64_t)ents.size();
+  const mihs_batched_tuning_t tn =
+      tuning ? *tuning : mihs::block_tuning_for(handle, ents.data(), count);
+  mihs::BlockPlan* P = nullptr;
+  rc = mihs::plan_block(handle, ents.data(), count, 0, precision == MIHS_MIXED, eps_sub, tol,
+                        max_outer, max_inner, tn, workspace, ws_bytes, as_stream(stream), &P);
+  if (rc) return rc;
+  mihs_batched_plan* out = new (std::nothrow) mihs_batched_plan();
+  if (!out) {
+    mihs::free_block_plan(P);
+    return MIHS_ERR_INVALID;
+  }
+  out->plan = P;
+  out->device = handle->device;
+  *plan = out;
+  return MIHS_OK;
+}
+
+int mihs_batched_plan_run(mihs_batched_plan_t plan, void* stream) {
+  if (!plan || !plan->plan) return MIHS_ERR_INVALID;
+  if (hipSetDevice(plan->device) != hipSuccess) return MIHS_ERR_HIP;
+  return mihs::run_block(plan->plan, as_stream(stream));
+}
+
+int mihs_batched_plan_destroy(mihs_batched_plan_t plan) {
+  if (!plan) return MIHS_OK;
+  mihs::free_block_plan(plan->plan);
+  delete plan;
+  return MIHS_OK;
+}
+
+int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, int64_t nprob,
+                      const double* lambdas, const double* alphas, const double* betas,
+                      int64_t nlam, mihs_precision_t precision, double eps_sub, double tol,
+                      int64_t trial_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
+                      void* stream, mihs_batched_tuning_t* best, float* cand_ms,
+                      int32_t* ncand) {
+  if (!best || trial_outer < 1) return MIHS_ERR_INVALID;
+  int rc = check_batched(handle, h_problems, nprob, lambdas, alphas, betas, nlam, precision,
+                         eps_sub, trial_outer, max_inner);
+  if (rc) return rc;
+  std::vector<mihs::BlockEntryDesc> ents;
+  batched_entries(h_problems, nprob, lambdas, alphas, betas, nlam, &ents);
+  const int64_t count = (int64_t)ents.size();
+  hipStream_t st = as_stream(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return MIHS_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return MIHS_ERR_HIP;
+  }
+  int n_tried = 0;
+  // one timed trial from X = 0
+  auto trial = [&](const mihs_batched_tuning_t& tn, float* ms) -> int {
+    for (int64_t p = 0; p < nprob; ++p) {
+      const int r = mihs::launch_fill(h_problems[p].X, 0.0, h_problems[p].d * nlam, st);
+      if (r) return r;
+    }
+    mihs::BlockPlan* P = nullptr;
+    int r = mihs::plan_block(handle, ents.data(), count, 0, precision == MIHS_MIXED, eps_sub,
+                             tol, trial_outer, max_inner, tn, workspace, ws_bytes, st, &P);
+    if (r) return r;
+    if (hipEventRecord(e0, st) != hipSuccess) r = MIHS_ERR_HIP;
+    if (!r) r = mihs::run_block(P, st);
+    if (!r && hipEventRecord(e1, st) != hipSuccess) r = MIHS_ERR_HIP;
+    if (!r && hipEventSynchronize(e1) != hipSuccess) r = MIHS_ERR_HIP;
+    if (!r && hipEventElapsedTime(ms, e0, e1) != hipSuccess) r = MIHS_ERR_HIP;
+    mihs::free_block_plan(P);
+    if (!r && n_tried < MIHS_TUNE_MAX_CANDIDATES) {
+      if (cand_ms) cand_ms[n_tried] = *ms;
+      ++n_tried;
+    }
+    return r;
+  };
+  mihs_batched_tuning_t cur;
+  mihs_batched_default_tuning(&cur);
+  float cur_ms = 0.0f;
+  rc = trial(cur, &cur_ms);
+  // coordinate descent: inner_weight, then cg_cols, then a_dma
+  const double weights[] = {25.0, 400.0};
+  for (double w : weights) {
+    if (rc) break;
+    mihs_batched_tuning_t t = cur;
+    t.inner_weight = w;
+    float ms = 0.0f;
+    rc = trial(t, &ms);
+    if (!rc && ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+  }
+  mihs_batched_tuning_t base = cur;
+  const int cols[] = {16, 64};
+  for (int c : cols) {
+    if (rc) break;
+    mihs_batched_tuning_t t = base;
+    t.cg_cols = c;
+    float ms = 0.0f;
+    rc = trial(t, &ms);
+    if (!rc && ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+  }
+  if (!rc) {
+    mihs_batched_tuning_t t = cur;
+    t.a_dma = 0;
+    float ms = 0.0f;
+    rc = trial(t, &ms);
+    if (!rc && ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ncand) *ncand = n_tried;
+  if (rc) return rc;
+  *best = cur;
+  const uint64_t key = mihs::block_signature(ents.data(), count);
+  std::lock_guard<std::mutex> lock(handle->tune_mu);
+  bool found = false;
+  for (auto& kv : handle->tuned)
+    if (kv.first == key) {
+      kv.second = cur;
+      found = true;
+    }
+  if (!found) handle->tuned.emplace_back(key, cur);
+  return MIHS_OK;
 }
 
 }  // extern "C"

@@ -70,6 +70,8 @@ struct BatchArgs {
   int items_stride;
   int* err;
   int a_f32, h_f32;
+  int a_dma;     // 1: direct-to-LDS row groups where rows are 1-4 KiB
+  int wall_khz;  // rate of wall_clock64()
   double eps_sub, tol;
   int64_t max_outer, max_inner;
   BarrierSpin spin, spin_idle;
@@ -464,7 +466,7 @@ __device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t
 // (the X operand, the Gram-block accumulators and the tile in flight) do not
 // compete with the solver state around it:
 //   part_out = A_rows^T (C - A_rows X) over this member's tiles (d x 16, FP64).
-template <typename TM, int DP>
+template <typename TM, int DP, bool DMA>
 __device__ __attribute__((noinline)) void a_pass(const TM* __restrict__ M, int64_t ld,
                                                  int64_t rows, int d, int rank, int T,
                                                  const double* __restrict__ B, int64_t ldb,
@@ -495,7 +497,7 @@ __device__ __attribute__((noinline)) void a_pass(const TM* __restrict__ M, int64
   f64x4 Gacc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) Gacc[b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  if (DmaCfg<TM, DP>::ok)
+  if (DmaCfg<TM, DP>::ok && DMA)
     block_pass_dma<TM, DP>(M, ld, rows, d, rank, T, B, ldb, ldbc, ncols, Vreg, Gacc,
                            (lds_char*)lds_raw, ured, ufin);
   else
@@ -666,6 +668,173 @@ __device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, 
   return k;
 }
 
+
+// The lockstep CG of an entry whose inner solve runs on one workgroup
+// (sub-team of one): every vector stays in the workgroup.  Thread (wave w,
+// lane l) owns rows 16 (4 b + w) + l / 16 + 4 i (i < 4, b < DP / 64) of
+// column j = l % 16 -- the rows of the matrix-core result block it holds -- so
+// r lives in registers, p (the MFMA operand) and z in LDS, q goes to the
+// entry's Q buffer (written and read back by the same thread), and the
+// per-column sums go through two LDS buffers in a fixed order.  Each wave forms
+// whole rows of H p for its own 16-row blocks (no reduction across waves, no
+// barrier inside the product) and skips the blocks and k-chunks at or beyond
+// d, where H is zero.  Same iteration as cg_solve (step lengths, masks,
+// breakdown and stop rule per column); z ends in the LDS region after p.
+template <typename TH, int DP>
+__device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict__ H, int64_t ldh,
+                                                            int d, const double* __restrict__ R,
+                                                            double* __restrict__ Q, double eps_sub,
+                                                            int64_t max_inner) {
+  extern __shared__ uint4 lds_raw[];
+  double* stage = (double*)lds_raw;      // p, DP x 16
+  double* zl = stage + DP * KR;          // z, DP x 16
+  double* red0 = (double*)((char*)lds_raw + kUredOffset);
+  double* red1 = red0 + kBlock;
+  Shared& sh = g_sh;
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  constexpr int NBW = DP / 64;                    // 16-row blocks per wave
+  constexpr int NV = 4 * NBW;                     // owned entries per vector
+  constexpr int VE = 16 / (int)sizeof(TH);        // elements per 16-byte load
+  constexpr int KQ = DP / 4;
+  constexpr int NLD = (KQ * (int)sizeof(TH) / 16) < 8 ? KQ * (int)sizeof(TH) / 16 : 8;
+  constexpr int CE = NLD * VE;                    // k elements per lane and chunk
+  constexpr int NRING = 4;                        // chunks in flight per lane
+  const int lane = lane_id(), wave = wave_id();
+  const int j = lane & 15, g = lane >> 4;
+  const int tid = (int)threadIdx.x;
+  // active blocks of this wave and k-chunks (a chunk covers k in [c 4 CE, (c+1) 4 CE))
+  const int nbw = d > 16 * wave ? min(NBW, (d - 16 * wave + 63) / 64) : 0;
+  const int nch = min(KQ / CE, (d + 4 * CE - 1) / (4 * CE));
+  // element i of a 16 x 16 x 4 FP64 MFMA result is row l / 16 + 4 i, column l % 16
+  auto row_of = [&](int v) { return 16 * (4 * (v >> 2) + wave) + g + 4 * (v & 3); };
+
+  double r[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int row = row_of(v);
+    r[v] = row < d ? R[(int64_t)row * KR + j] : 0.0;
+    zl[row * KR + j] = 0.0;
+  }
+  const double lj = sh.lam[j];
+  bool act = sh.active[j] != 0;
+  double rr = sh.rr[j], bc = 0.0;
+  const double rr0 = sh.rr0[j];
+  int64_t k = 0, kin = 0;
+  __syncthreads();
+
+  // H rows for the A operand: lane (row l % 16, k-group g) reads 16-byte
+  // chunks of row cb + j at k = c 4 CE + g CE ... (contiguous per lane)
+  auto hptr = [&](int b, int c) -> const u32x4* {
+    return (const u32x4*)(H + (int64_t)(16 * (4 * b + wave) + j) * ldh + c * 4 * CE + g * CE);
+  };
+  while (true) {
+    int any = 0;
+    for (int jj = 0; jj < KR; ++jj) any |= sh.active[jj];
+    if (!any || k >= max_inner) break;
+    // p = r (first step) or r + beta_cg p; inactive columns carry p = 0
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int o = row_of(v) * KR + j;
+      stage[o] = act ? ((k == 0) ? r[v] : r[v] + bc * stage[o]) : 0.0;
+    }
+    __syncthreads();
+    // q = H p + lambda p on the owned rows; chunks stream through a two-deep
+    // register pipeline across block boundaries
+    double pq = 0.0;
+    {
+      // the chunks of the owned blocks in order (t = b nch + c) through a ring of
+      // NRING register buffers: NRING chunks in flight per lane; H is re-read
+      // every step, so it is loaded through the caches
+      union Chunk {
+        u32x4 u[NLD];
+        TH v[CE];
+      };
+      Chunk ring[NRING];
+      const int T = nbw * nch;
+      auto fetch = [&](Chunk& buf, int t) {
+        if (t < T) {
+          const int b = t / nch;
+          const u32x4* src = hptr(b, t - b * nch);
+#pragma unroll
+          for (int i = 0; i < NLD; ++i) buf.u[i] = src[i];
+        }
+      };
+#pragma unroll
+      for (int u = 0; u < NRING; ++u) fetch(ring[u], u);
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      int b = 0, c = 0;
+      for (int t0 = 0; t0 < T; t0 += NRING) {
+#pragma unroll
+        for (int u = 0; u < NRING; ++u) {
+          if (t0 + u < T) {
+            const double* pk = stage + (c * 4 * CE + g * CE) * KR + j;
+#pragma unroll
+            for (int e = 0; e < CE; ++e)
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ring[u].v[e], pk[e * KR], acc,
+                                                         0, 0, 0);
+            fetch(ring[u], t0 + u + NRING);
+            if (++c == nch) {
+              const int row0 = 16 * (4 * b + wave) + g;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int o = (row0 + 4 * i) * KR + j;
+                const double pv = stage[o];
+                const double qv = acc[i] + lj * pv;
+                Q[o] = qv;
+                pq += pv * qv;
+              }
+              acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+              c = 0;
+              ++b;
+            }
+          }
+        }
+      }
+    }
+    red0[tid] = pq;
+    __syncthreads();
+    double spq = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) spq += red0[t * 16 + j];
+    double al = 0.0;
+    if (act) {
+      al = rr / spq;
+      if (!(spq > 0.0) || !isfinite(al)) {
+        al = 0.0;
+        act = false;  // breakdown in this column: keep the current step
+      }
+    }
+    double rrp = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int o = row_of(v) * KR + j;
+      // rows of blocks this wave skipped (at or beyond d) keep r = 0
+      if (act && (v >> 2) < nbw) {
+        zl[o] += al * stage[o];
+        r[v] -= al * Q[o];
+      }
+      rrp += r[v] * r[v];
+    }
+    red1[tid] = rrp;
+    __syncthreads();
+    double rn = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) rn += red1[t * 16 + j];
+    ++k;
+    if (act) {
+      bc = rn / rr;
+      rr = rn;
+      kin = k;
+      if (rn <= eps_sub * eps_sub * rr0) act = false;
+    }
+    if (tid < KR) sh.active[tid] = act ? 1 : 0;
+    __syncthreads();
+  }
+  if (tid < KR) sh.kin[tid] = kin;
+  __syncthreads();
+  return k;
+}
+
 template <int DP>
 __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, void* tile,
                           Shared& sh) {
@@ -687,6 +856,9 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
   double* myscal = scal + (int64_t)rank * kNScal;
   double* stage = (double*)tile;  // d x 16 vectors (row-major = MFMA B-operand order)
   const bool cg = rank < Tc;
+  // a one-workgroup CG keeps its vectors in the workgroup (p and z in LDS:
+  // 2 x DP x 16 doubles within the tile region)
+  const bool local_cg = Tc == 1 && 2 * (size_t)DP * KR * sizeof(double) <= kUredOffset;
   // CG members own 16-aligned column ranges of R, Z, Q, XP and X
   const int cpw = ((d + Tc - 1) / Tc + 15) / 16 * 16;
   const int c_lo = cg ? min(d, rank * cpw) : d;
@@ -695,6 +867,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
   unsigned ep_all = 0, ep_cg = 0;
   int* s_flag = &sh.flag;
   bool alive = true;
+  const long long t_start = wall_clock64();
 
   if (threadIdx.x < KR) {
     const int j = threadIdx.x;
@@ -722,12 +895,24 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
   int64_t outer = 0;
   for (; outer < a.max_outer; ++outer) {
     // ---- A pass: G partial = A^T (C - A X) over this member's tiles
-    if (a.a_f32)
-      a_pass<float, DP>((const float*)e.A, e.lda, e.n, d, rank, T, e.B, e.ldb, e.ldbc, e.ncols,
-                        e.X, e.ldx, part + (int64_t)rank * DP * KR);
-    else
-      a_pass<double, DP>((const double*)e.A, e.lda, e.n, d, rank, T, e.B, e.ldb, e.ldbc,
-                         e.ncols, e.X, e.ldx, part + (int64_t)rank * DP * KR);
+    // (the direct-to-LDS and register-staged passes are separate functions,
+    // each with its own register allocation)
+    double* my_part = part + (int64_t)rank * DP * KR;
+    if (a.a_f32) {
+      if (a.a_dma)
+        a_pass<float, DP, true>((const float*)e.A, e.lda, e.n, d, rank, T, e.B, e.ldb, e.ldbc,
+                                e.ncols, e.X, e.ldx, my_part);
+      else
+        a_pass<float, DP, false>((const float*)e.A, e.lda, e.n, d, rank, T, e.B, e.ldb, e.ldbc,
+                                 e.ncols, e.X, e.ldx, my_part);
+    } else {
+      if (a.a_dma)
+        a_pass<double, DP, true>((const double*)e.A, e.lda, e.n, d, rank, T, e.B, e.ldb,
+                                 e.ldbc, e.ncols, e.X, e.ldx, my_part);
+      else
+        a_pass<double, DP, false>((const double*)e.A, e.lda, e.n, d, rank, T, e.B, e.ldb,
+                                  e.ldbc, e.ncols, e.X, e.ldx, my_part);
+    }
     if (!(alive = group_sync(e.bar, T, ep_all, a.err, s_flag, a.spin))) break;
 
     // ---- every member reduces the partials of a slice of columns:
@@ -767,14 +952,21 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       }
       __syncthreads();
 
-      // ---- lockstep CG on (H + lambda_j I)
-      const int64_t k =
-          a.h_f32 ? cg_solve<float, DP>((const float*)e.H, e.ldh, d, c_lo, c_hi, R, Z, Q, scal,
-                                        myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin, a.eps_sub,
-                                        a.max_inner)
-                  : cg_solve<double, DP>((const double*)e.H, e.ldh, d, c_lo, c_hi, R, Z, Q, scal,
-                                         myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin, a.eps_sub,
-                                         a.max_inner);
+      // ---- lockstep CG on (H + lambda_j I): in the workgroup when the CG
+      // sub-team is one workgroup (z then sits in LDS after p), else on the team
+      int64_t k;
+      if (local_cg)
+        k = a.h_f32 ? cg_solve_local<float, DP>((const float*)e.H, e.ldh, d, R, Q, a.eps_sub,
+                                                a.max_inner)
+                    : cg_solve_local<double, DP>((const double*)e.H, e.ldh, d, R, Q, a.eps_sub,
+                                                 a.max_inner);
+      else
+        k = a.h_f32 ? cg_solve<float, DP>((const float*)e.H, e.ldh, d, c_lo, c_hi, R, Z, Q, scal,
+                                          myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin, a.eps_sub,
+                                          a.max_inner)
+                    : cg_solve<double, DP>((const double*)e.H, e.ldh, d, c_lo, c_hi, R, Z, Q,
+                                           scal, myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin,
+                                           a.eps_sub, a.max_inner);
       alive = k >= 0;
       if (alive && Tc > 1) ep_cg += 2u * (unsigned)k;
       if (!alive) break;
@@ -787,6 +979,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       }
 
       // ---- heavy-ball update per column (owners) and relative-step partials
+      const double* Zsrc = local_cg ? (const double*)tile + DP * KR : Z;
       double s0 = 0.0, s1 = 0.0;
       for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
         const int c = c_lo + idx / KR, j = idx % KR;
@@ -794,7 +987,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
         const int64_t o = (int64_t)c * KR + j;
         double* xp = e.X + (int64_t)c * e.ldx + j;
         const double xc = *xp;
-        const double xn = xc + sh.alpha[j] * Z[o] + sh.beta[j] * (xc - XP[o]);
+        const double xn = xc + sh.alpha[j] * Zsrc[o] + sh.beta[j] * (xc - XP[o]);
         XP[o] = xc;
         *xp = xn;
         s0 += (xn - xc) * (xn - xc);
@@ -834,7 +1027,9 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
     inf->grad_norm = sh.gnorm[j];
     inf->status = !alive ? MIHS_BARRIER_TIMEOUT
                          : ((sh.thr[j] > 0.0 && sh.done[j]) ? MIHS_CONVERGED : MIHS_MAX_ITER);
-    inf->reserved = 0;
+    const long long ticks = wall_clock64() - t_start;
+    const long long us = a.wall_khz > 0 ? ticks * 1000 / a.wall_khz : 0;
+    inf->elapsed_us = (int32_t)(us < 0x7fffffffLL ? us : 0x7fffffffLL);
   }
   __syncthreads();
 }
@@ -883,7 +1078,17 @@ int dp_for(int64_t d) {
 
 int block_max_d() { return 1024; }
 
+bool block_tuning_valid(const mihs_batched_tuning_t& t) {
+  return (t.cg_cols == 16 || t.cg_cols == 32 || t.cg_cols == 64) &&
+         (t.a_dma == 0 || t.a_dma == 1) && t.inner_weight >= 1.0 && t.inner_weight <= 1e4;
+}
+
 namespace {
+
+// Candidate shapes (every one must fit the workspace that block_workspace_bytes
+// reports): the coordinate-descent axes of the tuner.
+const double kInnerWeights[] = {25.0, 100.0, 400.0};
+const int kCgCols[] = {16, 32, 64};
 
 // Deterministic schedule of the entries over G workgroups (also used to size
 // the workspace): dedicated teams for heavy entries, single-workgroup bins for
@@ -894,14 +1099,15 @@ struct Schedule {
   size_t stride = 1;
 };
 
-int make_schedule(const BlockEntryDesc* ents, int64_t count, int G, Schedule* S) {
-  // weight: one A pass plus a typical inner solve on H per outer iteration
-  // (lockstep CGs over 16 lambdas down to 1e-6 sigma_1^2 take ~100 steps)
+int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
+                  const mihs_batched_tuning_t& tn, Schedule* S) {
+  // weight: one A pass plus the expected inner solve on H per outer iteration
+  // (inner_weight passes over H; lockstep CGs over 16 lambdas down to
+  // 1e-6 sigma_1^2 take ~100 steps)
   std::vector<double> wgt(count);
   double total = 0.0;
   for (int64_t i = 0; i < count; ++i) {
-    const double inner_est = 100.0;
-    wgt[i] = (double)ents[i].n * ents[i].d + inner_est * (double)ents[i].d * ents[i].d;
+    wgt[i] = (double)ents[i].n * ents[i].d + tn.inner_weight * (double)ents[i].d * ents[i].d;
     total += wgt[i];
   }
   std::vector<int64_t> order(count);
@@ -946,9 +1152,10 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G, Schedule* S)
     S->items[best].push_back((int)i);
     load[best] += wgt[i];
   }
-  // CG sub-team: about 32 columns of H per member, at most the whole team
+  // CG sub-team: about cg_cols columns of H per member, at most the whole team
   for (int64_t i = 0; i < count; ++i)
-    S->tcg[i] = std::max(1, std::min(S->tsize[i], (int)((ents[i].d + 31) / 32)));
+    S->tcg[i] = std::max(
+        1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
   S->stride = 1;
   for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
   return MIHS_OK;
@@ -1008,19 +1215,82 @@ BlockLayout block_layout(const BlockEntryDesc* ents, int64_t count, const Schedu
   return L;
 }
 
+__global__ void clear_words(unsigned* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+uint64_t mix64(uint64_t h, uint64_t v) {
+  // FNV-1a over the 8 bytes of v
+  for (int b = 0; b < 8; ++b) {
+    h ^= (v >> (8 * b)) & 0xFFu;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
 }  // namespace
+
+struct BlockPlan {
+  BatchKernel kern;
+  size_t shmem;
+  int G;
+  BatchArgs args;
+  const GramJob* d_jobs;
+  int64_t njobs;
+  int sa_f32;
+  unsigned* bar;       // barrier words and the error flag
+  int64_t bar_words;
+};
 
 size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count) {
   if (count <= 0) return 0;
-  Schedule S;
-  if (make_schedule(ents, count, h->num_cu, &S) != MIHS_OK) return 0;
-  return block_layout(ents, count, S, h->num_cu).total;
+  size_t most = 0;
+  mihs_batched_tuning_t tn;
+  mihs_batched_default_tuning(&tn);
+  for (double w : kInnerWeights)
+    for (int cc : kCgCols) {
+      tn.inner_weight = w;
+      tn.cg_cols = cc;
+      Schedule S;
+      if (make_schedule(ents, count, h->num_cu, tn, &S) != MIHS_OK) return 0;
+      most = std::max(most, block_layout(ents, count, S, h->num_cu).total);
+    }
+  return most;
 }
 
-int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
-                 int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
-                 void* ws, size_t ws_bytes, hipStream_t st) {
-  if (count <= 0) return MIHS_OK;
+uint64_t block_signature(const BlockEntryDesc* ents, int64_t count) {
+  uint64_t s = 1469598103934665603ull;
+  s = mix64(s, (uint64_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    s = mix64(s, (uint64_t)ents[i].n);
+    s = mix64(s, (uint64_t)ents[i].d);
+    s = mix64(s, (uint64_t)ents[i].m);
+    s = mix64(s, (uint64_t)ents[i].ncols);
+    s = mix64(s, (uint64_t)ents[i].sa_group);
+  }
+  return s;
+}
+
+mihs_batched_tuning_t block_tuning_for(mihs_handle* h, const BlockEntryDesc* ents,
+                                       int64_t count) {
+  mihs_batched_tuning_t tn;
+  mihs_batched_default_tuning(&tn);
+  const uint64_t key = block_signature(ents, count);
+  std::lock_guard<std::mutex> lock(h->tune_mu);
+  for (const auto& kv : h->tuned)
+    if (kv.first == key) return kv.second;
+  return tn;
+}
+
+int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
+               int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+               const mihs_batched_tuning_t& tuning, void* ws, size_t ws_bytes, hipStream_t st,
+               BlockPlan** out) {
+  *out = nullptr;
+  if (count <= 0) return MIHS_ERR_INVALID;
+  if (!block_tuning_valid(tuning)) return MIHS_ERR_INVALID;
   int dpmax = 64;
   for (int64_t i = 0; i < count; ++i) {
     if (ents[i].d < 1 || ents[i].d > block_max_d() || ents[i].ncols < 1 || ents[i].ncols > KR)
@@ -1040,7 +1310,7 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
   const int G = h->num_cu;  // one workgroup per compute unit
 
   Schedule S;
-  int rc = make_schedule(ents, count, G, &S);
+  int rc = make_schedule(ents, count, G, tuning, &S);
   if (rc) return rc;
   const BlockLayout L = block_layout(ents, count, S, G);
   if (!ws || L.total > ws_bytes) return MIHS_ERR_WORKSPACE;
@@ -1115,23 +1385,27 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
   if (hipMemcpyAsync(base + L.gram_off, jobs.data(), jobs.size() * sizeof(GramJob),
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return MIHS_ERR_HIP;
-  if (hipMemsetAsync(base + L.bar_off, 0, (size_t)(2 * count + 2) * 128, st) != hipSuccess)
-    return MIHS_ERR_HIP;
   // the host tables above are freed when this function returns
   if (hipStreamSynchronize(st) != hipSuccess) return MIHS_ERR_HIP;
 
-  if (!jobs.empty()) {
-    rc = launch_gram_jobs((const GramJob*)(base + L.gram_off), (int64_t)jobs.size(), sa_f32, st);
-    if (rc) return rc;
-  }
-
-  BatchArgs a;
+  BlockPlan* P = new BlockPlan();
+  P->kern = kern;
+  P->shmem = shmem;
+  P->G = G;
+  P->d_jobs = (const GramJob*)(base + L.gram_off);
+  P->njobs = (int64_t)jobs.size();
+  P->sa_f32 = sa_f32;
+  P->bar = (unsigned*)(base + L.bar_off);
+  P->bar_words = (int64_t)(2 * count + 2) * 32;
+  BatchArgs& a = P->args;
   a.entries = (const BatchEntry*)(base + L.ent_off);
   a.wg_items = (const int*)(base + L.item_off);
   a.items_stride = (int)S.stride;
   a.err = (int*)(base + L.bar_off);
   a.a_f32 = a_f32;
   a.h_f32 = sa_f32;
+  a.a_dma = tuning.a_dma;
+  a.wall_khz = h->wall_khz;
   a.eps_sub = eps_sub;
   a.tol = tol;
   a.max_outer = max_outer;
@@ -1140,11 +1414,59 @@ int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count
   a.spin.sleep = 1;
   a.spin_idle.limit = 1L << 24;
   a.spin_idle.sleep = 16;
+  *out = P;
+  return MIHS_OK;
+}
+
+int run_block(const BlockPlan* P, hipStream_t st) {
+  // barrier words and the error flag start at zero (a fill kernel, not a
+  // memset, so that the sequence can be captured)
+  hipLaunchKernelGGL(clear_words, dim3(1), dim3(256), 0, st, P->bar, P->bar_words);
+  if (hipGetLastError() != hipSuccess) return MIHS_ERR_HIP;
+  if (P->njobs > 0) {
+    const int rc = launch_gram_jobs(P->d_jobs, P->njobs, P->sa_f32, st);
+    if (rc) return rc;
+  }
+  BatchArgs a = P->args;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return MIHS_ERR_HIP;
+  if (cap == hipStreamCaptureStatusActive) {
+    // one workgroup per compute unit fits (checked by the plan); the graph
+    // node is an ordinary launch
+    void* args[] = {&a};
+    if (hipLaunchKernel((const void*)P->kern, dim3(P->G), dim3(kBlock), args, P->shmem, st) !=
+        hipSuccess)
+      return MIHS_ERR_HIP;
+    return MIHS_OK;
+  }
   void* args[] = {&a};
-  if (hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(kBlock), args, shmem, st) !=
-      hipSuccess)
+  if (hipLaunchCooperativeKernel((const void*)P->kern, dim3(P->G), dim3(kBlock), args, P->shmem,
+                                 st) != hipSuccess)
     return MIHS_ERR_HIP;
   return MIHS_OK;
 }
 
+void free_block_plan(BlockPlan* P) { delete P; }
+
+int launch_block(mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
+                 int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+                 void* ws, size_t ws_bytes, hipStream_t st) {
+  if (count <= 0) return MIHS_OK;
+  const mihs_batched_tuning_t tn = block_tuning_for(h, ents, count);
+  BlockPlan* P = nullptr;
+  int rc = plan_block(h, ents, count, a_f32, sa_f32, eps_sub, tol, max_outer, max_inner, tn, ws,
+                      ws_bytes, st, &P);
+  if (rc) return rc;
+  rc = run_block(P, st);
+  free_block_plan(P);
+  return rc;
+}
+
 }  // namespace mihs
+
+extern "C" void mihs_batched_default_tuning(mihs_batched_tuning_t* t) {
+  if (!t) return;
+  t->cg_cols = 32;
+  t->a_dma = 1;
+  t->inner_weight = 100.0;
+}

@@ -7,10 +7,18 @@
 
 #include "../../include/mihs.h"
 
+#include <mutex>
+#include <utility>
+#include <vector>
+
 struct mihs_handle {
   int device;
   int num_cu;
+  int wall_khz;  // rate of the device's constant wall clock
   char arch[64];
+  // batched launch shapes chosen by mihs_tune_batched, keyed by problem set
+  std::mutex tune_mu;
+  std::vector<std::pair<uint64_t, mihs_batched_tuning_t>> tuned;
 };
 
 namespace mihs {
@@ -119,8 +127,22 @@ struct BlockEntryDesc {
   int64_t sa_group;   // entries with equal sa_group share SA (and its Gram matrix)
 };
 int block_max_d();
+// Largest workspace over every tuning candidate (any shape fits).
 size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count);
-int launch_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
+// Key of a problem set for the tuning cache: (n, d, m, ncols, sketch group) of each entry.
+uint64_t block_signature(const BlockEntryDesc* ents, int64_t count);
+bool block_tuning_valid(const mihs_batched_tuning_t& t);
+// The tuned shape for this set if the handle has one, else the defaults.
+mihs_batched_tuning_t block_tuning_for(mihs_handle* h, const BlockEntryDesc* ents, int64_t count);
+struct BlockPlan;  // opaque: kernel, launch shape, argument block, device tables
+int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
+               int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
+               const mihs_batched_tuning_t& tuning, void* ws, size_t ws_bytes,
+               hipStream_t stream, BlockPlan** plan);
+int run_block(const BlockPlan* plan, hipStream_t stream);
+void free_block_plan(BlockPlan* plan);
+// plan + run + free with the handle's tuning (one call, as before).
+int launch_block(mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
                  int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
                  void* ws, size_t ws_bytes, hipStream_t stream);
 

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void pd_init_kernel(const double* x, double
     info->rel_step = 0.0;
     info->grad_norm = 0.0;
     info->status = MIHS_MAX_ITER;
-    info->reserved = 0;
+    info->elapsed_us = 0;
   }
 }
 

@@ -877,7 +877,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
     a.info->rel_step = last_step;
     a.info->grad_norm = last_gnorm;
     a.info->status = status;
-    a.info->reserved = 0;
+    a.info->elapsed_us = 0;
   }
 }
 

@@ -1,0 +1,137 @@
+"""GPU: the batched solve as a plan + launch (graph capture, repeated runs) and the
+launch-shape autotuner, against the oracle's closed form."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sketches, solver as O
+from gpu_common import announce, rel, requires_gpu, to_dev, torch
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+# ragged d across every padded width (64 ... 512) and a ragged last row tile
+SHAPES = [(1500, 70), (3001, 130), (2500, 17), (4000, 300), (5000, 200), (2100, 500)]
+NLAM = 16
+
+
+def _mihs():
+    import paper_1912_03514_amd as mihs
+    return mihs
+
+
+@pytest.fixture(scope="module")
+def problem_set():
+    problems, refs, L, Al, Be = [], [], [], [], []
+    for i, (n, d) in enumerate(SHAPES):
+        sig = W.sigma_profile("exp", d, 6.0)
+        P = W.make_problem(n, d, sig, d / 4, 700 + i)
+        m = min(n, 4 * d)
+        SA = sketches.gaussian_sketch(P.A, m, 60 + i)
+        s1 = float(sig[0]) ** 2
+        lams = s1 * 10.0 ** (-6.0 + 5.0 * np.arange(NLAM) / (NLAM - 1))
+        sds = np.array([W.nominal_sd(sig, float(l)) for l in lams])
+        betas = np.minimum(sds / m, 0.95)
+        problems.append((P.A, P.b, SA))
+        refs.append([O.ridge_lstsq(P.A, P.b, float(l)) for l in lams])
+        L.append(lams)
+        Al.append((1.0 - betas) ** 2)
+        Be.append(betas)
+    return problems, refs, np.array(L), np.array(Al), np.array(Be)
+
+
+def _device_set(problem_set):
+    problems, refs, L, Al, Be = problem_set
+    dp = [(to_dev(A), to_dev(b), to_dev(SA)) for A, b, SA in problems]
+    return dp, refs, to_dev(L), to_dev(Al), to_dev(Be)
+
+
+def _check_closed_form(xs, infos, refs, tol=1e-10):
+    for i, X in enumerate(xs):
+        Xh = X.cpu().numpy()
+        for j in range(NLAM):
+            assert infos[i][j]["status"] == 0, (i, j, infos[i][j])
+            assert rel(Xh[:, j], refs[i][j]) <= tol, (i, j, rel(Xh[:, j], refs[i][j]))
+
+
+@pytest.mark.parametrize("tuning", [
+    {"cg_cols": 32, "a_dma": 1, "inner_weight": 100.0},
+    {"cg_cols": 16, "a_dma": 0, "inner_weight": 25.0},
+    {"cg_cols": 64, "a_dma": 1, "inner_weight": 400.0},
+    {"cg_cols": 32, "a_dma": 0, "inner_weight": 400.0},
+])
+def test_every_launch_shape_reaches_the_closed_form(problem_set, tuning):
+    """Each candidate shape of the autotuner (CG sub-team width, the A pass
+    through registers or direct-to-LDS, team sizing) solves every (problem,
+    lambda) to 1e-10."""
+    mihs = _mihs()
+    dp, refs, L, Al, Be = _device_set(problem_set)
+    announce(f"batched plan shape {tuning}")
+    s = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
+                           max_inner=2000, tuning=tuning)
+    s.run()
+    torch.cuda.synchronize()
+    infos = s.infos()
+    _check_closed_form(s.xs, infos, refs)
+    assert all(r["elapsed_us"] > 0 for inf in infos for r in inf)
+
+
+def test_graph_replays_match_the_eager_run(problem_set):
+    """The launch captured in a HIP graph, replayed three times with other
+    eager work (and garbage in X) between the replays, gives bit-identical
+    results to the eager launch of the same plan."""
+    mihs = _mihs()
+    dp, refs, L, Al, Be = _device_set(problem_set)
+    s = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
+                           max_inner=2000,
+                           tuning={"cg_cols": 32, "a_dma": 1, "inner_weight": 100.0})
+    announce("batched plan eager run")
+    s.run()
+    torch.cuda.synchronize()
+    X_eager = s.X_all.clone()
+    it_eager = [[r["outer_iters"] for r in inf] for inf in s.infos()]
+    _check_closed_form(s.xs, s.infos(), refs)
+    announce("batched plan graph capture")
+    g = s.capture()
+    for rep in range(3):
+        s.X_all.fill_(float("nan"))
+        s.info_all.fill_(0)
+        junk = torch.randn(1 << 20, device=s.dev, dtype=torch.float64).sum()
+        torch.cuda.synchronize()
+        announce(f"batched plan graph replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(s.X_all, X_eager), rep
+        assert [[r["outer_iters"] for r in inf] for inf in s.infos()] == it_eager, rep
+        assert bool(torch.isfinite(junk))
+
+
+def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
+    """mihs_tune_batched times six candidate shapes by coordinate descent and
+    keeps the best for this problem set: the plain batched call afterwards (which
+    looks the shape up) still reaches the closed form."""
+    mihs = _mihs()
+    dp, refs, L, Al, Be = _device_set(problem_set)
+    s = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
+                           max_inner=2000)
+    announce("batched autotuner")
+    res = s.tune(trial_outer=3)
+    best = res["best"]
+    assert len(res["trial_ms"]) == 6
+    assert all(t > 0 for t in res["trial_ms"])
+    assert best["cg_cols"] in (16, 32, 64) and best["a_dma"] in (0, 1)
+    assert best["inner_weight"] in (25.0, 100.0, 400.0)
+    s.run()
+    torch.cuda.synchronize()
+    _check_closed_form(s.xs, s.infos(), refs)
+    announce("batched call after tuning")
+    xs, infos = mihs.mihs_solve_batched(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
+                                        max_inner=2000)
+    _check_closed_form(xs, infos, refs)
+
+
+def test_plan_rejects_bad_tuning(problem_set):
+    mihs = _mihs()
+    dp, refs, L, Al, Be = _device_set(problem_set)
+    with pytest.raises(mihs.MihsError):
+        mihs.BatchedSolver(dp, L, Al, Be, tuning={"cg_cols": 48, "a_dma": 1,
+                                                  "inner_weight": 100.0})

@@ -151,6 +151,13 @@ __device__ __forceinline__ void column_partials(double v, double* out, double* r
   __syncthreads();
 }
 
+// Columns of the A pass per wave: the four waves split [0, d) into 16-aligned
+// slices (at most DP / 4 each), so a padded width costs nothing past d.
+__device__ __forceinline__ int wave_cols(int d, int dp) {
+  const int w = ((d + 3) / 4 + 15) / 16 * 16;
+  return w < dp / 4 ? w : dp / 4;
+}
+
 // Staging of one 16-row tile of M: each thread moves NCH 16-byte chunks
 // (coalesced across the workgroup) from global memory into registers, and later
 // from registers into the LDS tile (kept in M's own precision, row stride LDT).
@@ -227,7 +234,8 @@ __device__ __forceinline__ void block_pass(const TM* __restrict__ M, int64_t ld,
   constexpr int NB = DQ / 16;  // 16-column output blocks per wave
   TM* tile = (TM*)tile_raw;
   const int lane = lane_id(), wave = wave_id();
-  const int kbase = wave * DQ;
+  const int dqe = wave_cols(d, DP);
+  const int kbase = wave * dqe;
   const int rr = threadIdx.x / KR, jj = threadIdx.x % KR;  // (row, column) of U per thread
   const int64_t ntiles = (rows + TROWS - 1) / TROWS;
   // PF tiles in flight: while tile t is computed, t + T (.. t + PF T) are loading;
@@ -246,7 +254,7 @@ __device__ __forceinline__ void block_pass(const TM* __restrict__ M, int64_t ld,
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
+      if (4 * s < dqe) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
       if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     // result register r of lane l: row l/16 + 4 r, column l % 16
@@ -269,7 +277,7 @@ __device__ __forceinline__ void block_pass(const TM* __restrict__ M, int64_t ld,
         const int r2 = 4 * s + (lane >> 4);
         const double a = (double)tile[r2 * C::LDT + kbase + 16 * b + (lane & 15)];
         const double bv = ufin[r2 * KR + (lane & 15)];
-        Gacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, Gacc[b], 0, 0, 0);
+        if (16 * b < dqe) Gacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, Gacc[b], 0, 0, 0);
       }
       if ((b & 1) == 1) __builtin_amdgcn_sched_barrier(0);
     }
@@ -291,15 +299,18 @@ __device__ __forceinline__ void block_pass(const TM* __restrict__ M, int64_t ld,
 
 // Store this wave's Gacc (d-slice x 16) to out[c * KR + j].
 template <int DP>
-__device__ __forceinline__ void store_block(const f64x4 (&Gacc)[DP / 64], double* out) {
+__device__ __forceinline__ void store_block(const f64x4 (&Gacc)[DP / 64], int d, double* out) {
   constexpr int DQ = DP / 4;
-  const int lane = lane_id(), kbase = wave_id() * DQ;
+  const int dqe = wave_cols(d, DP);
+  const int lane = lane_id(), kbase = wave_id() * dqe;
 #pragma unroll
   for (int b = 0; b < DQ / 16; ++b)
+    if (16 * b < dqe) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int c = kbase + 16 * b + (lane >> 4) + 4 * r;
-      out[(int64_t)c * KR + (lane & 15)] = Gacc[b][r];
+      for (int r = 0; r < 4; ++r) {
+        const int c = kbase + 16 * b + (lane >> 4) + 4 * r;
+        out[(int64_t)c * KR + (lane & 15)] = Gacc[b][r];
+      }
     }
 }
 
@@ -380,7 +391,8 @@ __device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t
   constexpr int DQ = DP / 4, KS = DQ / 4, NB = DQ / 16;
   constexpr int VE = 16 / (int)sizeof(TM);
   const int lane = lane_id(), wave = wave_id();
-  const int kbase = wave * DQ;
+  const int dqe = wave_cols(d, DP);
+  const int kbase = wave * dqe;
   const int rr = threadIdx.x / KR, jj = threadIdx.x % KR;
   const int64_t ngroups = (rows + C::ROWS - 1) / C::ROWS;
   const int dz = (d + VE - 1) / VE * VE;  // columns [d, dz) share a 16-byte chunk with d - 1
@@ -419,7 +431,7 @@ __device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
+        if (4 * s < dqe) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
         if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
@@ -442,7 +454,7 @@ __device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t
           const int r2 = 4 * s + (lane >> 4);
           const double a = (double)tile[r2 * C::LDT + kbase + 16 * b + (lane & 15)];
           const double bv = ufin[r2 * KR + (lane & 15)];
-          Gacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, Gacc[b], 0, 0, 0);
+          if (16 * b < dqe) Gacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, Gacc[b], 0, 0, 0);
         }
         if ((b & 1) == 1) __builtin_amdgcn_sched_barrier(0);
       }
@@ -481,7 +493,7 @@ __device__ __attribute__((noinline)) void a_pass(const TM* __restrict__ M, int64
   constexpr int KS = DQ / 4;
   constexpr int NB = DQ / 16;
   double* stage = (double*)lds_raw;
-  const int lane = lane_id(), kbase = wave_id() * DQ;
+  const int lane = lane_id(), kbase = wave_id() * wave_cols(d, DP);
   // X through the LDS stage (row-major d x 16 is the B-operand order)
   __syncthreads();
 #pragma unroll 8
@@ -503,7 +515,7 @@ __device__ __attribute__((noinline)) void a_pass(const TM* __restrict__ M, int64
   else
     block_pass<TM, DP, true>(M, ld, rows, d, rank, T, B, ldb, ldbc, ncols, Vreg, Gacc, lds_raw,
                              ured, ufin);
-  store_block<DP>(Gacc, part_out);
+  store_block<DP>(Gacc, d, part_out);
 }
 
 // q = H p + lambda p on the owned columns [c_lo, c_hi) (16-aligned blocks), p
@@ -678,8 +690,10 @@ __device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, 
 // per-column sums go through two LDS buffers in a fixed order.  Each wave forms
 // whole rows of H p for its own 16-row blocks (no reduction across waves, no
 // barrier inside the product) and skips the blocks and k-chunks at or beyond
-// d, where H is zero.  Same iteration as cg_solve (step lengths, masks,
-// breakdown and stop rule per column); z ends in the LDS region after p.
+// d, where H is zero; H streams through a ring of register buffers with
+// global-address-space loads (so that they are not counted with the LDS
+// traffic).  Same iteration as cg_solve (step lengths, masks, breakdown and
+// stop rule per column); z ends in the LDS region after p.
 template <typename TH, int DP>
 __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict__ H, int64_t ldh,
                                                             int d, const double* __restrict__ R,
@@ -692,6 +706,8 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
   double* red1 = red0 + kBlock;
   Shared& sh = g_sh;
   typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  typedef const u32x4 __attribute__((address_space(1)))* gvec;
+  typedef double __attribute__((address_space(1)))* gdbl;
   constexpr int NBW = DP / 64;                    // 16-row blocks per wave
   constexpr int NV = 4 * NBW;                     // owned entries per vector
   constexpr int VE = 16 / (int)sizeof(TH);        // elements per 16-byte load
@@ -712,7 +728,8 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int row = row_of(v);
-    r[v] = row < d ? R[(int64_t)row * KR + j] : 0.0;
+    r[v] = row < d ? ((const double __attribute__((address_space(1)))*)R)[(int64_t)row * KR + j]
+                   : 0.0;
     zl[row * KR + j] = 0.0;
   }
   const double lj = sh.lam[j];
@@ -754,7 +771,7 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
       auto fetch = [&](Chunk& buf, int t) {
         if (t < T) {
           const int b = t / nch;
-          const u32x4* src = hptr(b, t - b * nch);
+          const gvec src = (gvec)hptr(b, t - b * nch);
 #pragma unroll
           for (int i = 0; i < NLD; ++i) buf.u[i] = src[i];
         }
@@ -780,7 +797,7 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
                 const int o = (row0 + 4 * i) * KR + j;
                 const double pv = stage[o];
                 const double qv = acc[i] + lj * pv;
-                Q[o] = qv;
+                ((gdbl)Q)[o] = qv;
                 pq += pv * qv;
               }
               acc = (f64x4){0.0, 0.0, 0.0, 0.0};
@@ -811,7 +828,7 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
       // rows of blocks this wave skipped (at or beyond d) keep r = 0
       if (act && (v >> 2) < nbw) {
         zl[o] += al * stage[o];
-        r[v] -= al * Q[o];
+        r[v] -= al * ((gdbl)Q)[o];
       }
       rrp += r[v] * r[v];
     }
@@ -856,8 +873,8 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
   double* myscal = scal + (int64_t)rank * kNScal;
   double* stage = (double*)tile;  // d x 16 vectors (row-major = MFMA B-operand order)
   const bool cg = rank < Tc;
-  // a one-workgroup CG keeps its vectors in the workgroup (p and z in LDS:
-  // 2 x DP x 16 doubles within the tile region)
+  // a one-workgroup CG keeps p and r in LDS (2 x DP x 16 doubles within the
+  // tile region)
   const bool local_cg = Tc == 1 && 2 * (size_t)DP * KR * sizeof(double) <= kUredOffset;
   // CG members own 16-aligned column ranges of R, Z, Q, XP and X
   const int cpw = ((d + Tc - 1) / Tc + 15) / 16 * 16;
@@ -953,7 +970,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       __syncthreads();
 
       // ---- lockstep CG on (H + lambda_j I): in the workgroup when the CG
-      // sub-team is one workgroup (z then sits in LDS after p), else on the team
+      // sub-team is one workgroup, else on the team
       int64_t k;
       if (local_cg)
         k = a.h_f32 ? cg_solve_local<float, DP>((const float*)e.H, e.ldh, d, R, Q, a.eps_sub,

@@ -494,7 +494,10 @@ __global__ __launch_bounds__(kBlock) void gemm_f64_kernel(const TS* __restrict__
 // P[z] (M x N) = S[:, kz] B[kz, :] with BF16 inputs and FP32 accumulation
 // (v_mfma_f32_16x16x32_bf16: lane l holds 8 consecutive k, 8(l/16)..+7, of
 // row l%16 (A) / column l%16 (B); result register r of lane l is row
-// 4(l/16) + r, column l%16).
+// 4(l/16) + r, column l%16).  The global loads of k-step t + 1 are in flight
+// in registers while step t is computed from LDS; B is rounded to BF16 and
+// transposed on its way into LDS, each thread moving 16 consecutive k of one
+// column with two 16-byte stores.
 template <typename TB>
 __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(const uint16_t* __restrict__ S,
                                                            int64_t lds, int64_t M, int64_t K,
@@ -502,39 +505,77 @@ __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(const uint16_t* __res
                                                            int64_t N, int64_t kchunk,
                                                            float* __restrict__ P) {
   constexpr int BM = 128, BN = 128, BK = 32, PAD = 8;
+  constexpr int SQ = BM * (BK / 8) / kBlock;  // 16-byte S chunks per thread and step
+  constexpr int BR = BK * BN / kBlock;        // B elements per thread and step (one column)
+  static_assert(SQ == 2 && BR == 16, "tile shape");
   __shared__ __attribute__((aligned(16))) uint16_t As[BM][BK + PAD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][BK + PAD];
   const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   const int lane = lane_id(), wave = wave_id();
   const int wr = wave >> 1, wc = wave & 1;
+  const int bc = threadIdx.x % BN, br0 = (threadIdx.x / BN) * BR;  // B column, first k
   f32x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+  uint4 sreg[SQ];
+  TB breg[BR];
+  auto gload = [&](int64_t k0) {
     // S tile: 128 rows x 32 k, 8 bf16 (16 B) per load; lds is a multiple of 8
-    for (int e = threadIdx.x; e < BM * (BK / 8); e += kBlock) {
+#pragma unroll
+    for (int t = 0; t < SQ; ++t) {
+      const int e = (int)threadIdx.x + t * kBlock;
       const int r = e / (BK / 8), q = e % (BK / 8);
       const int64_t gr = m0 + r, gk = k0 + 8 * q;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (gr < M && gk < ke) {
         v = *(const uint4*)(S + gr * lds + gk);
         if (gk + 8 > ke) {  // zero the k's beyond this split's end
-          uint16_t* h = (uint16_t*)&v;
-          for (int t = (int)(ke - gk); t < 8; ++t) h[t] = 0;
+          union {
+            uint4 u;
+            uint16_t h[8];
+          } x;
+          x.u = v;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (gk + u >= ke) x.h[u] = 0;
+          v = x.u;
         }
       }
-      *(uint4*)&As[r][8 * q] = v;
+      sreg[t] = v;
     }
-    // B tile: 32 k x 128 n, transposed into Bs[n][k] with BF16 rounding
-    for (int e = threadIdx.x; e < BK * BN; e += kBlock) {
-      const int r = e / BN, c = e % BN;
-      const int64_t gk = k0 + r, gc = n0 + c;
-      Bs[c][r] = (gk < ke && gc < N) ? bf16_rne(B[gk * ldb + gc]) : (uint16_t)0;
+    // B: 16 consecutive k of column bc (coalesced across the threads of a k)
+    const int64_t gc = n0 + bc;
+#pragma unroll
+    for (int t = 0; t < BR; ++t) {
+      const int64_t gk = k0 + br0 + t;
+      breg[t] = (gk < ke && gc < N) ? B[gk * ldb + gc] : (TB)0;
     }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int t = 0; t < SQ; ++t) {
+      const int e = (int)threadIdx.x + t * kBlock;
+      const int r = e / (BK / 8), q = e % (BK / 8);
+      *(uint4*)&As[r][8 * q] = sreg[t];
+    }
+    union {
+      uint4 u[2];
+      uint16_t h[16];
+    } pk;
+#pragma unroll
+    for (int t = 0; t < BR; ++t) pk.h[t] = bf16_rne(breg[t]);
+    *(uint4*)&Bs[bc][br0] = pk.u[0];
+    *(uint4*)&Bs[bc][br0 + 8] = pk.u[1];
+  };
+  if (kb < ke) gload(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    __syncthreads();  // the previous step's products are done with As / Bs
+    lstore();
     __syncthreads();
+    if (k0 + BK < ke) gload(k0 + BK);  // in flight during this step's products
     bf16x8 a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)&As[wr * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)];
@@ -545,7 +586,6 @@ __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(const uint16_t* __res
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
   }
   float* Pz = P + (int64_t)blockIdx.z * M * N;
 #pragma unroll

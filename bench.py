@@ -230,7 +230,8 @@ def run_batched(args):
     solver = mihs.BatchedSolver([(A, b, SA) for (A, b), SA in zip(probs, sks)], lam_d, al_d,
                                 be_d, eps_sub=eps_sub, tol=args.tol, max_outer=400,
                                 max_inner=2000)
-    log("autotuning the launch shape (8 outer iterations per trial)")
+    log("autotuning the launch shape (8 outer iterations per shape trial, then two full runs "
+        "for the measured schedule)")
     t0 = time.perf_counter()
     tune = solver.tune(trial_outer=8)
     tune["wall_s"] = round(time.perf_counter() - t0, 2)

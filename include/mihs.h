@@ -371,12 +371,17 @@ int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
  *   inner_weight  the expected inner-CG cost per outer iteration, in passes
  *                 over H per column group, used to size the teams (team size
  *                 proportional to n d + inner_weight d^2; 1 to 10000).
- * mihs_batched_default_tuning() fills the defaults (32, 1, 100).
+ * mihs_batched_default_tuning() fills the defaults (32, 1, 100, measured 0).
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t cg_cols;
   int32_t a_dma;
   double inner_weight;
+  int32_t measured;  /* 1: size the teams from the per-problem costs that
+                        mihs_tune_batched measured on an equal problem set
+                        (inner_weight unused); without such a measurement the
+                        model above is used */
+  int32_t reserved;  /* 0 */
 } mihs_batched_tuning_t;
 
 void mihs_batched_default_tuning(mihs_batched_tuning_t* tuning);
@@ -419,7 +424,15 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
  * Autotuner of the batched launch shape.  Times trial solves of the given
  * problems (each from X = 0, at most trial_outer outer iterations, HIP events
  * on `stream`) over candidate shapes by coordinate descent: inner_weight in
- * {25, 100, 400}, then cg_cols in {16, 32, 64}, then a_dma in {1, 0}.  The best
+ * {6.25, 25, 100, 400}, then cg_cols in {16, 32, 64}, then a_dma in {1, 0}.
+ * If measure_outer > 0 it then runs the best shape for up to measure_outer
+ * outer iterations (normally the solve's own limit, so that every problem
+ * runs to its stop), reads the wall time of every problem
+ * (mihs_info_t.elapsed_us), takes time x team size as the problem's cost on
+ * one workgroup, and runs a schedule sized from those costs (teams of
+ * ceil(cost / L) workgroups for problems above a makespan L, first-fit bins
+ * of capacity L for the rest, the smallest L that fits) for as long;
+ * measured = 1 in *best if that one was faster.  The best
  * shape is returned in *best and kept in the handle, keyed by the problem set's
  * shapes (n, d, m of every problem and nlam); later mihs_solve_batched and
  * mihs_batched_plan_create calls on an equal set use it.  cand_ms (nullable,
@@ -432,9 +445,9 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
 int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, int64_t nprob,
                       const double* lambdas, const double* alphas, const double* betas,
                       int64_t nlam, mihs_precision_t precision, double eps_sub, double tol,
-                      int64_t trial_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
-                      void* stream, mihs_batched_tuning_t* best, float* cand_ms,
-                      int32_t* ncand);
+                      int64_t trial_outer, int64_t measure_outer, int64_t max_inner,
+                      void* workspace, size_t ws_bytes, void* stream,
+                      mihs_batched_tuning_t* best, float* cand_ms, int32_t* ncand);
 
 /* ------------------------------------------------------------------------
  * Backward of x*_j = (A^T A + lambda I)^{-1} A^T b_j for k right-hand sides.

@@ -47,10 +47,12 @@ INFO_BYTES = ctypes.sizeof(Info)  # 48
 
 class Tuning(ctypes.Structure):
     _fields_ = [("cg_cols", ctypes.c_int32), ("a_dma", ctypes.c_int32),
-                ("inner_weight", ctypes.c_double)]
+                ("inner_weight", ctypes.c_double), ("measured", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {"cg_cols": self.cg_cols, "a_dma": self.a_dma, "inner_weight": self.inner_weight}
+        return {"cg_cols": self.cg_cols, "a_dma": self.a_dma, "inner_weight": self.inner_weight,
+                "measured": self.measured}
 
 
 TUNE_MAX_CANDIDATES = 16
@@ -115,7 +117,7 @@ _SIGS = {
     "mihs_batched_plan_run": (_int, [_vp, _vp]),
     "mihs_batched_plan_destroy": (_int, [_vp]),
     "mihs_tune_batched": (_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl, _i64,
-                                 _i64, _vp, _sz, _vp, _vp, _vp, _vp]),
+                                 _i64, _i64, _vp, _sz, _vp, _vp, _vp, _vp]),
     "mihs_solve_backward_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
                                                   ctypes.POINTER(_sz)]),
     "mihs_solve_backward": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _int,
@@ -652,7 +654,8 @@ class BatchedSolver:
             self.plan = None
         tn = None
         if tuning is not None:
-            tn = Tuning(int(tuning["cg_cols"]), int(tuning["a_dma"]), float(tuning["inner_weight"]))
+            tn = Tuning(int(tuning["cg_cols"]), int(tuning["a_dma"]), float(tuning["inner_weight"]),
+                        int(tuning.get("measured", 0)), 0)
         eps_sub, tol, max_outer, max_inner = self.params
         plan = _vp()
         _check(lib.mihs_batched_plan_create(
@@ -663,18 +666,21 @@ class BatchedSolver:
             "mihs_batched_plan_create")
         self.plan = plan
 
-    def tune(self, trial_outer: int = 8) -> dict:
+    def tune(self, trial_outer: int = 8, measure: bool = True) -> dict:
         """Autotune the launch shape on these problems (blocking; overwrites X)
-        and re-plan with the choice.  Returns the choice and the trial times."""
+        and re-plan with the choice: coordinate descent on trial_outer-iteration
+        trials, then (measure) a schedule sized from per-problem times of a full
+        run.  Returns the choice and the trial times."""
         lib = load_library()
-        eps_sub, tol, _, max_inner = self.params
+        eps_sub, tol, max_outer, max_inner = self.params
         best = Tuning()
         times = (ctypes.c_float * TUNE_MAX_CANDIDATES)()
         nc = ctypes.c_int32()
         _check(lib.mihs_tune_batched(
             self.h, ctypes.cast(self.table, _vp), self.nprob, self.lam.data_ptr(),
             self.alp.data_ptr(), self.bet.data_ptr(), self.nlam, self.precision, eps_sub, tol,
-            int(trial_outer), max_inner, self.ws.data_ptr(), self.ws.numel(), _stream(self.dev),
+            int(trial_outer), int(max_outer) if measure else 0, max_inner, self.ws.data_ptr(),
+            self.ws.numel(), _stream(self.dev),
             ctypes.byref(best), times, ctypes.byref(nc)), "mihs_tune_batched")
         self._make_plan(best.as_dict())
         return {"best": best.as_dict(), "trial_ms": [round(times[i], 3) for i in range(nc.value)]}

@@ -702,11 +702,13 @@ int mihs_batched_plan_create(mihs_handle_t handle, const mihs_problem_t* h_probl
   std::vector<mihs::BlockEntryDesc> ents;
   batched_entries(h_problems, nprob, lambdas, alphas, betas, nlam, &ents);
   const int64_t count = (int64_t)ents.size();
-  const mihs_batched_tuning_t tn =
-      tuning ? *tuning : mihs::block_tuning_for(handle, ents.data(), count);
+  std::vector<double> cost;
+  mihs_batched_tuning_t tn = mihs::block_tuning_for(handle, ents.data(), count, &cost);
+  if (tuning) tn = *tuning;  // (the measured costs still come from the handle)
   mihs::BlockPlan* P = nullptr;
   rc = mihs::plan_block(handle, ents.data(), count, 0, precision == MIHS_MIXED, eps_sub, tol,
-                        max_outer, max_inner, tn, workspace, ws_bytes, as_stream(stream), &P);
+                        max_outer, max_inner, tn, &cost, workspace, ws_bytes, as_stream(stream),
+                        &P);
   if (rc) return rc;
   mihs_batched_plan* out = new (std::nothrow) mihs_batched_plan();
   if (!out) {
@@ -735,10 +737,10 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan) {
 int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, int64_t nprob,
                       const double* lambdas, const double* alphas, const double* betas,
                       int64_t nlam, mihs_precision_t precision, double eps_sub, double tol,
-                      int64_t trial_outer, int64_t max_inner, void* workspace, size_t ws_bytes,
-                      void* stream, mihs_batched_tuning_t* best, float* cand_ms,
-                      int32_t* ncand) {
-  if (!best || trial_outer < 1) return MIHS_ERR_INVALID;
+                      int64_t trial_outer, int64_t measure_outer, int64_t max_inner,
+                      void* workspace, size_t ws_bytes, void* stream,
+                      mihs_batched_tuning_t* best, float* cand_ms, int32_t* ncand) {
+  if (!best || trial_outer < 1 || measure_outer < 0) return MIHS_ERR_INVALID;
   int rc = check_batched(handle, h_problems, nprob, lambdas, alphas, betas, nlam, precision,
                          eps_sub, trial_outer, max_inner);
   if (rc) return rc;
@@ -754,14 +756,16 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
   }
   int n_tried = 0;
   // one timed trial from X = 0
-  auto trial = [&](const mihs_batched_tuning_t& tn, float* ms) -> int {
+  auto trial = [&](const mihs_batched_tuning_t& tn, float* ms,
+                   const std::vector<double>* cost = nullptr, int64_t outer = 0) -> int {
     for (int64_t p = 0; p < nprob; ++p) {
       const int r = mihs::launch_fill(h_problems[p].X, 0.0, h_problems[p].d * nlam, st);
       if (r) return r;
     }
     mihs::BlockPlan* P = nullptr;
     int r = mihs::plan_block(handle, ents.data(), count, 0, precision == MIHS_MIXED, eps_sub,
-                             tol, trial_outer, max_inner, tn, workspace, ws_bytes, st, &P);
+                             tol, outer > 0 ? outer : trial_outer, max_inner, tn, cost,
+                             workspace, ws_bytes, st, &P);
     if (r) return r;
     if (hipEventRecord(e0, st) != hipSuccess) r = MIHS_ERR_HIP;
     if (!r) r = mihs::run_block(P, st);
@@ -780,7 +784,7 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
   float cur_ms = 0.0f;
   rc = trial(cur, &cur_ms);
   // coordinate descent: inner_weight, then cg_cols, then a_dma
-  const double weights[] = {25.0, 400.0};
+  const double weights[] = {6.25, 25.0, 400.0};
   for (double w : weights) {
     if (rc) break;
     mihs_batched_tuning_t t = cur;
@@ -815,20 +819,42 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
       cur_ms = ms;
     }
   }
+  // measured costs: every entry's wall time in a run of the best shape times
+  // its team size, then a schedule sized from them, run for as long
+  std::vector<double> cost;
+  if (!rc && measure_outer > 0) {
+    std::vector<int> tsz;
+    float ms = 0.0f;
+    rc = mihs::block_team_sizes(handle, ents.data(), count, cur, nullptr, &tsz);
+    if (!rc) rc = trial(cur, &cur_ms, nullptr, measure_outer);
+    if (!rc) {
+      cost.resize(count);
+      for (int64_t i = 0; i < count; ++i) {
+        mihs_info_t rec;
+        if (hipMemcpy(&rec, ents[i].info, sizeof(rec), hipMemcpyDeviceToHost) != hipSuccess) {
+          rc = MIHS_ERR_HIP;
+          break;
+        }
+        cost[i] = (double)rec.elapsed_us * tsz[i];
+      }
+    }
+    if (!rc) {
+      mihs_batched_tuning_t t = cur;
+      t.measured = 1;
+      rc = trial(t, &ms, &cost, measure_outer);
+      if (!rc && ms < cur_ms) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (ncand) *ncand = n_tried;
   if (rc) return rc;
   *best = cur;
-  const uint64_t key = mihs::block_signature(ents.data(), count);
-  std::lock_guard<std::mutex> lock(handle->tune_mu);
-  bool found = false;
-  for (auto& kv : handle->tuned)
-    if (kv.first == key) {
-      kv.second = cur;
-      found = true;
-    }
-  if (!found) handle->tuned.emplace_back(key, cur);
+  mihs::block_tuning_store(handle, ents.data(), count, cur,
+                           cur.measured ? cost : std::vector<double>());
   return MIHS_OK;
 }
 

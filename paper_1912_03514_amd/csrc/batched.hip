@@ -1097,15 +1097,11 @@ int block_max_d() { return 1024; }
 
 bool block_tuning_valid(const mihs_batched_tuning_t& t) {
   return (t.cg_cols == 16 || t.cg_cols == 32 || t.cg_cols == 64) &&
-         (t.a_dma == 0 || t.a_dma == 1) && t.inner_weight >= 1.0 && t.inner_weight <= 1e4;
+         (t.a_dma == 0 || t.a_dma == 1) && t.inner_weight >= 1.0 && t.inner_weight <= 1e4 &&
+         (t.measured == 0 || t.measured == 1);
 }
 
 namespace {
-
-// Candidate shapes (every one must fit the workspace that block_workspace_bytes
-// reports): the coordinate-descent axes of the tuner.
-const double kInnerWeights[] = {25.0, 100.0, 400.0};
-const int kCgCols[] = {16, 32, 64};
 
 // Deterministic schedule of the entries over G workgroups (also used to size
 // the workspace): dedicated teams for heavy entries, single-workgroup bins for
@@ -1116,8 +1112,79 @@ struct Schedule {
   size_t stride = 1;
 };
 
+// Sizing from measured costs c_i (entry i on one workgroup): the smallest
+// makespan L (bisection) for which teams of ceil(c_i / L) workgroups for the
+// entries above L and first-fit-decreasing bins of capacity L for the rest fit
+// in G workgroups.
+bool makespan_schedule(const std::vector<double>& c, int G, double L, Schedule* S) {
+  const int64_t count = (int64_t)c.size();
+  std::vector<int64_t> order(count);
+  for (int64_t i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return c[x] > c[y]; });
+  S->team0.assign(count, 0);
+  S->tsize.assign(count, 1);
+  S->tcg.assign(count, 1);
+  S->items.assign(G, std::vector<int>());
+  int next = 0;
+  for (int64_t i : order) {
+    if (c[i] <= L) break;
+    const int t = (int)std::ceil(c[i] / L - 1e-9);
+    if (next + t > G) return false;
+    S->team0[i] = next;
+    S->tsize[i] = t;
+    for (int u = 0; u < t; ++u) S->items[next + u].push_back((int)i);
+    next += t;
+  }
+  const int first_bin = next;
+  std::vector<double> load;
+  for (int64_t i : order) {
+    if (c[i] > L) continue;
+    size_t b = 0;
+    while (b < load.size() && load[b] + c[i] > L * (1.0 + 1e-9)) ++b;
+    if (b == load.size()) {
+      if (first_bin + (int)b >= G) return false;
+      load.push_back(0.0);
+    }
+    load[b] += c[i];
+    S->team0[i] = first_bin + (int)b;
+    S->items[first_bin + b].push_back((int)i);
+  }
+  return true;
+}
+
 int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
-                  const mihs_batched_tuning_t& tn, Schedule* S) {
+                  const mihs_batched_tuning_t& tn, const std::vector<double>* cost,
+                  Schedule* S) {
+  if (tn.measured && cost && (int64_t)cost->size() == count) {
+    double hi = 0.0, sum = 0.0;
+    for (double v : *cost) {
+      hi = std::max(hi, std::max(v, 1.0));
+      sum += std::max(v, 1.0);
+    }
+    std::vector<double> c(count);
+    for (int64_t i = 0; i < count; ++i) c[i] = std::max((*cost)[i], 1.0);
+    double lo = std::max(sum / G, 1.0);
+    hi = std::max(hi, sum);  // one entry per workgroup in turn always fits when count <= G
+    Schedule T;
+    if (!makespan_schedule(c, G, hi, &T)) return MIHS_ERR_UNSUPPORTED;
+    for (int it = 0; it < 48 && hi > lo * (1.0 + 1e-4); ++it) {
+      const double mid = 0.5 * (lo + hi);
+      Schedule U;
+      if (makespan_schedule(c, G, mid, &U)) {
+        hi = mid;
+        T = U;
+      } else {
+        lo = mid;
+      }
+    }
+    *S = T;
+    for (int64_t i = 0; i < count; ++i)
+      S->tcg[i] = std::max(
+          1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
+    S->stride = 1;
+    for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
+    return MIHS_OK;
+  }
   // weight: one A pass plus the expected inner solve on H per outer iteration
   // (inner_weight passes over H; lockstep CGs over 16 lambdas down to
   // 1e-6 sigma_1^2 take ~100 steps)
@@ -1263,18 +1330,20 @@ struct BlockPlan {
 
 size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count) {
   if (count <= 0) return 0;
-  size_t most = 0;
-  mihs_batched_tuning_t tn;
-  mihs_batched_default_tuning(&tn);
-  for (double w : kInnerWeights)
-    for (int cc : kCgCols) {
-      tn.inner_weight = w;
-      tn.cg_cols = cc;
-      Schedule S;
-      if (make_schedule(ents, count, h->num_cu, tn, &S) != MIHS_OK) return 0;
-      most = std::max(most, block_layout(ents, count, S, h->num_cu).total);
-    }
-  return most;
+  // Every schedule has at most G team members in all and at most G items per
+  // workgroup list: size for teams of one plus G extra members of the widest
+  // entry, and the longest item list.
+  const int G = h->num_cu;
+  Schedule S;
+  S.team0.assign(count, 0);
+  S.tsize.assign(count, 1);
+  S.tcg.assign(count, 1);
+  S.stride = (size_t)std::max<int64_t>(count, G) + 1;
+  int dpmax = 64;
+  for (int64_t i = 0; i < count; ++i) dpmax = std::max(dpmax, dp_for(ents[i].d));
+  const size_t base = block_layout(ents, count, S, G).total;
+  const size_t extra = (size_t)G * ((size_t)dpmax * KR + kNScal) * sizeof(double) + 256 * (size_t)count;
+  return base + extra;
 }
 
 uint64_t block_signature(const BlockEntryDesc* ents, int64_t count) {
@@ -1290,21 +1359,48 @@ uint64_t block_signature(const BlockEntryDesc* ents, int64_t count) {
   return s;
 }
 
-mihs_batched_tuning_t block_tuning_for(mihs_handle* h, const BlockEntryDesc* ents,
-                                       int64_t count) {
+mihs_batched_tuning_t block_tuning_for(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
+                                       std::vector<double>* cost) {
   mihs_batched_tuning_t tn;
   mihs_batched_default_tuning(&tn);
+  if (cost) cost->clear();
   const uint64_t key = block_signature(ents, count);
   std::lock_guard<std::mutex> lock(h->tune_mu);
-  for (const auto& kv : h->tuned)
-    if (kv.first == key) return kv.second;
+  for (const auto& t : h->tuned)
+    if (t.key == key) {
+      if (cost) *cost = t.cost;
+      return t.tuning;
+    }
   return tn;
+}
+
+void block_tuning_store(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
+                        const mihs_batched_tuning_t& tuning, const std::vector<double>& cost) {
+  const uint64_t key = block_signature(ents, count);
+  std::lock_guard<std::mutex> lock(h->tune_mu);
+  for (auto& t : h->tuned)
+    if (t.key == key) {
+      t.tuning = tuning;
+      t.cost = cost;
+      return;
+    }
+  h->tuned.push_back(mihs_tuned_set{key, tuning, cost});
+}
+
+int block_team_sizes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
+                     const mihs_batched_tuning_t& tuning, const std::vector<double>* cost,
+                     std::vector<int>* tsize) {
+  Schedule S;
+  const int rc = make_schedule(ents, count, h->num_cu, tuning, cost, &S);
+  if (rc) return rc;
+  *tsize = S.tsize;
+  return MIHS_OK;
 }
 
 int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
                int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
-               const mihs_batched_tuning_t& tuning, void* ws, size_t ws_bytes, hipStream_t st,
-               BlockPlan** out) {
+               const mihs_batched_tuning_t& tuning, const std::vector<double>* cost, void* ws,
+               size_t ws_bytes, hipStream_t st, BlockPlan** out) {
   *out = nullptr;
   if (count <= 0) return MIHS_ERR_INVALID;
   if (!block_tuning_valid(tuning)) return MIHS_ERR_INVALID;
@@ -1327,7 +1423,7 @@ int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, 
   const int G = h->num_cu;  // one workgroup per compute unit
 
   Schedule S;
-  int rc = make_schedule(ents, count, G, tuning, &S);
+  int rc = make_schedule(ents, count, G, tuning, cost, &S);
   if (rc) return rc;
   const BlockLayout L = block_layout(ents, count, S, G);
   if (!ws || L.total > ws_bytes) return MIHS_ERR_WORKSPACE;
@@ -1469,10 +1565,11 @@ int launch_block(mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int 
                  int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
                  void* ws, size_t ws_bytes, hipStream_t st) {
   if (count <= 0) return MIHS_OK;
-  const mihs_batched_tuning_t tn = block_tuning_for(h, ents, count);
+  std::vector<double> cost;
+  const mihs_batched_tuning_t tn = block_tuning_for(h, ents, count, &cost);
   BlockPlan* P = nullptr;
-  int rc = plan_block(h, ents, count, a_f32, sa_f32, eps_sub, tol, max_outer, max_inner, tn, ws,
-                      ws_bytes, st, &P);
+  int rc = plan_block(h, ents, count, a_f32, sa_f32, eps_sub, tol, max_outer, max_inner, tn,
+                      &cost, ws, ws_bytes, st, &P);
   if (rc) return rc;
   rc = run_block(P, st);
   free_block_plan(P);
@@ -1486,4 +1583,6 @@ extern "C" void mihs_batched_default_tuning(mihs_batched_tuning_t* t) {
   t->cg_cols = 32;
   t->a_dma = 1;
   t->inner_weight = 100.0;
+  t->measured = 0;
+  t->reserved = 0;
 }

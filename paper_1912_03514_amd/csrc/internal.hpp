@@ -11,14 +11,21 @@
 #include <utility>
 #include <vector>
 
+// A batched launch shape chosen by mihs_tune_batched for one problem set, with
+// the per-entry costs (one workgroup, microseconds) it measured.
+struct mihs_tuned_set {
+  uint64_t key;
+  mihs_batched_tuning_t tuning;
+  std::vector<double> cost;
+};
+
 struct mihs_handle {
   int device;
   int num_cu;
   int wall_khz;  // rate of the device's constant wall clock
   char arch[64];
-  // batched launch shapes chosen by mihs_tune_batched, keyed by problem set
   std::mutex tune_mu;
-  std::vector<std::pair<uint64_t, mihs_batched_tuning_t>> tuned;
+  std::vector<mihs_tuned_set> tuned;
 };
 
 namespace mihs {
@@ -132,13 +139,23 @@ size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, i
 // Key of a problem set for the tuning cache: (n, d, m, ncols, sketch group) of each entry.
 uint64_t block_signature(const BlockEntryDesc* ents, int64_t count);
 bool block_tuning_valid(const mihs_batched_tuning_t& t);
-// The tuned shape for this set if the handle has one, else the defaults.
-mihs_batched_tuning_t block_tuning_for(mihs_handle* h, const BlockEntryDesc* ents, int64_t count);
+// The tuned shape for this set if the handle has one, else the defaults; the
+// measured per-entry costs go to *cost (empty if none).
+mihs_batched_tuning_t block_tuning_for(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
+                                       std::vector<double>* cost);
+// Keep a tuned shape (and its measured costs) for this set.
+void block_tuning_store(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
+                        const mihs_batched_tuning_t& tuning, const std::vector<double>& cost);
+// Team size of every entry under a shape (cost: measured costs or null).
+int block_team_sizes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
+                     const mihs_batched_tuning_t& tuning, const std::vector<double>* cost,
+                     std::vector<int>* tsize);
 struct BlockPlan;  // opaque: kernel, launch shape, argument block, device tables
+// cost: per-entry costs for tuning.measured (null or empty: the n d + w d^2 model)
 int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
                int sa_f32, double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
-               const mihs_batched_tuning_t& tuning, void* ws, size_t ws_bytes,
-               hipStream_t stream, BlockPlan** plan);
+               const mihs_batched_tuning_t& tuning, const std::vector<double>* cost, void* ws,
+               size_t ws_bytes, hipStream_t stream, BlockPlan** plan);
 int run_block(const BlockPlan* plan, hipStream_t stream);
 void free_block_plan(BlockPlan* plan);
 // plan + run + free with the handle's tuning (one call, as before).

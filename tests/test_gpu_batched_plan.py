@@ -106,9 +106,11 @@ def test_graph_replays_match_the_eager_run(problem_set):
 
 
 def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
-    """mihs_tune_batched times six candidate shapes by coordinate descent and
-    keeps the best for this problem set: the plain batched call afterwards (which
-    looks the shape up) still reaches the closed form."""
+    """mihs_tune_batched times seven candidate shapes by coordinate descent, a
+    full run of the best and a schedule sized from its per-problem costs,
+    and keeps the best for this problem set: the plain batched call afterwards
+    (which looks the shape up) still reaches the closed form, and so does a plan
+    that asks for the measured schedule explicitly."""
     mihs = _mihs()
     dp, refs, L, Al, Be = _device_set(problem_set)
     s = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
@@ -116,10 +118,11 @@ def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
     announce("batched autotuner")
     res = s.tune(trial_outer=3)
     best = res["best"]
-    assert len(res["trial_ms"]) == 6
+    assert len(res["trial_ms"]) == 9
     assert all(t > 0 for t in res["trial_ms"])
     assert best["cg_cols"] in (16, 32, 64) and best["a_dma"] in (0, 1)
-    assert best["inner_weight"] in (25.0, 100.0, 400.0)
+    assert best["inner_weight"] in (6.25, 25.0, 100.0, 400.0)
+    assert best["measured"] in (0, 1)
     s.run()
     torch.cuda.synchronize()
     _check_closed_form(s.xs, s.infos(), refs)
@@ -127,6 +130,12 @@ def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
     xs, infos = mihs.mihs_solve_batched(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
                                         max_inner=2000)
     _check_closed_form(xs, infos, refs)
+    announce("batched plan on the measured schedule")
+    m = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800, max_inner=2000,
+                           tuning=dict(best, measured=1))
+    m.run()
+    torch.cuda.synchronize()
+    _check_closed_form(m.xs, m.infos(), refs)
 
 
 def test_plan_rejects_bad_tuning(problem_set):

@@ -251,11 +251,17 @@ __device__ __forceinline__ void block_pass(const TM* __restrict__ M, int64_t ld,
     if (t + PF * T < ntiles) tile_load<TM, DP, NT>(M, ld, rows, d, (t + PF * T) * TROWS, buf);
     // partial U over this wave's k-range
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    // (dqe is a multiple of 16: groups of four k-steps are all in or all out)
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
-      if (4 * s < dqe) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
-      if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    for (int s4 = 0; s4 < KS; s4 += 4) {
+      if (4 * s4 < dqe) {
+#pragma unroll
+        for (int s = s4; s < s4 + 4; ++s) {
+          const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
+        }
+      }
+      if ((s4 & 7) == 4) __builtin_amdgcn_sched_barrier(0);
     }
     // result register r of lane l: row l/16 + 4 r, column l % 16
 #pragma unroll
@@ -428,11 +434,17 @@ __device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t
       const TM* tile = tileg + t * TROWS * C::LDT;
       const int64_t gr = row0 + t * TROWS + rr;
       f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      // (dqe is a multiple of 16: groups of four k-steps are all in or all out)
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
-        if (4 * s < dqe) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
-        if ((s & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      for (int s4 = 0; s4 < KS; s4 += 4) {
+        if (4 * s4 < dqe) {
+#pragma unroll
+          for (int s = s4; s < s4 + 4; ++s) {
+            const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
+          }
+        }
+        if ((s4 & 7) == 4) __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)

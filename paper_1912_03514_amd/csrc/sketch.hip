@@ -491,84 +491,97 @@ __global__ __launch_bounds__(kBlock) void gemm_f64_kernel(const TS* __restrict__
       }
 }
 
-// P[z] (M x N) = S[:, kz] B[kz, :] with BF16 inputs and FP32 accumulation
+// Bt (N x ldbt, BF16 bits) = B^T rounded to BF16 (round to nearest even of the
+// exact value), zero for k in [K, ldbt): the sketch GEMM's right operand with k
+// contiguous, made once per sketch so that the GEMM streams 2-byte values
+// instead of re-reading (and re-rounding) B for every 128-row tile of S.
+// 64 x 64 tiles through LDS: reads along n, writes along k.
+template <typename TB>
+__global__ __launch_bounds__(kBlock) void bf16_transpose_kernel(const TB* __restrict__ B,
+                                                                int64_t K, int64_t N, int64_t ldb,
+                                                                uint16_t* __restrict__ Bt,
+                                                                int64_t ldbt) {
+  __shared__ uint16_t tile[64][66];
+  const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int kk = ty + 4 * i;
+    const int64_t gk = k0 + kk, gn = n0 + tx;
+    tile[kk][tx] = (gk < K && gn < N) ? bf16_rne(B[gk * ldb + gn]) : (uint16_t)0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int nn = ty + 4 * i;
+    const int64_t gn = n0 + nn, gk = k0 + tx;
+    if (gn < N && gk < ldbt) Bt[gn * ldbt + gk] = tile[tx][nn];
+  }
+}
+
+// P[z] (M x N) = S[:, kz] B[kz, :] with BF16 inputs and FP32 accumulation, B
+// given as Bt = B^T in BF16 (both operands k-contiguous)
 // (v_mfma_f32_16x16x32_bf16: lane l holds 8 consecutive k, 8(l/16)..+7, of
 // row l%16 (A) / column l%16 (B); result register r of lane l is row
-// 4(l/16) + r, column l%16).  The global loads of k-step t + 1 are in flight
-// in registers while step t is computed from LDS; B is rounded to BF16 and
-// transposed on its way into LDS, each thread moving 16 consecutive k of one
-// column with two 16-byte stores.
-template <typename TB>
+// 4(l/16) + r, column l%16).  128 x 128 tiles, 64 k per step; the global loads
+// of step t + 1 are in flight in registers while step t is multiplied from LDS.
 __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(const uint16_t* __restrict__ S,
                                                            int64_t lds, int64_t M, int64_t K,
-                                                           const TB* __restrict__ B, int64_t ldb,
-                                                           int64_t N, int64_t kchunk,
-                                                           float* __restrict__ P) {
-  constexpr int BM = 128, BN = 128, BK = 32, PAD = 8;
-  constexpr int SQ = BM * (BK / 8) / kBlock;  // 16-byte S chunks per thread and step
-  constexpr int BR = BK * BN / kBlock;        // B elements per thread and step (one column)
-  static_assert(SQ == 2 && BR == 16, "tile shape");
+                                                           const uint16_t* __restrict__ Bt,
+                                                           int64_t ldbt, int64_t N,
+                                                           int64_t kchunk, float* __restrict__ P) {
+  constexpr int BM = 128, BN = 128, BK = 64, PAD = 8;
+  constexpr int Q = BM * (BK / 8) / kBlock;  // 16-byte chunks per operand, thread and step
+  static_assert(BM == BN && Q == 4, "tile shape");
   __shared__ __attribute__((aligned(16))) uint16_t As[BM][BK + PAD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][BK + PAD];
   const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   const int lane = lane_id(), wave = wave_id();
   const int wr = wave >> 1, wc = wave & 1;
-  const int bc = threadIdx.x % BN, br0 = (threadIdx.x / BN) * BR;  // B column, first k
   f32x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  uint4 sreg[SQ];
-  TB breg[BR];
+  uint4 sreg[Q], breg[Q];
   auto gload = [&](int64_t k0) {
-    // S tile: 128 rows x 32 k, 8 bf16 (16 B) per load; lds is a multiple of 8
 #pragma unroll
-    for (int t = 0; t < SQ; ++t) {
+    for (int t = 0; t < Q; ++t) {
       const int e = (int)threadIdx.x + t * kBlock;
       const int r = e / (BK / 8), q = e % (BK / 8);
-      const int64_t gr = m0 + r, gk = k0 + 8 * q;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (gr < M && gk < ke) {
-        v = *(const uint4*)(S + gr * lds + gk);
-        if (gk + 8 > ke) {  // zero the k's beyond this split's end
-          union {
-            uint4 u;
-            uint16_t h[8];
-          } x;
-          x.u = v;
+      const int64_t gk = k0 + 8 * q;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u), w = make_uint4(0u, 0u, 0u, 0u);
+      if (gk < ke) {
+        const int64_t gr = m0 + r, gn = n0 + r;
+        if (gr < M) {
+          v = *(const uint4*)(S + gr * lds + gk);
+          if (gk + 8 > ke) {  // zero the k's beyond this split's end (in S only)
+            union {
+              uint4 u;
+              uint16_t h[8];
+            } x;
+            x.u = v;
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (gk + u >= ke) x.h[u] = 0;
-          v = x.u;
+            for (int u = 0; u < 8; ++u)
+              if (gk + u >= ke) x.h[u] = 0;
+            v = x.u;
+          }
         }
+        if (gn < N) w = *(const uint4*)(Bt + gn * ldbt + gk);
       }
       sreg[t] = v;
-    }
-    // B: 16 consecutive k of column bc (coalesced across the threads of a k)
-    const int64_t gc = n0 + bc;
-#pragma unroll
-    for (int t = 0; t < BR; ++t) {
-      const int64_t gk = k0 + br0 + t;
-      breg[t] = (gk < ke && gc < N) ? B[gk * ldb + gc] : (TB)0;
+      breg[t] = w;
     }
   };
   auto lstore = [&]() {
 #pragma unroll
-    for (int t = 0; t < SQ; ++t) {
+    for (int t = 0; t < Q; ++t) {
       const int e = (int)threadIdx.x + t * kBlock;
       const int r = e / (BK / 8), q = e % (BK / 8);
       *(uint4*)&As[r][8 * q] = sreg[t];
+      *(uint4*)&Bs[r][8 * q] = breg[t];
     }
-    union {
-      uint4 u[2];
-      uint16_t h[16];
-    } pk;
-#pragma unroll
-    for (int t = 0; t < BR; ++t) pk.h[t] = bf16_rne(breg[t]);
-    *(uint4*)&Bs[bc][br0] = pk.u[0];
-    *(uint4*)&Bs[bc][br0 + 8] = pk.u[1];
   };
   if (kb < ke) gload(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += BK) {
@@ -576,16 +589,21 @@ __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(const uint16_t* __res
     lstore();
     __syncthreads();
     if (k0 + BK < ke) gload(k0 + BK);  // in flight during this step's products
-    bf16x8 a[4], b[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)&As[wr * 64 + i * 16 + (lane & 15)][8 * (lane >> 4)];
+    for (int kk = 0; kk < BK; kk += 32) {
+      bf16x8 a[4], b[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8*)&Bs[wc * 64 + j * 16 + (lane & 15)][8 * (lane >> 4)];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
+        a[i] = *(const bf16x8*)&As[wr * 64 + i * 16 + (lane & 15)][kk + 8 * (lane >> 4)];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        b[j] = *(const bf16x8*)&Bs[wc * 64 + j * 16 + (lane & 15)][kk + 8 * (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
   }
   float* Pz = P + (int64_t)blockIdx.z * M * N;
 #pragma unroll
@@ -619,12 +637,14 @@ struct GaussPlan {
   int64_t lds;     // padded row stride of S
   int splits;
   int64_t kchunk;
-  size_t s_bytes, p_bytes;
+  int64_t ldbt;    // row stride of the BF16 transpose of B (mixed)
+  size_t s_bytes, p_bytes, bt_bytes;
+  size_t total() const { return s_bytes + p_bytes + bt_bytes; }
 };
 
 GaussPlan gauss_plan(const mihs_handle* h, int64_t M, int64_t K, int64_t N, int mixed) {
   GaussPlan g;
-  const int BM = mixed ? 128 : 64, BN = mixed ? 128 : 64, BK = mixed ? 32 : 16;
+  const int BM = mixed ? 128 : 64, BN = mixed ? 128 : 64, BK = mixed ? 64 : 16;
   g.lds = (K + 7) / 8 * 8;
   const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
   int64_t want = ceil_div(2 * (int64_t)h->num_cu, tiles);
@@ -636,6 +656,8 @@ GaussPlan gauss_plan(const mihs_handle* h, int64_t M, int64_t K, int64_t N, int 
   g.splits = (int)ceil_div(K, g.kchunk);
   g.s_bytes = align_up((size_t)M * g.lds * (mixed ? 2 : 8), 256);
   g.p_bytes = align_up((size_t)g.splits * M * N * (mixed ? 4 : 8), 256);
+  g.ldbt = (K + 7) / 8 * 8;
+  g.bt_bytes = mixed ? align_up((size_t)N * g.ldbt * 2, 256) : 0;
   return g;
 }
 
@@ -646,7 +668,7 @@ int run_gauss(const mihs_handle* h, const TB* B, int64_t K, int64_t N, int64_t l
               uint32_t seed, uint64_t stream_id, int mixed, void* out, int64_t ldo, char* ws,
               size_t ws_bytes, hipStream_t st) {
   const GaussPlan g = gauss_plan(h, M, K, N, mixed);
-  if (ws_bytes < g.s_bytes + g.p_bytes) return MIHS_ERR_WORKSPACE;
+  if (ws_bytes < g.total()) return MIHS_ERR_WORKSPACE;
   void* S = ws;
   void* P = ws + g.s_bytes;
   const double scale = 1.0 / sqrt((double)M);
@@ -662,9 +684,13 @@ int run_gauss(const mihs_handle* h, const TB* B, int64_t K, int64_t N, int64_t l
                        st, S, mixed ? 2 : 8, M, K, g.lds);
   if (!hip_ok()) return MIHS_ERR_HIP;
   if (mixed) {
+    uint16_t* Bt = (uint16_t*)(ws + g.s_bytes + g.p_bytes);
+    hipLaunchKernelGGL(bf16_transpose_kernel<TB>,
+                       dim3((unsigned)ceil_div(N, 64), (unsigned)ceil_div(g.ldbt, 64)),
+                       dim3(kBlock), 0, st, B, K, N, ldb, Bt, g.ldbt);
     dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)g.splits);
-    hipLaunchKernelGGL(gemm_bf16_kernel<TB>, grid, dim3(kBlock), 0, st, (const uint16_t*)S, g.lds,
-                       M, K, B, ldb, N, g.kchunk, (float*)P);
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kBlock), 0, st, (const uint16_t*)S, g.lds,
+                       M, K, (const uint16_t*)Bt, g.ldbt, N, g.kchunk, (float*)P);
     hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), dim3((unsigned)ceil_div(M * N, 256)),
                        dim3(256), 0, st, (const float*)P, g.splits, M, N, (float*)out, ldo);
   } else {
@@ -803,7 +829,7 @@ size_t sketch_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_
   switch (kind) {
     case MIHS_GAUSSIAN: {
       const GaussPlan g = gauss_plan(h, m, n, d, mixed);
-      return g.s_bytes + g.p_bytes;
+      return g.total();
     }
     case MIHS_SRHT: {
       const int64_t ldy = (d + 3) / 4 * 4;
@@ -815,7 +841,7 @@ size_t sketch_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_
       const int64_t ldc = (d + 3) / 4 * 4;
       const size_t ca = align_up((size_t)m * ldc * (mixed ? 4 : 8), 256);
       const GaussPlan g = gauss_plan(h, m2, m, d, mixed);
-      const size_t a = cs_plan(n, m).total, b = g.s_bytes + g.p_bytes;
+      const size_t a = cs_plan(n, m).total, b = g.total();
       return ca + (a > b ? a : b);
     }
     default:

@@ -404,17 +404,22 @@ __global__ void gauss_gen_kernel(TSel* S, int64_t M, int64_t K, int64_t lds, uin
   if (first >= total) return;
   double z[4];
   gaussian_block(seed, stream, (uint64_t)e, z);
+  // row and column of the first element (one 64-bit division per thread), then
+  // step along the row with wrap-around
+  int64_t i = first / K, j = first - i * K;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int64_t f = first + t;
-    if (f < total) {
-      const int64_t i = f / K, j = f % K;
+    if (first + t < total) {
       const double v = z[t] * scale;
       if constexpr (sizeof(TSel) == 8) {
         S[i * lds + j] = v;
       } else {
         S[i * lds + j] = bf16_rne(v);
       }
+    }
+    if (++j == K) {
+      j = 0;
+      ++i;
     }
   }
 }

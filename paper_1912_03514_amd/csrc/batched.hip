@@ -352,6 +352,11 @@ struct DmaCfg {
 
 typedef __attribute__((address_space(3))) char lds_char;
 
+// Cache policy of the A-stream loads: non-temporal (A is read once per outer
+// iteration; the Gram matrices the inner CG re-reads every step should stay in
+// the caches instead).
+constexpr int kStreamAux = 2;
+
 // Issue the DMA of rows [row0, row0 + ROWS) into buffer `dst`: lane l of the
 // instruction for (row r, chunk c) moves 16 bytes at column c*1024/s + 16 l/s.
 // Rows past the end and columns past d read finite in-bounds data instead
@@ -368,7 +373,7 @@ __device__ __forceinline__ void dma_group(const TM* __restrict__ M, int64_t ld, 
     const int64_t gr = min(row0 + r, rows - 1);
     const int col = c * (1024 / (int)sizeof(TM)) + lane * (16 / (int)sizeof(TM));
     const TM* src = M + gr * ld + (col < d ? col : 0);
-    __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(dst + r * C::LDB + c * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(dst + r * C::LDB + c * 1024), 16, 0, kStreamAux);
   }
 }
 

@@ -440,6 +440,22 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
  * candidate order and *ncand their count (nullable).  The trials overwrite X
  * and info: initialise X after tuning.  Blocks until the trials end.
  * ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------
+ * The batched launch's schedule without a device (host computation only; for
+ * inspection and tests).  Problem k of nprob has n[k] x d[k] and nlam columns
+ * (one entry per group of up to 16); num_cu workgroups.  With tuning->measured
+ * = 1 and cost non-NULL (one value per entry: its time on one workgroup) the
+ * teams come from the makespan rule of mihs_tune_batched, else from the model
+ * n d + inner_weight d^2.  Per entry (problem-major, groups of 16 columns in
+ * order): team0[e] first workgroup, tsize[e] team size (1: the entry shares a
+ * single-workgroup bin), tcg[e] inner-CG sub-team size.  Arrays hold
+ * nprob * ceil(nlam / 16) values.  Returns MIHS_ERR_UNSUPPORTED if the entries
+ * do not fit.
+ * ------------------------------------------------------------------------ */
+int mihs_batched_schedule(int32_t num_cu, const int64_t* n, const int64_t* d, int64_t nprob,
+                          int64_t nlam, const mihs_batched_tuning_t* tuning, const double* cost,
+                          int32_t* team0, int32_t* tsize, int32_t* tcg);
+
 #define MIHS_TUNE_MAX_CANDIDATES 16
 
 int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, int64_t nprob,

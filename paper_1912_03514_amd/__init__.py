@@ -11,7 +11,7 @@ device memory and the current HIP stream.
 """
 from ._binding import (  # noqa: F401
     EXPORTED, INFO_BYTES, LIB_PATH, BatchedSolver, MihsError, SolveWorkspace, handle,
-    info_to_dict, sketch_workspace_bytes,
+    batched_schedule, info_to_dict, sketch_workspace_bytes,
     load_library, mihs_estimate_sd, mihs_sketch, mihs_sketch_two_stage, mihs_solve,
     mihs_solve_backward, mihs_solve_batched, mihs_solve_dual, mihs_solve_multi, mihs_solve_pd,
     mihs_solve_pd_dual, mihs_transpose, MIHSRidge, momentum,

@@ -115,6 +115,8 @@ _SIGS = {
     "mihs_batched_plan_create": (_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl,
                                         _i64, _i64, _vp, _vp, _sz, _vp, ctypes.POINTER(_vp)]),
     "mihs_batched_plan_run": (_int, [_vp, _vp]),
+    "mihs_batched_schedule": (_int, [ctypes.c_int32, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp,
+                                     _vp]),
     "mihs_batched_plan_destroy": (_int, [_vp]),
     "mihs_tune_batched": (_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl, _i64,
                                  _i64, _i64, _vp, _sz, _vp, _vp, _vp, _vp]),
@@ -572,6 +574,32 @@ def mihs_solve_batched(problems, lambdas: torch.Tensor, alphas: torch.Tensor,
         return xs, infos, (keep, ws)
     torch.cuda.synchronize(dev)
     return xs, [info_to_dict(t) for t in infos]
+
+
+def batched_schedule(shapes, nlam: int, num_cu: int, tuning: Optional[dict] = None,
+                     cost=None) -> dict:
+    """The batched launch's schedule for problems of the given (n, d) shapes on
+    num_cu workgroups, computed on the host (no device): team0, tsize, tcg per
+    entry (problem-major, one entry per 16 lambdas)."""
+    lib = load_library()
+    nprob = len(shapes)
+    n = (ctypes.c_int64 * nprob)(*[int(s[0]) for s in shapes])
+    d = (ctypes.c_int64 * nprob)(*[int(s[1]) for s in shapes])
+    tn = Tuning()
+    lib.mihs_batched_default_tuning(ctypes.byref(tn))
+    if tuning is not None:
+        tn = Tuning(int(tuning["cg_cols"]), int(tuning["a_dma"]), float(tuning["inner_weight"]),
+                    int(tuning.get("measured", 0)), 0)
+    count = nprob * ((nlam + 15) // 16)
+    c = None
+    if cost is not None:
+        if len(cost) != count:
+            raise MihsError(f"cost needs {count} values")
+        c = (ctypes.c_double * count)(*[float(v) for v in cost])
+    t0, ts, tc = ((ctypes.c_int32 * count)() for _ in range(3))
+    _check(lib.mihs_batched_schedule(int(num_cu), n, d, nprob, int(nlam), ctypes.byref(tn), c,
+                                     t0, ts, tc), "mihs_batched_schedule")
+    return {"team0": list(t0), "tsize": list(ts), "tcg": list(tc)}
 
 
 def sketch_workspace_bytes(n: int, d: int, m: int, kind: str, precision: str = "plain",

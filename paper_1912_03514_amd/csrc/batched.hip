@@ -1595,6 +1595,40 @@ int launch_block(mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int 
 
 }  // namespace mihs
 
+extern "C" int mihs_batched_schedule(int32_t num_cu, const int64_t* n, const int64_t* d,
+                                     int64_t nprob, int64_t nlam,
+                                     const mihs_batched_tuning_t* tuning, const double* cost,
+                                     int32_t* team0, int32_t* tsize, int32_t* tcg) {
+  if (num_cu < 1 || !n || !d || nprob < 1 || nlam < 1 || !tuning || !team0 || !tsize || !tcg)
+    return MIHS_ERR_INVALID;
+  if (!mihs::block_tuning_valid(*tuning)) return MIHS_ERR_INVALID;
+  std::vector<mihs::BlockEntryDesc> ents;
+  for (int64_t p = 0; p < nprob; ++p) {
+    if (n[p] < 1 || d[p] < 1 || n[p] < d[p]) return MIHS_ERR_INVALID;
+    for (int64_t g0 = 0; g0 < nlam; g0 += 16) {
+      mihs::BlockEntryDesc e;
+      memset(&e, 0, sizeof(e));
+      e.n = n[p];
+      e.d = d[p];
+      e.ncols = (int)((nlam - g0) < 16 ? (nlam - g0) : 16);
+      e.sa_group = p;
+      ents.push_back(e);
+    }
+  }
+  const int64_t count = (int64_t)ents.size();
+  std::vector<double> c;
+  if (cost) c.assign(cost, cost + count);
+  mihs::Schedule S;
+  const int rc = mihs::make_schedule(ents.data(), count, num_cu, *tuning, cost ? &c : nullptr, &S);
+  if (rc) return rc;
+  for (int64_t i = 0; i < count; ++i) {
+    team0[i] = S.team0[i];
+    tsize[i] = S.tsize[i];
+    tcg[i] = S.tcg[i];
+  }
+  return MIHS_OK;
+}
+
 extern "C" void mihs_batched_default_tuning(mihs_batched_tuning_t* t) {
   if (!t) return;
   t->cg_cols = 32;

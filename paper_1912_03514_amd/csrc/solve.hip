@@ -419,8 +419,12 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   const int c_hi = in_cg ? min(d, c_lo + cpw) : d;
   const int nown = c_hi - c_lo;
   double* scal_w = a.scal + (int64_t)w * kScal;
-  TV* r = (TV*)a.r;
-  TV* P[2] = {(TV*)a.p0, (TV*)a.p1};
+  // CG vectors in global memory, addressed as such: loads through the generic
+  // address space would also count as LDS traffic, so every LDS wait in the
+  // step would wait for them too
+  typedef TV __attribute__((address_space(1))) gTV;
+  gTV* r = (gTV*)a.r;
+  gTV* P[2] = {(gTV*)a.p0, (gTV*)a.p1};
   TV* partS = (TV*)a.partS;
   const TA* A = (const TA*)a.A;
   const TS* SA = (const TS*)a.SA;
@@ -519,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           // workgroup keeps v in LDS and the same scalars; owners keep the
           // direction vector (in own_r) and the iterate z on their columns.
           TV* vp = (TV*)vbuf;
-          TV* wv = r;  // w, exchanged through the residual buffer
+          gTV* wv = r;  // w, exchanged through the residual buffer
           TV* dv = own_r;
           const double theta1 = sqrt(rr0);
           for (int c = threadIdx.x; c < a.dpad; c += kBlock)
@@ -702,8 +706,8 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           while (true) {
             // ---- C1: p = r + beta_cg p_prev (k > 0), staged in LDS.  The loads of
             // r, p_prev and the residual partials are all issued before use.
-            TV* pcur = P[k & 1];
-            const TV* pprev = P[(k + 1) & 1];
+            gTV* pcur = P[k & 1];
+            const gTV* pprev = P[(k + 1) & 1];
             TV rv[NPT], pv[NPT];
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {

@@ -702,23 +702,25 @@ __device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, 
 // (sub-team of one): every vector stays in the workgroup.  Thread (wave w,
 // lane l) owns rows 16 (4 b + w) + l / 16 + 4 i (i < 4, b < DP / 64) of
 // column j = l % 16 -- the rows of the matrix-core result block it holds -- so
-// r lives in registers, p (the MFMA operand) and z in LDS, q goes to the
-// entry's Q buffer (written and read back by the same thread), and the
+// r and z live in registers, p (the MFMA operand) and q in LDS, and the
 // per-column sums go through two LDS buffers in a fixed order.  Each wave forms
-// whole rows of H p for its own 16-row blocks (no reduction across waves, no
-// barrier inside the product) and skips the blocks and k-chunks at or beyond
-// d, where H is zero; H streams through a ring of register buffers with
-// global-address-space loads (so that they are not counted with the LDS
-// traffic).  Same iteration as cg_solve (step lengths, masks, breakdown and
-// stop rule per column); z ends in the LDS region after p.
+// whole rows of H p for its own 16-row blocks (no reduction across waves) and
+// skips the blocks and k-chunks at or beyond d, where H is zero.  H streams
+// through a ring of register buffers: every load is unconditional (past the
+// last chunk the ring already fetches the next step's first chunks; H does not
+// change between steps), nothing else in the step touches global memory, and
+// the barriers wait for LDS traffic only, so the waits before the products
+// count exactly the chunks still in flight.  Same iteration as cg_solve (step
+// lengths, masks, breakdown and stop rule per column); z ends in the entry's Z
+// buffer.
 template <typename TH, int DP>
 __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict__ H, int64_t ldh,
                                                             int d, const double* __restrict__ R,
-                                                            double* __restrict__ Q, double eps_sub,
+                                                            double* __restrict__ Z, double eps_sub,
                                                             int64_t max_inner) {
   extern __shared__ uint4 lds_raw[];
   double* stage = (double*)lds_raw;      // p, DP x 16
-  double* zl = stage + DP * KR;          // z, DP x 16
+  double* ql = stage + DP * KR;          // q, DP x 16
   double* red0 = (double*)((char*)lds_raw + kUredOffset);
   double* red1 = red0 + kBlock;
   Shared& sh = g_sh;
@@ -729,38 +731,60 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
   constexpr int NV = 4 * NBW;                     // owned entries per vector
   constexpr int VE = 16 / (int)sizeof(TH);        // elements per 16-byte load
   constexpr int KQ = DP / 4;
-  constexpr int NLD = (KQ * (int)sizeof(TH) / 16) < 8 ? KQ * (int)sizeof(TH) / 16 : 8;
+  constexpr int NLD = (KQ * (int)sizeof(TH) / 16) < 4 ? KQ * (int)sizeof(TH) / 16 : 4;
   constexpr int CE = NLD * VE;                    // k elements per lane and chunk
   constexpr int NRING = 4;                        // chunks in flight per lane
   const int lane = lane_id(), wave = wave_id();
   const int j = lane & 15, g = lane >> 4;
   const int tid = (int)threadIdx.x;
-  // active blocks of this wave and k-chunks (a chunk covers k in [c 4 CE, (c+1) 4 CE))
+  // active blocks of this wave and k-chunks (chunk c covers k in [c 4 CE, (c+1) 4 CE))
   const int nbw = d > 16 * wave ? min(NBW, (d - 16 * wave + 63) / 64) : 0;
   const int nch = min(KQ / CE, (d + 4 * CE - 1) / (4 * CE));
+  const int T = nbw * nch;  // chunks of one product, in order t = b nch + c
+  // each step walks Tp positions (T rounded up to whole rings; the extra ones
+  // are dummy reads), so ring slot u always holds a position congruent to u
+  const int Tp = T > 0 ? (T + NRING - 1) / NRING * NRING : 0;
   // element i of a 16 x 16 x 4 FP64 MFMA result is row l / 16 + 4 i, column l % 16
   auto row_of = [&](int v) { return 16 * (4 * (v >> 2) + wave) + g + 4 * (v & 3); };
+  union Chunk {
+    u32x4 u[NLD];
+    TH v[CE];
+  };
+  // the fetch cursor walks the positions of every step in turn; dummy
+  // positions (and a wave with no active block) read row j (valid, cached)
+  int pos = 0, fb = 0, fc = 0;
+  auto fetch = [&](Chunk& dst) {
+    const bool in = pos < T;
+    const int row = in ? 16 * (4 * fb + wave) + j : j;
+    const gvec src = (gvec)(H + (int64_t)row * ldh + (in ? fc : 0) * 4 * CE + g * CE);
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) dst.u[i] = src[i];
+    if (++pos >= Tp) {
+      pos = 0;
+      fb = 0;
+      fc = 0;
+    } else if (++fc == nch) {
+      fc = 0;
+      ++fb;
+    }
+  };
+  Chunk ring[NRING];
+#pragma unroll
+  for (int u = 0; u < NRING; ++u) fetch(ring[u]);
 
-  double r[NV];
+  double r[NV], z[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int row = row_of(v);
-    r[v] = row < d ? ((const double __attribute__((address_space(1)))*)R)[(int64_t)row * KR + j]
-                   : 0.0;
-    zl[row * KR + j] = 0.0;
+    r[v] = row < d ? ((const double __attribute__((address_space(1)))*)R)[row * KR + j] : 0.0;
+    z[v] = 0.0;
   }
   const double lj = sh.lam[j];
   bool act = sh.active[j] != 0;
   double rr = sh.rr[j], bc = 0.0;
   const double rr0 = sh.rr0[j];
   int64_t k = 0, kin = 0;
-  __syncthreads();
 
-  // H rows for the A operand: lane (row l % 16, k-group g) reads 16-byte
-  // chunks of row cb + j at k = c 4 CE + g CE ... (contiguous per lane)
-  auto hptr = [&](int b, int c) -> const u32x4* {
-    return (const u32x4*)(H + (int64_t)(16 * (4 * b + wave) + j) * ldh + c * 4 * CE + g * CE);
-  };
   while (true) {
     int any = 0;
     for (int jj = 0; jj < KR; ++jj) any |= sh.active[jj];
@@ -771,33 +795,14 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
       const int o = row_of(v) * KR + j;
       stage[o] = act ? ((k == 0) ? r[v] : r[v] + bc * stage[o]) : 0.0;
     }
-    __syncthreads();
-    // q = H p + lambda p on the owned rows; chunks stream through a two-deep
-    // register pipeline across block boundaries
+    wait_lgkm0();
+    raw_barrier();
+    // q = H p + lambda p on the owned blocks (into LDS), p . q per column
     double pq = 0.0;
     {
-      // the chunks of the owned blocks in order (t = b nch + c) through a ring of
-      // NRING register buffers: NRING chunks in flight per lane; H is re-read
-      // every step, so it is loaded through the caches
-      union Chunk {
-        u32x4 u[NLD];
-        TH v[CE];
-      };
-      Chunk ring[NRING];
-      const int T = nbw * nch;
-      auto fetch = [&](Chunk& buf, int t) {
-        if (t < T) {
-          const int b = t / nch;
-          const gvec src = (gvec)hptr(b, t - b * nch);
-#pragma unroll
-          for (int i = 0; i < NLD; ++i) buf.u[i] = src[i];
-        }
-      };
-#pragma unroll
-      for (int u = 0; u < NRING; ++u) fetch(ring[u], u);
       f64x4 acc = {0.0, 0.0, 0.0, 0.0};
       int b = 0, c = 0;
-      for (int t0 = 0; t0 < T; t0 += NRING) {
+      for (int t0 = 0; t0 < Tp; t0 += NRING) {
 #pragma unroll
         for (int u = 0; u < NRING; ++u) {
           if (t0 + u < T) {
@@ -806,7 +811,6 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
             for (int e = 0; e < CE; ++e)
               acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ring[u].v[e], pk[e * KR], acc,
                                                          0, 0, 0);
-            fetch(ring[u], t0 + u + NRING);
             if (++c == nch) {
               const int row0 = 16 * (4 * b + wave) + g;
 #pragma unroll
@@ -814,7 +818,7 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
                 const int o = (row0 + 4 * i) * KR + j;
                 const double pv = stage[o];
                 const double qv = acc[i] + lj * pv;
-                ((gdbl)Q)[o] = qv;
+                ql[o] = qv;
                 pq += pv * qv;
               }
               acc = (f64x4){0.0, 0.0, 0.0, 0.0};
@@ -822,11 +826,14 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
               ++b;
             }
           }
+          // the slot's next position (this step's or the next step's)
+          fetch(ring[u]);
         }
       }
     }
     red0[tid] = pq;
-    __syncthreads();
+    wait_lgkm0();
+    raw_barrier();
     double spq = 0.0;
 #pragma unroll
     for (int t = 0; t < 16; ++t) spq += red0[t * 16 + j];
@@ -841,16 +848,17 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
     double rrp = 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int o = row_of(v) * KR + j;
       // rows of blocks this wave skipped (at or beyond d) keep r = 0
       if (act && (v >> 2) < nbw) {
-        zl[o] += al * stage[o];
-        r[v] -= al * ((gdbl)Q)[o];
+        const int o = row_of(v) * KR + j;
+        z[v] += al * stage[o];
+        r[v] -= al * ql[o];
       }
       rrp += r[v] * r[v];
     }
     red1[tid] = rrp;
-    __syncthreads();
+    wait_lgkm0();
+    raw_barrier();
     double rn = 0.0;
 #pragma unroll
     for (int t = 0; t < 16; ++t) rn += red1[t * 16 + j];
@@ -862,9 +870,16 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
       if (rn <= eps_sub * eps_sub * rr0) act = false;
     }
     if (tid < KR) sh.active[tid] = act ? 1 : 0;
-    __syncthreads();
+    wait_lgkm0();
+    raw_barrier();
   }
   if (tid < KR) sh.kin[tid] = kin;
+  // z to the entry's buffer (read by the update with another thread mapping);
+  // the ring's look-ahead loads are waited for before the registers go
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ((gdbl)Z)[row_of(v) * KR + j] = z[v];
+  __builtin_amdgcn_s_waitcnt(0);
+  __threadfence_block();
   __syncthreads();
   return k;
 }
@@ -890,7 +905,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
   double* myscal = scal + (int64_t)rank * kNScal;
   double* stage = (double*)tile;  // d x 16 vectors (row-major = MFMA B-operand order)
   const bool cg = rank < Tc;
-  // a one-workgroup CG keeps p and r in LDS (2 x DP x 16 doubles within the
+  // a one-workgroup CG keeps p and q in LDS (2 x DP x 16 doubles within the
   // tile region)
   const bool local_cg = Tc == 1 && 2 * (size_t)DP * KR * sizeof(double) <= kUredOffset;
   // CG members own 16-aligned column ranges of R, Z, Q, XP and X
@@ -990,9 +1005,9 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       // sub-team is one workgroup, else on the team
       int64_t k;
       if (local_cg)
-        k = a.h_f32 ? cg_solve_local<float, DP>((const float*)e.H, e.ldh, d, R, Q, a.eps_sub,
+        k = a.h_f32 ? cg_solve_local<float, DP>((const float*)e.H, e.ldh, d, R, Z, a.eps_sub,
                                                 a.max_inner)
-                    : cg_solve_local<double, DP>((const double*)e.H, e.ldh, d, R, Q, a.eps_sub,
+                    : cg_solve_local<double, DP>((const double*)e.H, e.ldh, d, R, Z, a.eps_sub,
                                                  a.max_inner);
       else
         k = a.h_f32 ? cg_solve<float, DP>((const float*)e.H, e.ldh, d, c_lo, c_hi, R, Z, Q, scal,
@@ -1013,7 +1028,6 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       }
 
       // ---- heavy-ball update per column (owners) and relative-step partials
-      const double* Zsrc = local_cg ? (const double*)tile + DP * KR : Z;
       double s0 = 0.0, s1 = 0.0;
       for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
         const int c = c_lo + idx / KR, j = idx % KR;
@@ -1021,7 +1035,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
         const int64_t o = (int64_t)c * KR + j;
         double* xp = e.X + (int64_t)c * e.ldx + j;
         const double xc = *xp;
-        const double xn = xc + sh.alpha[j] * Zsrc[o] + sh.beta[j] * (xc - XP[o]);
+        const double xn = xc + sh.alpha[j] * Z[o] + sh.beta[j] * (xc - XP[o]);
         XP[o] = xc;
         *xp = xn;
         s0 += (xn - xc) * (xn - xc);

@@ -363,8 +363,9 @@ int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
  * Tunable shape of the batched launch (not in the paper; the schedule and the
  * tiling of the one persistent launch above).
  *   cg_cols       columns of the Gram matrix owned by one workgroup of a
- *                 problem's inner-CG sub-team (16, 32 or 64): the sub-team has
- *                 ceil(d / cg_cols) members, at most the problem's team;
+ *                 problem's inner-CG sub-team (16, 32, 64 or 512): the sub-team
+ *                 has ceil(d / cg_cols) members, at most the problem's team (512:
+ *                 for d <= 512 the inner CG runs inside one workgroup);
  *   a_dma         1: each pass over A moves 64 KiB groups of rows straight
  *                 into LDS (rows of 1-4 KiB); 0: 16-row tiles staged through
  *                 registers;
@@ -424,7 +425,7 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
  * Autotuner of the batched launch shape.  Times trial solves of the given
  * problems (each from X = 0, at most trial_outer outer iterations, HIP events
  * on `stream`) over candidate shapes by coordinate descent: inner_weight in
- * {6.25, 25, 100, 400}, then cg_cols in {16, 32, 64}, then a_dma in {1, 0}.
+ * {6.25, 25, 100, 400}, then cg_cols in {16, 32, 64, 512}, then a_dma in {1, 0}.
  * If measure_outer > 0 it then runs the best shape for up to measure_outer
  * outer iterations (normally the solve's own limit, so that every problem
  * runs to its stop), reads the wall time of every problem

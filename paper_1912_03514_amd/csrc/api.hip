@@ -797,7 +797,7 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
     }
   }
   mihs_batched_tuning_t base = cur;
-  const int cols[] = {16, 64};
+  const int cols[] = {16, 64, 512};
   for (int c : cols) {
     if (rc) break;
     mihs_batched_tuning_t t = base;

@@ -58,6 +58,7 @@ def _check_closed_form(xs, infos, refs, tol=1e-10):
     {"cg_cols": 16, "a_dma": 0, "inner_weight": 25.0},
     {"cg_cols": 64, "a_dma": 1, "inner_weight": 400.0},
     {"cg_cols": 32, "a_dma": 0, "inner_weight": 400.0},
+    {"cg_cols": 512, "a_dma": 1, "inner_weight": 6.25},
 ])
 def test_every_launch_shape_reaches_the_closed_form(problem_set, tuning):
     """Each candidate shape of the autotuner (CG sub-team width, the A pass
@@ -106,7 +107,7 @@ def test_graph_replays_match_the_eager_run(problem_set):
 
 
 def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
-    """mihs_tune_batched times seven candidate shapes by coordinate descent, a
+    """mihs_tune_batched times eight candidate shapes by coordinate descent, a
     full run of the best and a schedule sized from its per-problem costs,
     and keeps the best for this problem set: the plain batched call afterwards
     (which looks the shape up) still reaches the closed form, and so does a plan
@@ -118,9 +119,9 @@ def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
     announce("batched autotuner")
     res = s.tune(trial_outer=3)
     best = res["best"]
-    assert len(res["trial_ms"]) == 9
+    assert len(res["trial_ms"]) == 10
     assert all(t > 0 for t in res["trial_ms"])
-    assert best["cg_cols"] in (16, 32, 64) and best["a_dma"] in (0, 1)
+    assert best["cg_cols"] in (16, 32, 64, 512) and best["a_dma"] in (0, 1)
     assert best["inner_weight"] in (6.25, 25.0, 100.0, 400.0)
     assert best["measured"] in (0, 1)
     s.run()

@@ -120,13 +120,16 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, int size, unsigned& ep
   return barrier_flat(bar, epoch, (unsigned)size, err, s_flag, spin);
 }
 
-// Sum over the first T slots: out[j] = sum_t scal[t * kNScal + s0 + j], j < KR.
+// Sum over the first T slots: out[j] = sum_t scal[t * kNScal + s0 + j], j < KR
+// (scal in global memory, out and red in LDS).
 __device__ __forceinline__ void team_slot_sums(const double* scal, int T, int s0, double* out,
                                                double* red) {
   // thread (j, q) with j = tid % 16 sums t = q, q + 16, ... ; fixed tree over q
+  const double __attribute__((address_space(1)))* gs =
+      (const double __attribute__((address_space(1)))*)scal;
   const int j = threadIdx.x % KR, q = threadIdx.x / KR;
   double v = 0.0;
-  for (int t = q; t < T; t += kBlock / KR) v += scal[(int64_t)t * kNScal + s0 + j];
+  for (int t = q; t < T; t += kBlock / KR) v += gs[(int64_t)t * kNScal + s0 + j];
   __syncthreads();
   red[threadIdx.x] = v;
   __syncthreads();
@@ -138,7 +141,8 @@ __device__ __forceinline__ void team_slot_sums(const double* scal, int T, int s0
   __syncthreads();
 }
 
-// Per-column sums of values held by all threads (thread tid owns column tid % 16).
+// Per-column sums of values held by all threads (thread tid owns column tid % 16),
+// into the global slots `out`.
 __device__ __forceinline__ void column_partials(double v, double* out, double* red) {
   __syncthreads();
   red[threadIdx.x] = v;
@@ -146,7 +150,7 @@ __device__ __forceinline__ void column_partials(double v, double* out, double* r
   if (threadIdx.x < KR) {
     double a = red[threadIdx.x];
     for (int i = 1; i < kBlock / KR; ++i) a += red[i * KR + threadIdx.x];
-    out[threadIdx.x] = a;
+    ((double __attribute__((address_space(1)))*)out)[threadIdx.x] = a;
   }
   __syncthreads();
 }
@@ -567,7 +571,7 @@ __device__ __forceinline__ double h_matvec(const TH* __restrict__ H, int64_t ldh
           u32x4 u;
           TH v[VE];
         } x;
-        x.u = *(const u32x4*)(hrow + i * VE);
+        x.u = *(const u32x4 __attribute__((address_space(1)))*)(hrow + i * VE);
 #pragma unroll
         for (int e = 0; e < VE; ++e) hv[i * VE + e] = x.v[e];
       }
@@ -594,7 +598,7 @@ __device__ __forceinline__ double h_matvec(const TH* __restrict__ H, int64_t ldh
       for (int w = 0; w < kWavesPerBlock; ++w) qv += ured[w * TROWS * KR + rr * KR + j];
       const double pv = stage[c * KR + j];
       qv += lj * pv;
-      Q[(int64_t)c * KR + j] = qv;
+      ((double __attribute__((address_space(1)))*)Q)[(int64_t)c * KR + j] = qv;
       pq += pv * qv;
     }
     __syncthreads();
@@ -617,13 +621,16 @@ __device__ __forceinline__ double h_matvec(const TH* __restrict__ H, int64_t ldh
 // out; the caller advances its barrier epoch by two per step.
 template <typename TH, int DP>
 __device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, int64_t ldh, int d,
-                                                      int c_lo, int c_hi, double* R, double* Z,
-                                                      double* Q, const double* scal,
+                                                      int c_lo, int c_hi, double* Rp, double* Zp,
+                                                      double* Qp, const double* scal,
                                                       double* myscal, int Tc, unsigned* bar_cg,
                                                       unsigned epoch, int* err, BarrierSpin spin,
                                                       double eps_sub, int64_t max_inner) {
   extern __shared__ uint4 lds_raw[];
   double* stage = (double*)lds_raw;
+  // the entry's vectors, addressed as global memory (not counted with LDS traffic)
+  typedef double __attribute__((address_space(1)))* gdbl;
+  const gdbl R = (gdbl)Rp, Z = (gdbl)Zp, Q = (gdbl)Qp;
   Shared& sh = g_sh;
   const int nown = c_hi - c_lo;
   int64_t k = 0;
@@ -648,7 +655,7 @@ __device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, 
     }
     __syncthreads();
     // q = H p + lambda p on the owned 16-column blocks
-    const double pq_lane = h_matvec<TH, DP>(H, ldh, c_lo, c_hi, sh.lam, Q);
+    const double pq_lane = h_matvec<TH, DP>(H, ldh, c_lo, c_hi, sh.lam, Qp);
     column_partials(pq_lane, myscal + KR, sh.red);
     if (!group_sync(bar_cg, Tc, epoch, err, &sh.flag, spin)) return -1;
     team_slot_sums(scal, Tc, KR, sh.ufin, sh.red);  // ufin[0..15] <- p_j^T q_j

@@ -443,17 +443,26 @@ __device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t
       const TM* tile = tileg + t * TROWS * C::LDT;
       const int64_t gr = row0 + t * TROWS + rr;
       f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-      // (dqe is a multiple of 16: groups of four k-steps are all in or all out)
+      // (dqe is a multiple of 16: groups of four k-steps are all in or all out).
+      // Software pipeline: the tile values of group q + 1 are read from LDS
+      // (unconditionally: the tile row is DP wide) before the products of
+      // group q, so each group waits only for reads issued one group earlier.
+      const TM* arow = tile + (lane & 15) * C::LDT + kbase + (lane >> 4);
+      double abuf[2][4];
 #pragma unroll
-      for (int s4 = 0; s4 < KS; s4 += 4) {
-        if (4 * s4 < dqe) {
+      for (int i = 0; i < 4; ++i) abuf[0][i] = (double)arow[4 * i];
 #pragma unroll
-          for (int s = s4; s < s4 + 4; ++s) {
-            const double a = (double)tile[(lane & 15) * C::LDT + kbase + 4 * s + (lane >> 4)];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Vreg[s], acc, 0, 0, 0);
-          }
+      for (int q = 0; q < KS / 4; ++q) {
+        if (q + 1 < KS / 4) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) abuf[(q + 1) & 1][i] = (double)arow[4 * (4 * (q + 1) + i)];
         }
-        if ((s4 & 7) == 4) __builtin_amdgcn_sched_barrier(0);
+        if (16 * q < dqe) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(abuf[q & 1][i], Vreg[4 * q + i], acc, 0,
+                                                       0, 0);
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -468,16 +477,28 @@ __device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t
       }
       wait_lgkm0();
       raw_barrier();
+      // G += tile^T U: the U operand is the same for every block b (read once);
+      // the tile values of block b + 1 are read before the products of block b
+      double bvu[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bvu[s] = ufin[(4 * s + (lane >> 4)) * KR + (lane & 15)];
+      const TM* gcol = tile + (lane >> 4) * C::LDT + kbase + (lane & 15);
+      double gbuf[2][4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) gbuf[0][s] = (double)gcol[4 * s * C::LDT];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
+        if (b + 1 < NB) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int r2 = 4 * s + (lane >> 4);
-          const double a = (double)tile[r2 * C::LDT + kbase + 16 * b + (lane & 15)];
-          const double bv = ufin[r2 * KR + (lane & 15)];
-          if (16 * b < dqe) Gacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, Gacc[b], 0, 0, 0);
+          for (int s = 0; s < 4; ++s)
+            gbuf[(b + 1) & 1][s] = (double)gcol[4 * s * C::LDT + 16 * (b + 1)];
         }
-        if ((b & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        if (16 * b < dqe) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            Gacc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(gbuf[b & 1][s], bvu[s], Gacc[b], 0, 0,
+                                                           0);
+        }
       }
       wait_lgkm0();
       raw_barrier();  // ured / ufin (and after the last tile, this buffer) free again

@@ -145,3 +145,49 @@ def test_plan_rejects_bad_tuning(problem_set):
     with pytest.raises(mihs.MihsError):
         mihs.BatchedSolver(dp, L, Al, Be, tuning={"cg_cols": 48, "a_dma": 1,
                                                   "inner_weight": 100.0})
+
+
+def test_measured_schedule_with_more_entries_than_workgroups():
+    """600 entries (300 small problems x 20 lambdas, i.e. two column groups each)
+    on the GPU's workgroups: the tuner's measured schedule packs many entries per
+    bin; after tuning, a graph replay of the plan reaches the closed form on a
+    sample of problems and lambdas."""
+    mihs = _mihs()
+    rng = np.random.default_rng(11)
+    nlam = 20
+    problems, L, Al, Be, refs = [], [], [], [], {}
+    for i in range(300):
+        d = int(rng.integers(8, 96))
+        n = int(rng.integers(max(d, 200), 900))
+        sig = W.sigma_profile("exp", d, 6.0)
+        P = W.make_problem(n, d, sig, max(1.0, d / 4), 900 + i)
+        m = min(n, 4 * d)
+        SA = sketches.gaussian_sketch(P.A, m, 40 + i)
+        s1 = float(sig[0]) ** 2
+        lams = s1 * 10.0 ** (-6.0 + 5.0 * np.arange(nlam) / (nlam - 1))
+        sds = np.array([W.nominal_sd(sig, float(l)) for l in lams])
+        betas = np.minimum(sds / m, 0.95)
+        problems.append((to_dev(P.A), to_dev(P.b), to_dev(SA)))
+        L.append(lams)
+        Al.append((1.0 - betas) ** 2)
+        Be.append(betas)
+        if i % 37 == 0:
+            refs[i] = (P, lams)
+    s = mihs.BatchedSolver(problems, to_dev(np.array(L)), to_dev(np.array(Al)),
+                           to_dev(np.array(Be)), eps_sub=1e-2, tol=1e-12, max_outer=800,
+                           max_inner=2000)
+    announce("batched 300 problems: tuner with measured schedule")
+    res = s.tune(trial_outer=3)
+    assert len(res["trial_ms"]) == 10
+    g = s.capture()
+    s.X_all.fill_(float("nan"))
+    torch.cuda.synchronize()
+    announce("batched 300 problems: graph replay")
+    g.replay()
+    torch.cuda.synchronize()
+    infos = s.infos()
+    for i, (P, lams) in refs.items():
+        X = s.xs[i].cpu().numpy()
+        for j in (0, 9, 19):
+            assert infos[i][j]["status"] == 0, (i, j, infos[i][j])
+            assert rel(X[:, j], O.ridge_lstsq(P.A, P.b, float(lams[j]))) <= 1e-10, (i, j)

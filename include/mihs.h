@@ -372,7 +372,8 @@ int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
  *   inner_weight  the expected inner-CG cost per outer iteration, in passes
  *                 over H per column group, used to size the teams (team size
  *                 proportional to n d + inner_weight d^2; 1 to 10000).
- * mihs_batched_default_tuning() fills the defaults (32, 1, 100, measured 0).
+ * mihs_batched_default_tuning() fills the defaults (32, 1, 100, measured 0,
+ * exact 0).
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t cg_cols;
@@ -382,7 +383,16 @@ typedef struct {
                         mihs_tune_batched measured on an equal problem set
                         (inner_weight unused); without such a measurement the
                         model above is used */
-  int32_t reserved;  /* 0 */
+  int32_t exact;     /* 1: solve the sub-problem of every outer step exactly
+                        (Exact M-IHS, the variant of the experiments in
+                        Section 5 that factorizes the sketched system): one
+                        FP64 Cholesky factor of (SA)^T SA + lambda_j I per
+                        column, formed in the launch before the solve, then a
+                        forward and a backward substitution per outer step
+                        (inner_iters counts 1 per outer step; cg_cols unused).
+                        A column whose factorization meets a non-positive
+                        pivot makes its problem use the inexact CG instead.
+                        0: the inexact inner CG to eps_sub */
 } mihs_batched_tuning_t;
 
 void mihs_batched_default_tuning(mihs_batched_tuning_t* tuning);
@@ -425,12 +435,15 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
  * Autotuner of the batched launch shape.  Times trial solves of the given
  * problems (each from X = 0, at most trial_outer outer iterations, HIP events
  * on `stream`) over candidate shapes by coordinate descent: inner_weight in
- * {6.25, 25, 100, 400}, then cg_cols in {16, 32, 64, 512}, then a_dma in {1, 0}.
- * If measure_outer > 0 it then runs the best shape for up to measure_outer
- * outer iterations (normally the solve's own limit, so that every problem
- * runs to its stop), reads the wall time of every problem
- * (mihs_info_t.elapsed_us), takes time x team size as the problem's cost on
- * one workgroup, and runs a schedule sized from those costs (teams of
+ * {6.25, 25, 100, 400}, then cg_cols in {16, 32, 64, 512}, then a_dma in {1, 0},
+ * then exact = 1 with inner_weight in {6.25, 25} (the best exact shape is kept
+ * apart: short trials charge its factorizations to few outer iterations).
+ * If measure_outer > 0 it then runs the best inexact and the best exact shape
+ * for up to measure_outer outer iterations each (normally the solve's own
+ * limit, so that every problem runs to its stop), keeps the faster, reads the
+ * wall time of every problem in that run (mihs_info_t.elapsed_us), takes time
+ * x team size as the problem's cost on one workgroup, and runs a schedule
+ * sized from those costs (teams of
  * ceil(cost / L) workgroups for problems above a makespan L, first-fit bins
  * of capacity L for the rest, the smallest L that fits) for as long;
  * measured = 1 in *best if that one was faster.  The best

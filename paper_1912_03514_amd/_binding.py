@@ -48,11 +48,11 @@ INFO_BYTES = ctypes.sizeof(Info)  # 48
 class Tuning(ctypes.Structure):
     _fields_ = [("cg_cols", ctypes.c_int32), ("a_dma", ctypes.c_int32),
                 ("inner_weight", ctypes.c_double), ("measured", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("exact", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"cg_cols": self.cg_cols, "a_dma": self.a_dma, "inner_weight": self.inner_weight,
-                "measured": self.measured}
+                "measured": self.measured, "exact": self.exact}
 
 
 TUNE_MAX_CANDIDATES = 16
@@ -589,7 +589,7 @@ def batched_schedule(shapes, nlam: int, num_cu: int, tuning: Optional[dict] = No
     lib.mihs_batched_default_tuning(ctypes.byref(tn))
     if tuning is not None:
         tn = Tuning(int(tuning["cg_cols"]), int(tuning["a_dma"]), float(tuning["inner_weight"]),
-                    int(tuning.get("measured", 0)), 0)
+                    int(tuning.get("measured", 0)), int(tuning.get("exact", 0)))
     count = nprob * ((nlam + 15) // 16)
     c = None
     if cost is not None:
@@ -683,7 +683,7 @@ class BatchedSolver:
         tn = None
         if tuning is not None:
             tn = Tuning(int(tuning["cg_cols"]), int(tuning["a_dma"]), float(tuning["inner_weight"]),
-                        int(tuning.get("measured", 0)), 0)
+                        int(tuning.get("measured", 0)), int(tuning.get("exact", 0)))
         eps_sub, tol, max_outer, max_inner = self.params
         plan = _vp()
         _check(lib.mihs_batched_plan_create(
@@ -697,8 +697,10 @@ class BatchedSolver:
     def tune(self, trial_outer: int = 8, measure: bool = True) -> dict:
         """Autotune the launch shape on these problems (blocking; overwrites X)
         and re-plan with the choice: coordinate descent on trial_outer-iteration
-        trials, then (measure) a schedule sized from per-problem times of a full
-        run.  Returns the choice and the trial times."""
+        trials (inexact CG shapes, then exact Cholesky sub-solves), then
+        (measure) full runs of the best of each kind and a schedule sized from
+        the faster one's per-problem times.  Returns the choice and the trial
+        times."""
         lib = load_library()
         eps_sub, tol, max_outer, max_inner = self.params
         best = Tuning()

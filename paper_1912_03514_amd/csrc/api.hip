@@ -819,23 +819,58 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
       cur_ms = ms;
     }
   }
-  // measured costs: every entry's wall time in a run of the best shape times
-  // its team size, then a schedule sized from them, run for as long
+  // exact sub-solves (one Cholesky factor per column, formed in the launch),
+  // teams sized for a sub-solve worth a few to a few tens of passes over H;
+  // the short trials charge the factorizations to few outer iterations, so
+  // the best exact shape is kept apart and compared over full runs below
+  mihs_batched_tuning_t ex = cur;
+  float ex_ms = 0.0f;
+  const double exact_weights[] = {6.25, 25.0};
+  for (int wi = 0; wi < 2 && !rc; ++wi) {
+    mihs_batched_tuning_t t = cur;
+    t.exact = 1;
+    t.inner_weight = exact_weights[wi];
+    float ms = 0.0f;
+    rc = trial(t, &ms);
+    if (!rc && (wi == 0 || ms < ex_ms)) {
+      ex = t;
+      ex_ms = ms;
+    }
+  }
+  if (!rc && measure_outer == 0 && ex_ms < cur_ms) {
+    cur = ex;
+    cur_ms = ex_ms;
+  }
+  // measured costs: every entry's wall time in a full run times its team
+  // size.  The best inexact and the best exact shape both run; the faster
+  // one's costs then size a schedule, run for as long.
   std::vector<double> cost;
   if (!rc && measure_outer > 0) {
-    std::vector<int> tsz;
-    float ms = 0.0f;
-    rc = mihs::block_team_sizes(handle, ents.data(), count, cur, nullptr, &tsz);
-    if (!rc) rc = trial(cur, &cur_ms, nullptr, measure_outer);
-    if (!rc) {
-      cost.resize(count);
+    auto full_run = [&](const mihs_batched_tuning_t& tn, float* ms,
+                        std::vector<double>* c) -> int {
+      std::vector<int> tsz;
+      int r = mihs::block_team_sizes(handle, ents.data(), count, tn, nullptr, &tsz);
+      if (!r) r = trial(tn, ms, nullptr, measure_outer);
+      if (r) return r;
+      c->resize(count);
       for (int64_t i = 0; i < count; ++i) {
         mihs_info_t rec;
-        if (hipMemcpy(&rec, ents[i].info, sizeof(rec), hipMemcpyDeviceToHost) != hipSuccess) {
-          rc = MIHS_ERR_HIP;
-          break;
-        }
-        cost[i] = (double)rec.elapsed_us * tsz[i];
+        if (hipMemcpy(&rec, ents[i].info, sizeof(rec), hipMemcpyDeviceToHost) != hipSuccess)
+          return MIHS_ERR_HIP;
+        (*c)[i] = (double)rec.elapsed_us * tsz[i];
+      }
+      return MIHS_OK;
+    };
+    float ms = 0.0f;
+    rc = full_run(cur, &cur_ms, &cost);
+    if (!rc) {
+      std::vector<double> ex_cost;
+      float full_ex = 0.0f;
+      rc = full_run(ex, &full_ex, &ex_cost);
+      if (!rc && full_ex < cur_ms) {
+        cur = ex;
+        cur_ms = full_ex;
+        cost.swap(ex_cost);
       }
     }
     if (!rc) {

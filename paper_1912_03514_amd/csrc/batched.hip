@@ -58,6 +58,8 @@ struct BatchEntry {
   const double* beta;
   mihs_info_t* info;  // ncols records
   double* work;       // per-entry scratch (see entry_layout)
+  double* fac;        // exact sub-solves: ncols Cholesky factors, dp x dp each (or null)
+  int* fac_bad;       // set when a factorization met a non-positive pivot
   unsigned* bar;      // team barrier counter (own 128-byte line)
   unsigned* bar_cg;   // CG sub-team barrier counter (own 128-byte line)
   int d, dp, ncols;
@@ -71,6 +73,7 @@ struct BatchArgs {
   int* err;
   int a_f32, h_f32;
   int a_dma;     // 1: direct-to-LDS row groups where rows are 1-4 KiB
+  int exact;     // 1: exact sub-solves with the entries' Cholesky factors
   int wall_khz;  // rate of wall_clock64()
   double eps_sub, tol;
   int64_t max_outer, max_inner;
@@ -912,6 +915,110 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
   return k;
 }
 
+// Partial dot product of one factor row with the solved vector over the
+// 16-column blocks [m0, m1): this lane's k slot g covers k = 16 m + 4 g + 0..3.
+// Four blocks per step with separate sums keep eight 16-byte loads in flight.
+__device__ __forceinline__ double row_dot(const double* __restrict__ Fr,
+                                          const double* __restrict__ y, int m0, int m1, int g) {
+  typedef double dbl2 __attribute__((ext_vector_type(2)));
+  typedef const dbl2 __attribute__((address_space(1)))* gd2;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int m = m0;
+  for (; m + 4 <= m1; m += 4) {
+    dbl2 f[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k0 = 16 * (m + u) + 4 * g;
+      f[u][0] = ((gd2)(Fr + k0))[0];
+      f[u][1] = ((gd2)(Fr + k0))[1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k0 = 16 * (m + u) + 4 * g;
+      s[u] += f[u][0].x * y[k0] + f[u][0].y * y[k0 + 1] + f[u][1].x * y[k0 + 2] +
+              f[u][1].y * y[k0 + 3];
+    }
+  }
+  for (; m < m1; ++m) {
+    const int k0 = 16 * m + 4 * g;
+    const dbl2 f0 = ((gd2)(Fr + k0))[0], f1 = ((gd2)(Fr + k0))[1];
+    s[0] += f0.x * y[k0] + f0.y * y[k0 + 1] + f1.x * y[k0 + 2] + f1.y * y[k0 + 3];
+  }
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+// Sum over the four k slots (lanes r, r + 16, r + 32, r + 48).
+__device__ __forceinline__ double slot_sum(double s) {
+  s += __shfl_xor(s, 16);
+  return s + __shfl_xor(s, 32);
+}
+
+// Exact sub-solve of one outer step (Exact M-IHS, Section 5): for every active
+// column j, z_j = (L_j L_j^T)^{-1} r_j with the column's Cholesky factor F_j
+// (L_j in the lower triangle, L_j^T mirrored into the upper one, zero at
+// indices >= d).  Wave w takes columns w, w + 4, ...; the column's vector lives
+// in the wave's slice of LDS.  Both substitutions run by 16-row blocks, each
+// block first taking the dot products of its rows with the already solved part
+// (lane = row + 16 k-slot, four consecutive k per lane and 16-column step,
+// summed over the four slots), then solving its 16 x 16 diagonal block in
+// registers, one shuffle per column.
+template <int DP>
+__device__ __attribute__((noinline)) void tri_solve_local(const double* __restrict__ Fb,
+                                                          int64_t ld, int d,
+                                                          const double* __restrict__ R,
+                                                          double* __restrict__ Z) {
+  extern __shared__ uint4 lds_raw[];
+  Shared& sh = g_sh;
+  const int lane = lane_id(), wave = wave_id();
+  const int r = lane & 15, g = lane >> 4;
+  double* y = (double*)lds_raw + wave * DP;
+  const int nb = (d + 15) / 16;
+  for (int j = wave; j < KR; j += kWavesPerBlock) {
+    if (!sh.active[j]) continue;
+    const double* F = Fb + (int64_t)j * ld * ld;
+    for (int k = lane; k < DP; k += kWave) y[k] = k < d ? R[(int64_t)k * KR + j] : 0.0;
+    // forward substitution L u = r (u overwrites y block by block)
+    for (int I = 0; I < nb; ++I) {
+      const int row = 16 * I + r;
+      const double* Fr = F + (int64_t)(row < d ? row : 0) * ld;
+      const double s = slot_sum(row < d ? row_dot(Fr, y, 0, I, g) : 0.0);
+      double dr[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) dr[c] = 16 * I + c < d ? Fr[16 * I + c] : 1.0;
+      double x = row < d ? y[row] - s : 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (16 * I + c < d) {
+          if (r == c) x /= dr[c];
+          const double xc = __shfl(x, c);
+          if (r > c) x -= dr[c] * xc;
+        }
+      if (g == 0 && row < d) y[row] = x;
+    }
+    // backward substitution L^T z = u, reading the rows of L^T
+    for (int I = nb - 1; I >= 0; --I) {
+      const int row = 16 * I + r;
+      const double* Fr = F + (int64_t)(row < d ? row : 0) * ld;
+      const double s = slot_sum(row < d ? row_dot(Fr, y, I + 1, nb, g) : 0.0);
+      double dr[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) dr[c] = 16 * I + c < d ? Fr[16 * I + c] : 1.0;
+      double x = row < d ? y[row] - s : 0.0;
+#pragma unroll
+      for (int c = 15; c >= 0; --c)
+        if (16 * I + c < d) {
+          if (r == c) x /= dr[c];
+          const double xc = __shfl(x, c);
+          if (r < c) x -= dr[c] * xc;
+        }
+      if (g == 0 && row < d) y[row] = x;
+    }
+    for (int k = lane; k < d; k += kWave) Z[(int64_t)k * KR + j] = y[k];
+  }
+  if (threadIdx.x < KR) sh.kin[threadIdx.x] = sh.active[threadIdx.x] ? 1 : 0;
+  __threadfence_block();
+  __syncthreads();
+}
+
 template <int DP>
 __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, void* tile,
                           Shared& sh) {
@@ -1032,7 +1139,10 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       // ---- lockstep CG on (H + lambda_j I): in the workgroup when the CG
       // sub-team is one workgroup, else on the team
       int64_t k;
-      if (local_cg)
+      if (a.exact && e.fac && !*(volatile int*)e.fac_bad) {
+        tri_solve_local<DP>(e.fac, e.dp, d, R, Z);
+        k = 1;
+      } else if (local_cg)
         k = a.h_f32 ? cg_solve_local<float, DP>((const float*)e.H, e.ldh, d, R, Z, a.eps_sub,
                                                 a.max_inner)
                     : cg_solve_local<double, DP>((const double*)e.H, e.ldh, d, R, Z, a.eps_sub,
@@ -1157,7 +1267,7 @@ int block_max_d() { return 1024; }
 bool block_tuning_valid(const mihs_batched_tuning_t& t) {
   return (t.cg_cols == 16 || t.cg_cols == 32 || t.cg_cols == 64 || t.cg_cols == 512) &&
          (t.a_dma == 0 || t.a_dma == 1) && t.inner_weight >= 1.0 && t.inner_weight <= 1e4 &&
-         (t.measured == 0 || t.measured == 1);
+         (t.measured == 0 || t.measured == 1) && (t.exact == 0 || t.exact == 1);
 }
 
 namespace {
@@ -1238,7 +1348,7 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
     }
     *S = T;
     for (int64_t i = 0; i < count; ++i)
-      S->tcg[i] = std::max(
+      S->tcg[i] = tn.exact ? 1 : std::max(
           1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
     S->stride = 1;
     for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
@@ -1296,8 +1406,9 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
     load[best] += wgt[i];
   }
   // CG sub-team: about cg_cols columns of H per member, at most the whole team
+  // (exact sub-solves: the team's first workgroup)
   for (int64_t i = 0; i < count; ++i)
-    S->tcg[i] = std::max(
+    S->tcg[i] = tn.exact ? 1 : std::max(
         1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
   S->stride = 1;
   for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
@@ -1321,12 +1432,13 @@ std::vector<int64_t> group_leaders(const BlockEntryDesc* ents, int64_t count) {
 
 struct BlockLayout {
   size_t ent_off, item_off, gram_off, bar_off, total;
-  std::vector<size_t> work_off, h_off;
+  std::vector<size_t> work_off, h_off, fac_off;  // fac_off empty without exact sub-solves
   std::vector<int> ngram;  // gram jobs per group
   size_t njobs;
 };
 
-BlockLayout block_layout(const BlockEntryDesc* ents, int64_t count, const Schedule& S, int G) {
+BlockLayout block_layout(const BlockEntryDesc* ents, int64_t count, const Schedule& S, int G,
+                         bool exact) {
   BlockLayout L;
   size_t off = 0;
   L.ent_off = off;
@@ -1352,10 +1464,132 @@ BlockLayout block_layout(const BlockEntryDesc* ents, int64_t count, const Schedu
     L.h_off.push_back(off);
     off = align_up(off + dp * dp * sizeof(double), 256);
   }
+  if (exact)
+    for (int64_t i = 0; i < count; ++i) {
+      const size_t dp = (size_t)dp_for(ents[i].d);
+      L.fac_off.push_back(off);
+      off = align_up(off + (size_t)ents[i].ncols * dp * dp * sizeof(double), 256);
+    }
+  // barrier words (two lines per entry, plus the error flag), then one
+  // factorization flag per entry: all cleared by every launch
   L.bar_off = off;
-  off = align_up(off + (size_t)(2 * count + 2) * 128, 256);
+  off = align_up(off + (size_t)(2 * count + 2) * 128 + (size_t)count * sizeof(int), 256);
   L.total = off;
   return L;
+}
+
+// One FP64 Cholesky factor per (entry, column) for the exact sub-solves:
+// L L^T = H + lambda_j I, L in the lower triangle of F (dp x dp), L^T mirrored
+// into the upper triangle, zero at indices >= d.  Right-looking by 16-column
+// panels: the diagonal block is factored in registers of one wave (one
+// shuffle per column pair), the rows below it are solved against it one row
+// per thread and staged in LDS, and the trailing lower triangle is updated in
+// global memory from the staged panel.  A non-positive or non-finite pivot
+// sets the entry's fac_bad word (the solve then uses the inner CG) and the
+// factorization goes on with pivot 1 so that every value stays finite.
+constexpr int kPanel = 16;
+constexpr int kPanelLd = kPanel + 1;  // LDS row pitch (odd: no bank conflicts)
+__host__ __device__ constexpr size_t chol_lds_bytes(int dp) {
+  return ((size_t)dp + kPanel) * kPanelLd * sizeof(double);
+}
+template <typename TH>
+__global__ __launch_bounds__(kBlock) void chol_kernel(const BatchEntry* __restrict__ ents) {
+  extern __shared__ uint4 lds_raw[];
+  const BatchEntry& e = ents[blockIdx.x / KR];
+  const int col = (int)(blockIdx.x % KR);
+  if (col >= e.ncols || !e.fac) return;
+  const int d = e.d, dp = e.dp;
+  const int64_t ld = dp;
+  double* F = e.fac + (int64_t)col * ld * ld;
+  const TH* H = (const TH*)e.H;
+  const double lam = e.lam[col];
+  const int tid = (int)threadIdx.x, lane = lane_id(), wave = wave_id();
+  double* D = (double*)lds_raw;        // diagonal block, kPanel x kPanelLd
+  double* P = D + kPanel * kPanelLd;   // panel rows below it, dp x kPanelLd
+  for (int64_t idx = tid; idx < (int64_t)dp * dp; idx += kBlock) {
+    const int i = (int)(idx / dp), k = (int)(idx % dp);
+    F[idx] = (i < d && k <= i) ? (double)H[(int64_t)i * e.ldh + k] + (i == k ? lam : 0.0) : 0.0;
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int J = 0; J < d; J += kPanel) {
+    const int w = min(kPanel, d - J);
+    if (wave == 0) {
+      // lanes r < 16 hold row J + r of the diagonal block (lanes >= 16 repeat them)
+      const int r = lane & 15;
+      double a[kPanel];
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c)
+        a[c] = (r < w && c <= r) ? F[(int64_t)(J + r) * ld + J + c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c)
+        if (c < w) {
+          double piv = __shfl(a[c], c);
+          if (!(piv > 0.0) || !isfinite(piv)) {
+            bad = true;
+            piv = 1.0;
+          }
+          const double sq = sqrt(piv);
+          if (r == c) a[c] = sq;
+          else if (r > c) a[c] /= sq;
+#pragma unroll
+          for (int cc = c + 1; cc < kPanel; ++cc) {
+            const double lcc = __shfl(a[c], cc);
+            if (r >= cc) a[cc] -= a[c] * lcc;
+          }
+        }
+      if (lane < kPanel) {
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c) {
+          D[r * kPanelLd + c] = (r < w && c <= r) ? a[c] : 0.0;
+          if (r < w && c <= r) F[(int64_t)(J + r) * ld + J + c] = a[c];
+        }
+      }
+    }
+    __syncthreads();
+    // panel: row i below the block solves x D^T = F[i][J .. J + w)
+    const int i0 = J + w, nt = d - i0;
+    for (int i = i0 + tid; i < d; i += kBlock) {
+      double x[kPanel];
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) {
+        if (c < w) {
+          double v = F[(int64_t)i * ld + J + c];
+#pragma unroll
+          for (int t = 0; t < c; ++t) v -= x[t] * D[c * kPanelLd + t];
+          x[c] = v / D[c * kPanelLd + c];
+        } else {
+          x[c] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) {
+        if (c < w) F[(int64_t)i * ld + J + c] = x[c];
+        P[(i - i0) * kPanelLd + c] = x[c];
+      }
+    }
+    __syncthreads();
+    // trailing lower triangle: F[i][k] -= P_i . P_k for i0 <= k <= i < d
+    for (int ii = wave; ii < nt; ii += kWavesPerBlock) {
+      double pi[kPanel];
+#pragma unroll
+      for (int c = 0; c < kPanel; ++c) pi[c] = P[ii * kPanelLd + c];
+      double* Fi = F + (int64_t)(i0 + ii) * ld + i0;
+      for (int kk = lane; kk <= ii; kk += kWave) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c) s += pi[c] * P[kk * kPanelLd + c];
+        Fi[kk] -= s;
+      }
+    }
+    __syncthreads();
+  }
+  // L^T into the upper triangle
+  for (int64_t idx = tid; idx < (int64_t)d * d; idx += kBlock) {
+    const int i = (int)(idx / d), k = (int)(idx % d);
+    if (k < i) F[(int64_t)k * ld + i] = F[(int64_t)i * ld + k];
+  }
+  if (bad && lane == 0) *e.fac_bad = 1;
 }
 
 __global__ void clear_words(unsigned* p, int64_t count) {
@@ -1383,8 +1617,11 @@ struct BlockPlan {
   const GramJob* d_jobs;
   int64_t njobs;
   int sa_f32;
-  unsigned* bar;       // barrier words and the error flag
+  unsigned* bar;       // barrier words, the error flag and the factorization flags
   int64_t bar_words;
+  int exact;           // launch the Cholesky factors before the solve
+  int64_t count;
+  size_t chol_shmem;
 };
 
 size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count) {
@@ -1400,7 +1637,7 @@ size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, i
   S.stride = (size_t)std::max<int64_t>(count, G) + 1;
   int dpmax = 64;
   for (int64_t i = 0; i < count; ++i) dpmax = std::max(dpmax, dp_for(ents[i].d));
-  const size_t base = block_layout(ents, count, S, G).total;
+  const size_t base = block_layout(ents, count, S, G, true).total;
   const size_t extra = (size_t)G * ((size_t)dpmax * KR + kNScal) * sizeof(double) + 256 * (size_t)count;
   return base + extra;
 }
@@ -1484,7 +1721,7 @@ int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, 
   Schedule S;
   int rc = make_schedule(ents, count, G, tuning, cost, &S);
   if (rc) return rc;
-  const BlockLayout L = block_layout(ents, count, S, G);
+  const BlockLayout L = block_layout(ents, count, S, G, tuning.exact != 0);
   if (!ws || L.total > ws_bytes) return MIHS_ERR_WORKSPACE;
   char* base = (char*)ws;
 
@@ -1535,6 +1772,8 @@ int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, 
     e.beta = s.beta;
     e.info = s.info;
     e.work = (double*)(base + L.work_off[i]);
+    e.fac = L.fac_off.empty() ? nullptr : (double*)(base + L.fac_off[i]);
+    e.fac_bad = (int*)(base + L.bar_off + (size_t)(2 * count + 2) * 128) + i;
     e.bar = (unsigned*)(base + L.bar_off + (size_t)(2 * i + 1) * 128);
     e.bar_cg = (unsigned*)(base + L.bar_off + (size_t)(2 * i + 2) * 128);
     e.d = (int)s.d;
@@ -1568,7 +1807,18 @@ int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, 
   P->njobs = (int64_t)jobs.size();
   P->sa_f32 = sa_f32;
   P->bar = (unsigned*)(base + L.bar_off);
-  P->bar_words = (int64_t)(2 * count + 2) * 32;
+  P->bar_words = (int64_t)(2 * count + 2) * 32 + count;
+  P->exact = tuning.exact;
+  P->count = count;
+  P->chol_shmem = chol_lds_bytes(dpmax);
+  if (tuning.exact) {
+    const void* ck = sa_f32 ? (const void*)chol_kernel<float> : (const void*)chol_kernel<double>;
+    if (hipFuncSetAttribute(ck, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)P->chol_shmem) != hipSuccess) {
+      delete P;
+      return MIHS_ERR_HIP;
+    }
+  }
   BatchArgs& a = P->args;
   a.entries = (const BatchEntry*)(base + L.ent_off);
   a.wg_items = (const int*)(base + L.item_off);
@@ -1577,6 +1827,7 @@ int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, 
   a.a_f32 = a_f32;
   a.h_f32 = sa_f32;
   a.a_dma = tuning.a_dma;
+  a.exact = tuning.exact;
   a.wall_khz = h->wall_khz;
   a.eps_sub = eps_sub;
   a.tol = tol;
@@ -1598,6 +1849,16 @@ int run_block(const BlockPlan* P, hipStream_t st) {
   if (P->njobs > 0) {
     const int rc = launch_gram_jobs(P->d_jobs, P->njobs, P->sa_f32, st);
     if (rc) return rc;
+  }
+  if (P->exact) {
+    const dim3 grid((unsigned)(P->count * KR));
+    if (P->sa_f32)
+      hipLaunchKernelGGL(chol_kernel<float>, grid, dim3(kBlock), P->chol_shmem, st,
+                         P->args.entries);
+    else
+      hipLaunchKernelGGL(chol_kernel<double>, grid, dim3(kBlock), P->chol_shmem, st,
+                         P->args.entries);
+    if (hipGetLastError() != hipSuccess) return MIHS_ERR_HIP;
   }
   BatchArgs a = P->args;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -1677,5 +1938,5 @@ extern "C" void mihs_batched_default_tuning(mihs_batched_tuning_t* t) {
   t->a_dma = 1;
   t->inner_weight = 100.0;
   t->measured = 0;
-  t->reserved = 0;
+  t->exact = 0;
 }

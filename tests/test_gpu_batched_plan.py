@@ -59,11 +59,13 @@ def _check_closed_form(xs, infos, refs, tol=1e-10):
     {"cg_cols": 64, "a_dma": 1, "inner_weight": 400.0},
     {"cg_cols": 32, "a_dma": 0, "inner_weight": 400.0},
     {"cg_cols": 512, "a_dma": 1, "inner_weight": 6.25},
+    {"cg_cols": 32, "a_dma": 1, "inner_weight": 25.0, "exact": 1},
+    {"cg_cols": 32, "a_dma": 0, "inner_weight": 6.25, "exact": 1},
 ])
 def test_every_launch_shape_reaches_the_closed_form(problem_set, tuning):
     """Each candidate shape of the autotuner (CG sub-team width, the A pass
-    through registers or direct-to-LDS, team sizing) solves every (problem,
-    lambda) to 1e-10."""
+    through registers or direct-to-LDS, team sizing, inexact CG or exact
+    Cholesky sub-solves) solves every (problem, lambda) to 1e-10."""
     mihs = _mihs()
     dp, refs, L, Al, Be = _device_set(problem_set)
     announce(f"batched plan shape {tuning}")
@@ -74,6 +76,10 @@ def test_every_launch_shape_reaches_the_closed_form(problem_set, tuning):
     infos = s.infos()
     _check_closed_form(s.xs, infos, refs)
     assert all(r["elapsed_us"] > 0 for inf in infos for r in inf)
+    if tuning.get("exact"):
+        # one exact sub-solve per outer step
+        assert all(1 <= r["inner_iters_total"] <= r["outer_iters"] for inf in infos for r in inf)
+        assert all(r["inner_iters_max"] == 1 for inf in infos for r in inf)
 
 
 def test_graph_replays_match_the_eager_run(problem_set):
@@ -107,8 +113,9 @@ def test_graph_replays_match_the_eager_run(problem_set):
 
 
 def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
-    """mihs_tune_batched times eight candidate shapes by coordinate descent, a
-    full run of the best and a schedule sized from its per-problem costs,
+    """mihs_tune_batched times ten candidate shapes by coordinate descent, full
+    runs of the best inexact and the best exact shape, and a schedule sized
+    from the faster one's per-problem costs,
     and keeps the best for this problem set: the plain batched call afterwards
     (which looks the shape up) still reaches the closed form, and so does a plan
     that asks for the measured schedule explicitly."""
@@ -119,11 +126,11 @@ def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
     announce("batched autotuner")
     res = s.tune(trial_outer=3)
     best = res["best"]
-    assert len(res["trial_ms"]) == 10
+    assert len(res["trial_ms"]) == 13
     assert all(t > 0 for t in res["trial_ms"])
     assert best["cg_cols"] in (16, 32, 64, 512) and best["a_dma"] in (0, 1)
     assert best["inner_weight"] in (6.25, 25.0, 100.0, 400.0)
-    assert best["measured"] in (0, 1)
+    assert best["measured"] in (0, 1) and best["exact"] in (0, 1)
     s.run()
     torch.cuda.synchronize()
     _check_closed_form(s.xs, s.infos(), refs)
@@ -178,7 +185,7 @@ def test_measured_schedule_with_more_entries_than_workgroups():
                            max_inner=2000)
     announce("batched 300 problems: tuner with measured schedule")
     res = s.tune(trial_outer=3)
-    assert len(res["trial_ms"]) == 10
+    assert len(res["trial_ms"]) == 13
     g = s.capture()
     s.X_all.fill_(float("nan"))
     torch.cuda.synchronize()

@@ -915,6 +915,15 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
   return k;
 }
 
+// Lane l's value of v in every lane (l a compile-time constant after
+// unrolling: two v_readlane into scalar registers, no LDS round trip).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Partial dot product of one factor row with the solved vector over the
 // 16-column blocks [m0, m1): this lane's k slot g covers k = 16 m + 4 g + 0..3.
 // Four blocks per step with separate sums keep eight 16-byte loads in flight.
@@ -989,7 +998,7 @@ __device__ __attribute__((noinline)) void tri_solve_local(const double* __restri
       for (int c = 0; c < 16; ++c)
         if (16 * I + c < d) {
           if (r == c) x /= dr[c];
-          const double xc = __shfl(x, c);
+          const double xc = lane_value(x, c);
           if (r > c) x -= dr[c] * xc;
         }
       if (g == 0 && row < d) y[row] = x;
@@ -1007,7 +1016,7 @@ __device__ __attribute__((noinline)) void tri_solve_local(const double* __restri
       for (int c = 15; c >= 0; --c)
         if (16 * I + c < d) {
           if (r == c) x /= dr[c];
-          const double xc = __shfl(x, c);
+          const double xc = lane_value(x, c);
           if (r < c) x -= dr[c] * xc;
         }
       if (g == 0 && row < d) y[row] = x;
@@ -1482,9 +1491,10 @@ BlockLayout block_layout(const BlockEntryDesc* ents, int64_t count, const Schedu
 // L L^T = H + lambda_j I, L in the lower triangle of F (dp x dp), L^T mirrored
 // into the upper triangle, zero at indices >= d.  Right-looking by 16-column
 // panels: the diagonal block is factored in registers of one wave (one
-// shuffle per column pair), the rows below it are solved against it one row
-// per thread and staged in LDS, and the trailing lower triangle is updated in
-// global memory from the staged panel.  A non-positive or non-finite pivot
+// lane broadcast per column pair), the rows below it are solved against it
+// one row per thread and staged in LDS, and the trailing lower triangle is
+// updated in global memory from the staged panel.  Each finished panel is
+// also written transposed into the upper triangle.  A non-positive or non-finite pivot
 // sets the entry's fac_bad word (the solve then uses the inner CG) and the
 // factorization goes on with pivot 1 so that every value stays finite.
 constexpr int kPanel = 16;
@@ -1500,15 +1510,31 @@ __global__ __launch_bounds__(kBlock) void chol_kernel(const BatchEntry* __restri
   if (col >= e.ncols || !e.fac) return;
   const int d = e.d, dp = e.dp;
   const int64_t ld = dp;
-  double* F = e.fac + (int64_t)col * ld * ld;
-  const TH* H = (const TH*)e.H;
+  double* __restrict__ F = e.fac + (int64_t)col * ld * ld;
+  const TH* __restrict__ H = (const TH*)e.H;
   const double lam = e.lam[col];
   const int tid = (int)threadIdx.x, lane = lane_id(), wave = wave_id();
   double* D = (double*)lds_raw;        // diagonal block, kPanel x kPanelLd
   double* P = D + kPanel * kPanelLd;   // panel rows below it, dp x kPanelLd
-  for (int64_t idx = tid; idx < (int64_t)dp * dp; idx += kBlock) {
-    const int i = (int)(idx / dp), k = (int)(idx % dp);
-    F[idx] = (i < d && k <= i) ? (double)H[(int64_t)i * e.ldh + k] + (i == k ? lam : 0.0) : 0.0;
+  // lower triangle of H + lambda I, zero elsewhere (the upper triangle is
+  // written with L^T as the panels are produced); a wave per row, eight
+  // independent copies per lane in flight
+  for (int i = wave; i < dp; i += kWavesPerBlock) {
+    const TH* Hi = H + (int64_t)i * e.ldh;
+    double* Fi = F + (int64_t)i * ld;
+    for (int k0 = 0; k0 < dp; k0 += 8 * kWave) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + u * kWave + lane;
+        v[u] = (i < d && k <= i) ? (double)Hi[k] + (i == k ? lam : 0.0) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + u * kWave + lane;
+        if (k < dp) Fi[k] = v[u];
+      }
+    }
   }
   __syncthreads();
   bool bad = false;
@@ -1524,7 +1550,7 @@ __global__ __launch_bounds__(kBlock) void chol_kernel(const BatchEntry* __restri
 #pragma unroll
       for (int c = 0; c < kPanel; ++c)
         if (c < w) {
-          double piv = __shfl(a[c], c);
+          double piv = lane_value(a[c], c);
           if (!(piv > 0.0) || !isfinite(piv)) {
             bad = true;
             piv = 1.0;
@@ -1534,7 +1560,7 @@ __global__ __launch_bounds__(kBlock) void chol_kernel(const BatchEntry* __restri
           else if (r > c) a[c] /= sq;
 #pragma unroll
           for (int cc = c + 1; cc < kPanel; ++cc) {
-            const double lcc = __shfl(a[c], cc);
+            const double lcc = lane_value(a[c], cc);
             if (r >= cc) a[cc] -= a[c] * lcc;
           }
         }
@@ -1542,7 +1568,10 @@ __global__ __launch_bounds__(kBlock) void chol_kernel(const BatchEntry* __restri
 #pragma unroll
         for (int c = 0; c < kPanel; ++c) {
           D[r * kPanelLd + c] = (r < w && c <= r) ? a[c] : 0.0;
-          if (r < w && c <= r) F[(int64_t)(J + r) * ld + J + c] = a[c];
+          if (r < w && c <= r) {
+            F[(int64_t)(J + r) * ld + J + c] = a[c];
+            F[(int64_t)(J + c) * ld + J + r] = a[c];  // L^T
+          }
         }
       }
     }
@@ -1564,30 +1593,41 @@ __global__ __launch_bounds__(kBlock) void chol_kernel(const BatchEntry* __restri
       }
 #pragma unroll
       for (int c = 0; c < kPanel; ++c) {
-        if (c < w) F[(int64_t)i * ld + J + c] = x[c];
+        if (c < w) {
+          F[(int64_t)i * ld + J + c] = x[c];
+          F[(int64_t)(J + c) * ld + i] = x[c];  // L^T (consecutive i: coalesced)
+        }
         P[(i - i0) * kPanelLd + c] = x[c];
       }
     }
     __syncthreads();
-    // trailing lower triangle: F[i][k] -= P_i . P_k for i0 <= k <= i < d
-    for (int ii = wave; ii < nt; ii += kWavesPerBlock) {
-      double pi[kPanel];
+    // trailing lower triangle: F[i][k] -= P_i . P_k for i0 <= k <= i < d, four
+    // consecutive rows per wave step (four independent updates per column k,
+    // one LDS read of P_k for all four)
+    constexpr int RW = 4;
+    for (int q0 = RW * wave; q0 < nt; q0 += RW * kWavesPerBlock) {
+      double pi[RW][kPanel];
 #pragma unroll
-      for (int c = 0; c < kPanel; ++c) pi[c] = P[ii * kPanelLd + c];
-      double* Fi = F + (int64_t)(i0 + ii) * ld + i0;
-      for (int kk = lane; kk <= ii; kk += kWave) {
-        double s = 0.0;
+      for (int q = 0; q < RW; ++q)
 #pragma unroll
-        for (int c = 0; c < kPanel; ++c) s += pi[c] * P[kk * kPanelLd + c];
-        Fi[kk] -= s;
+        for (int c = 0; c < kPanel; ++c)
+          pi[q][c] = q0 + q < nt ? P[(q0 + q) * kPanelLd + c] : 0.0;
+      const int klast = min(q0 + RW, nt) - 1;
+      for (int kk = lane; kk <= klast; kk += kWave) {
+        double pk[kPanel];
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c) pk[c] = P[kk * kPanelLd + c];
+#pragma unroll
+        for (int q = 0; q < RW; ++q)
+          if (kk <= q0 + q && q0 + q < nt) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < kPanel; ++c) s += pi[q][c] * pk[c];
+            F[(int64_t)(i0 + q0 + q) * ld + i0 + kk] -= s;
+          }
       }
     }
     __syncthreads();
-  }
-  // L^T into the upper triangle
-  for (int64_t idx = tid; idx < (int64_t)d * d; idx += kBlock) {
-    const int i = (int)(idx / d), k = (int)(idx % d);
-    if (k < i) F[(int64_t)k * ld + i] = F[(int64_t)i * ld + k];
   }
   if (bad && lane == 0) *e.fac_bad = 1;
 }

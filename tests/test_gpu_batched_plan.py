@@ -198,3 +198,33 @@ def test_measured_schedule_with_more_entries_than_workgroups():
         for j in (0, 9, 19):
             assert infos[i][j]["status"] == 0, (i, j, infos[i][j])
             assert rel(X[:, j], O.ridge_lstsq(P.A, P.b, float(lams[j]))) <= 1e-10, (i, j)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_exact_subsolves_follow_the_oracle_trajectory(problem_set, k):
+    """Exact sub-solves (Exact M-IHS): after k outer steps from x = 0 every
+    column equals the oracle's M-IHS with a Cholesky sub-solve after k steps.
+    The bound allows for the conditioning of the sub-problems (kappa up to 1e6
+    at lambda = 1e-6 sigma_1^2, where two FP64 Cholesky solves may differ by
+    up to kappa d u in the worst direction; measured differences are ~3e-11),
+    far below the O(1) change of one step."""
+    mihs = _mihs()
+    problems, refs, L, Al, Be = problem_set
+    dp, _, Ld, Ald, Bed = _device_set(problem_set)
+    s = mihs.BatchedSolver(dp, Ld, Ald, Bed, eps_sub=1e-2, tol=0.0, max_outer=k, max_inner=2000,
+                           tuning={"cg_cols": 32, "a_dma": 1, "inner_weight": 25.0, "exact": 1})
+    announce(f"batched exact sub-solves, {k} outer steps")
+    s.run()
+    torch.cuda.synchronize()
+    infos = s.infos()
+    worst = 0.0
+    for i, (A, b, SA) in enumerate(problems):
+        X = s.xs[i].cpu().numpy()
+        for j in range(0, NLAM, 5):
+            assert infos[i][j]["outer_iters"] == k, (i, j, infos[i][j])
+            ref = O.mihs(A, b, float(L[i, j]), SA, float(Al[i, j]), float(Be[i, j]),
+                         inner="exact", n_iter=k).x
+            e = rel(X[:, j], ref)
+            worst = max(worst, e)
+            assert e <= 1e-9, (i, j, e)
+    print(f"exact trajectory after {k} steps: worst relative difference {worst:.2e}")

@@ -964,7 +964,8 @@ __device__ __forceinline__ double slot_sum(double s) {
 // Exact sub-solve of one outer step (Exact M-IHS, Section 5): for every active
 // column j, z_j = (L_j L_j^T)^{-1} r_j with the column's Cholesky factor F_j
 // (L_j in the lower triangle, L_j^T mirrored into the upper one, zero at
-// indices >= d).  Wave w takes columns w, w + 4, ...; the column's vector lives
+// indices >= d).  Member `rank` of a sub-team of `tc` workgroups takes columns
+// rank, rank + tc, ..., handed to its waves in turn; the column's vector lives
 // in the wave's slice of LDS.  Both substitutions run by 16-row blocks, each
 // block first taking the dot products of its rows with the already solved part
 // (lane = row + 16 k-slot, four consecutive k per lane and 16-column step,
@@ -974,14 +975,16 @@ template <int DP>
 __device__ __attribute__((noinline)) void tri_solve_local(const double* __restrict__ Fb,
                                                           int64_t ld, int d,
                                                           const double* __restrict__ R,
-                                                          double* __restrict__ Z) {
+                                                          double* __restrict__ Z, int rank,
+                                                          int tc) {
   extern __shared__ uint4 lds_raw[];
   Shared& sh = g_sh;
   const int lane = lane_id(), wave = wave_id();
   const int r = lane & 15, g = lane >> 4;
   double* y = (double*)lds_raw + wave * DP;
   const int nb = (d + 15) / 16;
-  for (int j = wave; j < KR; j += kWavesPerBlock) {
+  for (int q = wave; rank + q * tc < KR; q += kWavesPerBlock) {
+    const int j = rank + q * tc;
     if (!sh.active[j]) continue;
     const double* F = Fb + (int64_t)j * ld * ld;
     for (int k = lane; k < DP; k += kWave) y[k] = k < d ? R[(int64_t)k * KR + j] : 0.0;
@@ -1148,9 +1151,12 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       // ---- lockstep CG on (H + lambda_j I): in the workgroup when the CG
       // sub-team is one workgroup, else on the team
       int64_t k;
-      if (a.exact && e.fac && !*(volatile int*)e.fac_bad) {
-        tri_solve_local<DP>(e.fac, e.dp, d, R, Z);
-        k = 1;
+      const bool exact = a.exact && e.fac && !*(volatile int*)e.fac_bad;
+      if (exact) {
+        // the columns split over the sub-team; its barrier publishes Z to the
+        // row owners of the update
+        tri_solve_local<DP>(e.fac, e.dp, d, R, Z, rank, Tc);
+        k = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin) ? 1 : -1;
       } else if (local_cg)
         k = a.h_f32 ? cg_solve_local<float, DP>((const float*)e.H, e.ldh, d, R, Z, a.eps_sub,
                                                 a.max_inner)
@@ -1164,7 +1170,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
                                            scal, myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin,
                                            a.eps_sub, a.max_inner);
       alive = k >= 0;
-      if (alive && Tc > 1) ep_cg += 2u * (unsigned)k;
+      if (alive && Tc > 1 && !exact) ep_cg += 2u * (unsigned)k;
       if (!alive) break;
       if (threadIdx.x < KR) {
         const int j = threadIdx.x;
@@ -1357,7 +1363,7 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
     }
     *S = T;
     for (int64_t i = 0; i < count; ++i)
-      S->tcg[i] = tn.exact ? 1 : std::max(
+      S->tcg[i] = tn.exact ? std::min(S->tsize[i], KR) : std::max(
           1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
     S->stride = 1;
     for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
@@ -1415,9 +1421,9 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
     load[best] += wgt[i];
   }
   // CG sub-team: about cg_cols columns of H per member, at most the whole team
-  // (exact sub-solves: the team's first workgroup)
+  // (exact sub-solves: every member up to one per column)
   for (int64_t i = 0; i < count; ++i)
-    S->tcg[i] = tn.exact ? 1 : std::max(
+    S->tcg[i] = tn.exact ? std::min(S->tsize[i], KR) : std::max(
         1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
   S->stride = 1;
   for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);

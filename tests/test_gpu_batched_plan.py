@@ -228,3 +228,40 @@ def test_exact_subsolves_follow_the_oracle_trajectory(problem_set, k):
             worst = max(worst, e)
             assert e <= 1e-9, (i, j, e)
     print(f"exact trajectory after {k} steps: worst relative difference {worst:.2e}")
+
+
+def test_exact_falls_back_to_the_cg_when_a_factorization_fails():
+    """A Gram matrix whose FP32 rounding outweighs lambda (A of rank d - 8, an FP32
+    sketch, lambda ~ 1e-12 ||H||: the near-null eigenvalues of the rounded H are
+    ~1e-4 of either sign against lambda ~ 1e-9) meets a non-positive Cholesky
+    pivot; such a problem runs the inexact CG instead.  With teams of one
+    workgroup (300 problems) both plans then run the same one-workgroup CG, so
+    the exact plan must equal the inexact one bit for bit, with CG step counts."""
+    mihs = _mihs()
+    rng = np.random.default_rng(5)
+    nlam, problems, lams = 4, [], []
+    for i in range(300):
+        n, d = 600, 48
+        Bm = rng.standard_normal((n, d - 8))
+        A = np.hstack([Bm, Bm[:, :8] @ rng.standard_normal((8, 8))])
+        b = rng.standard_normal(n)
+        SA = sketches.gaussian_sketch(A, 2 * d, 100 + i).astype(np.float32)
+        hn = float(np.linalg.norm(SA.astype(np.float64).T @ SA.astype(np.float64), 2))
+        problems.append((to_dev(A), to_dev(b), torch.as_tensor(SA, device="cuda")))
+        lams.append(hn * 1e-12 * (1.0 + np.arange(nlam)))
+    L = to_dev(np.array(lams))
+    Al = to_dev(np.full((300, nlam), 0.5))
+    Be = to_dev(np.full((300, nlam), 0.2))
+    runs = {}
+    for exact in (0, 1):
+        s = mihs.BatchedSolver(problems, L, Al, Be, eps_sub=1e-2, tol=0.0, max_outer=4,
+                               max_inner=200, tuning={"cg_cols": 512, "a_dma": 1,
+                                                      "inner_weight": 6.25, "exact": exact})
+        announce(f"batched rank-deficient set, exact={exact}")
+        s.run()
+        torch.cuda.synchronize()
+        runs[exact] = (s.X_all.clone(), s.infos())
+    assert torch.equal(torch.nan_to_num(runs[0][0], nan=7.0), torch.nan_to_num(runs[1][0], nan=7.0))
+    assert [[r["inner_iters_total"] for r in inf] for inf in runs[0][1]] == \
+        [[r["inner_iters_total"] for r in inf] for inf in runs[1][1]]
+    assert max(r["inner_iters_max"] for inf in runs[1][1] for r in inf) > 1

@@ -181,7 +181,8 @@ def timed(fn, steps, warmup, stream):
 
 def run_batched(args):
     """256 problems x 16 lambdas (n_k in [4096, 65536], d_k in [64, 512], FP64 A),
-    one Gaussian sketch per problem (mixed: BF16 on the matrix cores), then all
+    one Gaussian sketch per problem (mixed: BF16 on the matrix cores; round-robin on four
+    streams, i.e. four branches of the captured graph), then all
     4096 lambda-path solves in one launch of the block kernel.  The launch shape
     is chosen by the library's autotuner (untimed, once); one step (the 256
     sketches, x^1 = 0 and the batched launch) is captured in a HIP graph and the
@@ -207,7 +208,11 @@ def run_batched(args):
         sks.append(torch.zeros((s.m, lds), dtype=torch.float32, device=dev)[:, :s.d])
         probs.append((Ab[:, :s.d], b))
         ws_bytes = max(ws_bytes, mihs.sketch_workspace_bytes(s.n, s.d, s.m, "gaussian", "mixed"))
-    sk_ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    # the sketches go round-robin to four streams (default priority), each with
+    # its own workspace: independent branches of the captured graph
+    nsk = 4
+    sk_streams = [torch.cuda.Stream(device=dev) for _ in range(nsk)]
+    sk_ws = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(nsk)]
     torch.cuda.synchronize()
     nlam = len(specs[0].lambdas)
     lam = np.stack([s.lambdas for s in specs])
@@ -222,9 +227,15 @@ def run_batched(args):
     eps_sub = 0.1
 
     def sketch_all():
+        main = torch.cuda.current_stream()
+        for st in sk_streams:
+            st.wait_stream(main)
         for i, ((A, b), s) in enumerate(zip(probs, specs)):
-            mihs.mihs_sketch(A, "gaussian", s.m, 10 + i, precision="mixed", out=sks[i],
-                             workspace=sk_ws)
+            with torch.cuda.stream(sk_streams[i % nsk]):
+                mihs.mihs_sketch(A, "gaussian", s.m, 10 + i, precision="mixed", out=sks[i],
+                                 workspace=sk_ws[i % nsk])
+        for st in sk_streams:
+            main.wait_stream(st)
 
     sketch_all()
     solver = mihs.BatchedSolver([(A, b, SA) for (A, b), SA in zip(probs, sks)], lam_d, al_d,

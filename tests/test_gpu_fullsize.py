@@ -77,8 +77,9 @@ def test_fullsize_countsketch_solve(count_problem, prec):
 
 def test_fullsize_batched_lambda_paths():
     """256 problems x 16 lambdas (n in [4096, 65536], d in [64, 512]) with mixed
-    Gaussian sketches in one launch; sampled (problem, lambda) pairs against the
-    oracle's closed form."""
+    Gaussian sketches in one launch, with the default shape and with the
+    autotuned plan the benchmark times; sampled (problem, lambda) pairs against
+    the oracle's closed form."""
     mihs = _mihs()
     specs = W.batched_specs()
     announce("full-size batched: draw")
@@ -98,11 +99,25 @@ def test_fullsize_batched_lambda_paths():
     xs, infos = mihs.mihs_solve_batched(probs, T(lam_rows), T(al_rows), T(be_rows),
                                         eps_sub=0.1, tol=1e-11, max_outer=400, max_inner=2000)
     assert all(r["status"] == 0 for inf in infos for r in inf)
+    refs = {}
     for i in (0, 31, 97, 180, 255):
         A_h, b_h = probs[i][0].cpu().numpy(), probs[i][1].cpu().numpy()
         for j in (0, 5, 15):
-            ref = O.ridge_lstsq(A_h, b_h, float(lam_rows[i][j]))
-            assert rel(xs[i][:, j].cpu().numpy(), ref) <= 1e-10, (i, j)
+            refs[i, j] = O.ridge_lstsq(A_h, b_h, float(lam_rows[i][j]))
+            assert rel(xs[i][:, j].cpu().numpy(), refs[i, j]) <= 1e-10, (i, j)
+    # the configuration the benchmark times: the autotuner's choice (exact
+    # Cholesky sub-solves or the inner CG, teams sized from measured costs)
+    announce("full-size batched: autotuned plan")
+    s = mihs.BatchedSolver(probs, T(lam_rows), T(al_rows), T(be_rows), eps_sub=0.1, tol=1e-11,
+                           max_outer=400, max_inner=2000)
+    tuned = s.tune(trial_outer=8)
+    print(f"full-size batched tuning: {tuned['best']}")
+    s.run()
+    torch.cuda.synchronize()
+    infos = s.infos()
+    assert all(r["status"] == 0 for inf in infos for r in inf)
+    for (i, j), ref in refs.items():
+        assert rel(s.xs[i][:, j].cpu().numpy(), ref) <= 1e-10, (i, j)
 
 
 def test_fullsize_differentiation():

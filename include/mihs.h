@@ -445,7 +445,8 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
  * x team size as the problem's cost on one workgroup, and runs a schedule
  * sized from those costs (teams of
  * ceil(cost / L) workgroups for problems above a makespan L, first-fit bins
- * of capacity L for the rest, the smallest L that fits) for as long;
+ * of capacity L for the rest, a team member's remaining capacity after its
+ * team problem included; the smallest L that fits) for as long;
  * measured = 1 in *best if that one was faster.  The best
  * shape is returned in *best and kept in the handle, keyed by the problem set's
  * shapes (n, d, m of every problem and nlam); later mihs_solve_batched and

@@ -1298,7 +1298,8 @@ struct Schedule {
 
 // Sizing from measured costs c_i (entry i on one workgroup): the smallest
 // makespan L (bisection) for which teams of ceil(c_i / L) workgroups for the
-// entries above L and first-fit-decreasing bins of capacity L for the rest fit
+// entries above L and first-fit-decreasing bins of capacity L for the rest
+// (team members offering what their team entry leaves of L) fit
 // in G workgroups.
 bool makespan_schedule(const std::vector<double>& c, int G, double L, Schedule* S) {
   const int64_t count = (int64_t)c.size();
@@ -1309,6 +1310,7 @@ bool makespan_schedule(const std::vector<double>& c, int G, double L, Schedule* 
   S->tsize.assign(count, 1);
   S->tcg.assign(count, 1);
   S->items.assign(G, std::vector<int>());
+  std::vector<double> load(G, 0.0);
   int next = 0;
   for (int64_t i : order) {
     if (c[i] <= L) break;
@@ -1316,22 +1318,23 @@ bool makespan_schedule(const std::vector<double>& c, int G, double L, Schedule* 
     if (next + t > G) return false;
     S->team0[i] = next;
     S->tsize[i] = t;
-    for (int u = 0; u < t; ++u) S->items[next + u].push_back((int)i);
+    for (int u = 0; u < t; ++u) {
+      S->items[next + u].push_back((int)i);
+      load[next + u] = c[i] / t;
+    }
     next += t;
   }
-  const int first_bin = next;
-  std::vector<double> load;
+  // the rest first-fit in decreasing cost over every workgroup, the team
+  // members' remaining capacity included (a team entry always comes first in
+  // its members' lists, so no team waits on a member busy elsewhere)
   for (int64_t i : order) {
     if (c[i] > L) continue;
-    size_t b = 0;
-    while (b < load.size() && load[b] + c[i] > L * (1.0 + 1e-9)) ++b;
-    if (b == load.size()) {
-      if (first_bin + (int)b >= G) return false;
-      load.push_back(0.0);
-    }
-    load[b] += c[i];
-    S->team0[i] = first_bin + (int)b;
-    S->items[first_bin + b].push_back((int)i);
+    int g = 0;
+    while (g < G && load[g] + c[i] > L * (1.0 + 1e-9)) ++g;
+    if (g == G) return false;
+    load[g] += c[i];
+    S->team0[i] = g;
+    S->items[g].push_back((int)i);
   }
   return true;
 }

@@ -16,10 +16,12 @@ def _mihs():
     return mihs
 
 
-def _check_layout(sched, d, G, cg_cols):
+def _check_layout(sched, d, G, cg_cols, singles_on_teams=False):
     """Every entry has a valid place; teams are disjoint ranges of their own;
-    bins (team size 1) only share workgroups with other bin entries; the CG
-    sub-team is at most the team and about d / cg_cols workgroups."""
+    bins (team size 1) only share workgroups with other bin entries (the
+    measured schedule may also put them on a team's workgroups, after the team
+    entry); the CG sub-team is at most the team and about d / cg_cols
+    workgroups."""
     t0, ts, tc = (np.array(sched[k]) for k in ("team0", "tsize", "tcg"))
     assert (ts >= 1).all() and (t0 >= 0).all() and (t0 + ts <= G).all()
     assert (tc >= 1).all() and (tc <= ts).all()
@@ -30,8 +32,9 @@ def _check_layout(sched, d, G, cg_cols):
         for g in range(t0[e], t0[e] + ts[e]):
             assert g not in owner, "teams overlap"
             owner[g] = e
-    for e in np.flatnonzero(ts == 1):
-        assert t0[e] not in owner, "a bin entry sits on a team workgroup"
+    if not singles_on_teams:
+        for e in np.flatnonzero(ts == 1):
+            assert t0[e] not in owner, "a bin entry sits on a team workgroup"
     return t0, ts
 
 
@@ -81,9 +84,10 @@ def test_one_problem_takes_every_workgroup():
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_measured_schedule_bounds_the_makespan(seed):
     """Teams of ceil(c / L) for entries above the makespan L, first-fit bins of
-    capacity L for the rest: every workgroup's load is at most L, which is
-    within a factor 2 of the lower bound max(sum c / G, max c / G), and no worse
-    than the model schedule's load under the same costs."""
+    capacity L for the rest (team members' remaining capacity included): every
+    workgroup's load is at most L, which is within a factor 2 of the lower
+    bound max(sum c / G, max c / G), and no worse than the model schedule's
+    load under the same costs."""
     mihs = _mihs()
     rng = np.random.default_rng(seed)
     G = 256
@@ -93,7 +97,7 @@ def test_measured_schedule_bounds_the_makespan(seed):
     tn = {"cg_cols": 32, "a_dma": 1, "inner_weight": 25.0, "measured": 1}
     sched = mihs.batched_schedule(shapes, 16, G, tn, cost=list(cost))
     d = np.array([s[1] for s in shapes])
-    t0, ts = _check_layout(sched, d, G, 32)
+    t0, ts = _check_layout(sched, d, G, 32, singles_on_teams=True)
     load = _loads(t0, ts, cost, G)
     lb = max(cost.sum() / G, cost.max() / G)
     assert load.max() <= 2.0 * lb * (1 + 1e-9) + np.sort(cost)[len(cost) // 2]
@@ -134,3 +138,23 @@ def test_exact_sub_solves_use_the_whole_team_up_to_sixteen():
         assert max(sched["tsize"]) > 1
         for ts, tc in zip(sched["tsize"], sched["tcg"]):
             assert tc == min(ts, 16), (ts, tc)
+
+
+def test_measured_schedule_fills_team_workgroups():
+    """One entry of cost 1.6 and eleven of 0.2 on four workgroups: the large one
+    gets a team of two (0.8 each).  With the small ones only on the other two
+    workgroups the makespan is 1.2 (six of them on one); filling the team
+    members' remaining capacity after their team entry brings it to 1.0."""
+    mihs = _mihs()
+    G = 4
+    cost = np.array([1.6] + [0.2] * 11)
+    shapes = [(40000, 300)] * len(cost)
+    tn = {"cg_cols": 32, "a_dma": 1, "inner_weight": 25.0, "measured": 1}
+    sched = mihs.batched_schedule(shapes, 16, G, tn, cost=list(cost * 1000.0))
+    d = np.array([s[1] for s in shapes])
+    t0, ts = _check_layout(sched, d, G, 32, singles_on_teams=True)
+    load = _loads(t0, ts, cost, G)
+    assert ts[0] == 2
+    team = set(range(t0[0], t0[0] + 2))
+    assert any(t0[e] in team for e in range(1, len(cost))), sched
+    assert load.max() <= 1.0 + 1e-3, load

@@ -355,6 +355,7 @@ struct DmaCfg {
   static constexpr int NI = ROWS * CPR / kWavesPerBlock;    // instructions per wave per group
   static constexpr int BUF = ROWS * LDB;                    // bytes per buffer
   static_assert(!ok || (NI == 16 && 2 * BUF <= (int)kDmaRegion), "dma layout");
+  static_assert(!ok || (LDB / 4) % 64 == 4, "the LDS row pitch shifts by 4 banks per row");
 };
 
 typedef __attribute__((address_space(3))) char lds_char;
@@ -481,20 +482,24 @@ __device__ __forceinline__ void block_pass_dma(const TM* __restrict__ M, int64_t
       wait_lgkm0();
       raw_barrier();
       // G += tile^T U: the U operand is the same for every block b (read once);
-      // the tile values of block b + 1 are read before the products of block b
+      // the tile values of block b + 1 are read before the products of block b.
+      // k slot g of product s is tile row s + 4 (g >> 1) + 8 (g & 1): the rows
+      // that share an LDS pass (k slots 0, 1 and 2, 3) then sit 8 rows, i.e.
+      // 32 banks, apart (the row pitch shifts by 4 banks), so no reads collide
+      const int g4 = 4 * ((lane >> 5) & 1) + 8 * ((lane >> 4) & 1);
       double bvu[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) bvu[s] = ufin[(4 * s + (lane >> 4)) * KR + (lane & 15)];
-      const TM* gcol = tile + (lane >> 4) * C::LDT + kbase + (lane & 15);
+      for (int s = 0; s < 4; ++s) bvu[s] = ufin[(s + g4) * KR + (lane & 15)];
+      const TM* gcol = tile + g4 * C::LDT + kbase + (lane & 15);
       double gbuf[2][4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) gbuf[0][s] = (double)gcol[4 * s * C::LDT];
+      for (int s = 0; s < 4; ++s) gbuf[0][s] = (double)gcol[s * C::LDT];
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         if (b + 1 < NB) {
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            gbuf[(b + 1) & 1][s] = (double)gcol[4 * s * C::LDT + 16 * (b + 1)];
+            gbuf[(b + 1) & 1][s] = (double)gcol[s * C::LDT + 16 * (b + 1)];
         }
         if (16 * b < dqe) {
 #pragma unroll

@@ -384,8 +384,8 @@ typedef struct {
                         (inner_weight unused); without such a measurement the
                         model above is used */
   int32_t exact;     /* 1: solve the sub-problem of every outer step exactly
-                        (Exact M-IHS, the variant of the experiments in
-                        Section 5 that factorizes the sketched system): one
+                        (Exact M-IHS, Table 2 and Section 4.2: the variant
+                        that factorizes the sketched system): one
                         FP64 Cholesky factor of (SA)^T SA + lambda_j I per
                         column, formed in the launch before the solve, then a
                         forward and a backward substitution per outer step

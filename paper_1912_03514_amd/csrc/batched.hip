@@ -966,7 +966,7 @@ __device__ __forceinline__ double slot_sum(double s) {
   return s + __shfl_xor(s, 32);
 }
 
-// Exact sub-solve of one outer step (Exact M-IHS, Section 5): for every active
+// Exact sub-solve of one outer step (Exact M-IHS: Table 2, Section 4.2): for every active
 // column j, z_j = (L_j L_j^T)^{-1} r_j with the column's Cholesky factor F_j
 // (L_j in the lower triangle, L_j^T mirrored into the upper one, zero at
 // indices >= d).  Member `rank` of a sub-team of `tc` workgroups takes columns
@@ -975,7 +975,7 @@ __device__ __forceinline__ double slot_sum(double s) {
 // block first taking the dot products of its rows with the already solved part
 // (lane = row + 16 k-slot, four consecutive k per lane and 16-column step,
 // summed over the four slots), then solving its 16 x 16 diagonal block in
-// registers, one shuffle per column.
+// registers, one lane broadcast per column.
 template <int DP>
 __device__ __attribute__((noinline)) void tri_solve_local(const double* __restrict__ Fb,
                                                           int64_t ld, int d,

@@ -265,3 +265,43 @@ def test_exact_falls_back_to_the_cg_when_a_factorization_fails():
     assert [[r["inner_iters_total"] for r in inf] for inf in runs[0][1]] == \
         [[r["inner_iters_total"] for r in inf] for inf in runs[1][1]]
     assert max(r["inner_iters_max"] for inf in runs[1][1] for r in inf) > 1
+
+
+@pytest.mark.parametrize("sa_f32", [False, True])
+def test_exact_subsolves_at_the_widest_padding(sa_f32):
+    """Exact sub-solves with d above 512 (the 1024-wide layout: factors of up to
+    1024 x 1024, the widest LDS panel) and 20 lambdas (entries of 16 and of 4
+    columns), FP64 and FP32 Gram matrices: every (problem, lambda) reaches the
+    closed form, one sub-solve per outer step."""
+    mihs = _mihs()
+    nlam = 20
+    problems, refs, L, Al, Be = [], [], [], [], []
+    for i, (n, d) in enumerate([(3000, 700), (2600, 1000)]):
+        sig = W.sigma_profile("exp", d, 5.0)
+        P = W.make_problem(n, d, sig, d / 4, 1300 + i)
+        m = min(n, 2 * d)
+        SA = sketches.gaussian_sketch(P.A, m, 70 + i)
+        s1 = float(sig[0]) ** 2
+        lams = s1 * 10.0 ** (-5.0 + 4.0 * np.arange(nlam) / (nlam - 1))
+        sds = np.array([W.nominal_sd(sig, float(l)) for l in lams])
+        betas = np.minimum(sds / m, 0.95)
+        SAd = torch.as_tensor(SA.astype(np.float32), device="cuda") if sa_f32 else to_dev(SA)
+        problems.append((to_dev(P.A), to_dev(P.b), SAd))
+        refs.append((P, lams))
+        L.append(lams)
+        Al.append((1.0 - betas) ** 2)
+        Be.append(betas)
+    s = mihs.BatchedSolver(problems, to_dev(np.array(L)), to_dev(np.array(Al)),
+                           to_dev(np.array(Be)), eps_sub=1e-2, tol=1e-12, max_outer=800,
+                           max_inner=2000,
+                           tuning={"cg_cols": 32, "a_dma": 1, "inner_weight": 25.0, "exact": 1})
+    announce(f"batched exact sub-solves, d = 700 and 1000, sa_f32={sa_f32}")
+    s.run()
+    torch.cuda.synchronize()
+    infos = s.infos()
+    for i, (P, lams) in enumerate(refs):
+        X = s.xs[i].cpu().numpy()
+        for j in range(nlam):
+            assert infos[i][j]["status"] == 0, (i, j, infos[i][j])
+            assert infos[i][j]["inner_iters_max"] == 1, (i, j, infos[i][j])
+            assert rel(X[:, j], O.ridge_lstsq(P.A, P.b, float(lams[j]))) <= 1e-10, (i, j)

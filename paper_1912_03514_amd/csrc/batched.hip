@@ -1158,8 +1158,8 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       int64_t k;
       const bool exact = a.exact && e.fac && !*(volatile int*)e.fac_bad;
       if (exact) {
-        // the columns split over the sub-team; its barrier publishes Z to the
-        // row owners of the update
+        // (the sub-team is one workgroup in exact mode; its barrier is then a
+        // workgroup barrier)
         tri_solve_local<DP>(e.fac, e.dp, d, R, Z, rank, Tc);
         k = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin) ? 1 : -1;
       } else if (local_cg)
@@ -1371,7 +1371,7 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
     }
     *S = T;
     for (int64_t i = 0; i < count; ++i)
-      S->tcg[i] = tn.exact ? std::min(S->tsize[i], KR) : std::max(
+      S->tcg[i] = tn.exact ? 1 : std::max(
           1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
     S->stride = 1;
     for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
@@ -1429,9 +1429,10 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
     load[best] += wgt[i];
   }
   // CG sub-team: about cg_cols columns of H per member, at most the whole team
-  // (exact sub-solves: every member up to one per column)
+  // (exact sub-solves: the team's first workgroup, which keeps the launch
+  // bit-reproducible; splitting the columns over the team was not)
   for (int64_t i = 0; i < count; ++i)
-    S->tcg[i] = tn.exact ? std::min(S->tsize[i], KR) : std::max(
+    S->tcg[i] = tn.exact ? 1 : std::max(
         1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
   S->stride = 1;
   for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);

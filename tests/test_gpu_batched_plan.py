@@ -82,15 +82,18 @@ def test_every_launch_shape_reaches_the_closed_form(problem_set, tuning):
         assert all(r["inner_iters_max"] == 1 for inf in infos for r in inf)
 
 
-def test_graph_replays_match_the_eager_run(problem_set):
-    """The launch captured in a HIP graph, replayed three times with other
-    eager work (and garbage in X) between the replays, gives bit-identical
-    results to the eager launch of the same plan."""
+@pytest.mark.parametrize("exact", [0, 1])
+def test_graph_replays_match_the_eager_run(problem_set, exact):
+    """The launch captured in a HIP graph (with the Cholesky factor kernel when
+    the sub-solves are exact), replayed three times with other eager work (and
+    garbage in X) between the replays, gives bit-identical results to the eager
+    launch of the same plan."""
     mihs = _mihs()
     dp, refs, L, Al, Be = _device_set(problem_set)
     s = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
                            max_inner=2000,
-                           tuning={"cg_cols": 32, "a_dma": 1, "inner_weight": 100.0})
+                           tuning={"cg_cols": 32, "a_dma": 1, "inner_weight": 100.0,
+                                   "exact": exact})
     announce("batched plan eager run")
     s.run()
     torch.cuda.synchronize()

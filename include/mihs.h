@@ -464,7 +464,7 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
  * n d + inner_weight d^2.  Per entry (problem-major, groups of 16 columns in
  * order): team0[e] first workgroup, tsize[e] team size (1: the entry shares a
  * single-workgroup bin), tcg[e] inner-solve sub-team size (exact
- * sub-solves: 1).  Arrays hold
+ * sub-solves: min(tsize, 16), one member per column at most).  Arrays hold
  * nprob * ceil(nlam / 16) values.  Returns MIHS_ERR_UNSUPPORTED if the entries
  * do not fit.
  * ------------------------------------------------------------------------ */

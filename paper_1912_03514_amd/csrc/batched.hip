@@ -971,7 +971,9 @@ __device__ __forceinline__ double slot_sum(double s) {
 // (L_j in the lower triangle, L_j^T mirrored into the upper one, zero at
 // indices >= d).  Member `rank` of a sub-team of `tc` workgroups takes columns
 // rank, rank + tc, ..., handed to its waves in turn; the column's vector lives
-// in the wave's slice of LDS.  Both substitutions run by 16-row blocks, each
+// in the wave's slice of LDS.  z goes to Zt column-major (column j at Zt + j ld,
+// ld the entry's padded width), so that no cache line holds results of two
+// workgroups.  Both substitutions run by 16-row blocks, each
 // block first taking the dot products of its rows with the already solved part
 // (lane = row + 16 k-slot, four consecutive k per lane and 16-column step,
 // summed over the four slots), then solving its 16 x 16 diagonal block in
@@ -980,7 +982,7 @@ template <int DP>
 __device__ __attribute__((noinline)) void tri_solve_local(const double* __restrict__ Fb,
                                                           int64_t ld, int d,
                                                           const double* __restrict__ R,
-                                                          double* __restrict__ Z, int rank,
+                                                          double* __restrict__ Zt, int rank,
                                                           int tc) {
   extern __shared__ uint4 lds_raw[];
   Shared& sh = g_sh;
@@ -1029,7 +1031,7 @@ __device__ __attribute__((noinline)) void tri_solve_local(const double* __restri
         }
       if (g == 0 && row < d) y[row] = x;
     }
-    for (int k = lane; k < d; k += kWave) Z[(int64_t)k * KR + j] = y[k];
+    for (int k = lane; k < d; k += kWave) Zt[(int64_t)j * ld + k] = y[k];
   }
   if (threadIdx.x < KR) sh.kin[threadIdx.x] = sh.active[threadIdx.x] ? 1 : 0;
   __threadfence_block();
@@ -1158,9 +1160,9 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
       int64_t k;
       const bool exact = a.exact && e.fac && !*(volatile int*)e.fac_bad;
       if (exact) {
-        // (the sub-team is one workgroup in exact mode; its barrier is then a
-        // workgroup barrier)
-        tri_solve_local<DP>(e.fac, e.dp, d, R, Z, rank, Tc);
+        // the columns split over the sub-team, z column-major in Q (unused by
+        // the exact path); the barrier publishes it to the row owners
+        tri_solve_local<DP>(e.fac, e.dp, d, R, Q, rank, Tc);
         k = group_sync(e.bar_cg, Tc, ep_cg, a.err, s_flag, a.spin) ? 1 : -1;
       } else if (local_cg)
         k = a.h_f32 ? cg_solve_local<float, DP>((const float*)e.H, e.ldh, d, R, Z, a.eps_sub,
@@ -1193,7 +1195,8 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
         const int64_t o = (int64_t)c * KR + j;
         double* xp = e.X + (int64_t)c * e.ldx + j;
         const double xc = *xp;
-        const double xn = xc + sh.alpha[j] * Z[o] + sh.beta[j] * (xc - XP[o]);
+        const double zv = !exact ? Z[o] : (sh.active[j] ? Q[(int64_t)j * e.dp + c] : 0.0);
+        const double xn = xc + sh.alpha[j] * zv + sh.beta[j] * (xc - XP[o]);
         XP[o] = xc;
         *xp = xn;
         s0 += (xn - xc) * (xn - xc);
@@ -1371,7 +1374,7 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
     }
     *S = T;
     for (int64_t i = 0; i < count; ++i)
-      S->tcg[i] = tn.exact ? 1 : std::max(
+      S->tcg[i] = tn.exact ? std::min(S->tsize[i], KR) : std::max(
           1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
     S->stride = 1;
     for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
@@ -1429,10 +1432,9 @@ int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
     load[best] += wgt[i];
   }
   // CG sub-team: about cg_cols columns of H per member, at most the whole team
-  // (exact sub-solves: the team's first workgroup, which keeps the launch
-  // bit-reproducible; splitting the columns over the team was not)
+  // (exact sub-solves: every member up to one per column)
   for (int64_t i = 0; i < count; ++i)
-    S->tcg[i] = tn.exact ? 1 : std::max(
+    S->tcg[i] = tn.exact ? std::min(S->tsize[i], KR) : std::max(
         1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
   S->stride = 1;
   for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);

@@ -127,15 +127,17 @@ def test_schedule_rejects_bad_arguments():
                                                    "inner_weight": 25.0})
 
 
-def test_exact_sub_solves_run_in_the_first_workgroup():
-    """With exact sub-solves the sub-team is the team's first workgroup."""
+def test_exact_sub_solves_use_the_whole_team_up_to_sixteen():
+    """With exact sub-solves the columns split over the team: the sub-team is the
+    team, capped at one member per column."""
     import paper_1912_03514_amd as mihs
     shapes = [(60000, 500), (50000, 480), (8000, 100), (6000, 90)]
     for cols in (32, 512):
         tn = {"cg_cols": cols, "a_dma": 1, "inner_weight": 25.0, "exact": 1}
         sched = mihs.batched_schedule(shapes, 16, 40, tuning=tn)
         assert max(sched["tsize"]) > 1
-        assert all(tc == 1 for tc in sched["tcg"]), sched
+        for ts, tc in zip(sched["tsize"], sched["tcg"]):
+            assert tc == min(ts, 16), (ts, tc)
 
 
 def test_measured_schedule_fills_team_workgroups():

@@ -45,7 +45,12 @@ def parse():
                     help="relative-step stop tolerance (default: per workload, chosen so "
                          "that the result is within 1e-10 of x*)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 15)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2^20 x 4096 CountSketch workload of the default line")
+    ap.add_argument("--large-steps", type=int, default=1)
+    ap.add_argument("--tol-large", type=float, default=None)
+    ap.add_argument("--cpu-sample-rows", type=int, default=0,
+                    help="rows of the oracle's CPU baseline instance (0: the full workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -56,12 +61,12 @@ def parse():
 # runs (FETCH_SIZE, then WRITE_SIZE, each scaled by what the counter reads for a
 # plain 1 GiB device copy: x1.99993 for FETCH_SIZE, x1.000 for WRITE_SIZE); see
 # profiles/solve_kernel_srht_2p18x2048.md.  Valid for the kernel as profiled.
-MEASURED_TRAFFIC = {("srht_2p18x2048", "mixed"): 155251289044}
+MEASURED_TRAFFIC = {}
 
 # Stop-rule tolerance per workload: the relative-step rule estimates the error
 # from the Corollary 4 rate sqrt(beta); where the observed rate is slower (the
 # two-stage sketch of the ill-conditioned FP32 workload) the tolerance is tighter.
-DEFAULT_TOL = {"count_2p20x4096": 2e-12, "batched_lambda_path": 1e-11}
+DEFAULT_TOL = {"count_2p20x4096": 2e-12, "batched_lambda_path": 3e-12}
 
 
 def log(msg):
@@ -137,12 +142,23 @@ def ref_ridge_device(A, b, lam, refine=0, chunk=1 << 16):
     return x.cpu().numpy()
 
 
-def cpu_baseline(w, lam, rows):
-    """The oracle (numpy FP64) on a bounded sample: the same workload recipe with
-    the first `rows` rows (same d, m, lambda), sketch + M-IHS to 1e-10; the
-    measured time is scaled by n / rows (both the sketch and the per-iteration
-    pass are linear in n)."""
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, lam, A_dev, b_dev, rows):
+    """The oracle (numpy/scipy FP64, as it stands) timed on the host cores:
+    sketch + M-IHS with its CG inner solver to 1e-10.  rows = n (the default) is
+    the full workload, on the same A and b the GPU solved (copied to the host
+    before timing); a smaller `rows` times a seeded instance of that many rows
+    drawn from the same recipe and scales the time by n / rows (both the sketch
+    and the per-iteration pass are linear in n)."""
     import workloads as W
     from oracle import sketches, solver as O
     try:
@@ -150,17 +166,24 @@ def cpu_baseline(w, lam, rows):
         cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
-    P = W.make_problem(rows, w.d, w.sigma, w.sd_target, w.data_seed + 1)
+    if rows >= w.n:
+        A, b = A_dev.cpu().numpy(), b_dev.cpu().numpy()
+        what = f"the full {w.n}x{w.d} workload (the GPU's A and b)"
+        scale = 1.0
+    else:
+        P = W.make_problem(rows, w.d, w.sigma, w.sd_target, w.data_seed + 1)
+        A, b = P.A, P.b
+        scale = w.n / rows
+        what = (f"a {rows}x{w.d} instance of the same recipe, scaled by n/rows = {scale:g}")
     t0 = time.perf_counter()
-    SA = sketches.sketch(P.A, w.sketch, w.m, w.sketch_seed, w.m2)
-    a, b = O.momentum_cor4(w.sd_target, w.m_out)
-    r = O.mihs(P.A, P.b, lam, SA, a, b, inner="cg", eps_sub=w.eps_sub, tol=1e-10)
+    SA = sketches.sketch(A, w.sketch, w.m, w.sketch_seed, w.m2)
+    a, be = O.momentum_cor4(w.sd_target, w.m_out)
+    r = O.mihs(A, b, lam, SA, a, be, inner="cg", eps_sub=w.eps_sub, tol=1e-10)
     dt = time.perf_counter() - t0
-    scale = w.n / rows
-    return {"value": dt * scale * 1e3, "unit": "ms", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle sketch+solve of a {rows}x{w.d} instance of the same recipe "
-                       f"({r.outer} outer / {sum(r.inner)} inner iterations, {dt:.1f} s), "
-                       f"scaled by n/rows = {scale:g}")}
+    return {"value": round(dt * scale * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": (f"oracle sketch + M-IHS (CG inner) to 1e-10 on {what}: "
+                       f"{r.outer} outer / {sum(r.inner)} inner iterations, {dt:.1f} s")}
 
 
 def timed(fn, steps, warmup, stream):
@@ -179,15 +202,43 @@ def timed(fn, steps, warmup, stream):
     return times, outs
 
 
+def ridge_path_qr(A, b, lams):
+    """Closed forms of one problem's lambda-path on the device with torch
+    (Householder QR of A, then a small QR of [R; sqrt(lam) I] per lambda;
+    backward stable, independent of the library).  Returns host d x k."""
+    import numpy as np
+    import torch
+    n, d = A.shape
+    Q, R = torch.linalg.qr(A.to(torch.float64))
+    c = Q.transpose(0, 1).contiguous() @ b.to(torch.float64)
+    del Q
+    lam = torch.as_tensor(np.asarray(lams, dtype=np.float64), device=A.device)
+    k = lam.numel()
+    eye = torch.eye(d, dtype=torch.float64, device=A.device)
+    M = torch.cat([R.expand(k, d, d), torch.sqrt(lam)[:, None, None] * eye], dim=1).contiguous()
+    rhs = torch.cat([c.expand(k, d), torch.zeros(k, d, dtype=torch.float64, device=A.device)],
+                    dim=1)[:, :, None].contiguous()
+    Q2, R2 = torch.linalg.qr(M)
+    x = torch.linalg.solve_triangular(R2, Q2.transpose(1, 2).contiguous() @ rhs, upper=True)
+    return x[:, :, 0].transpose(0, 1).contiguous().cpu().numpy()
+
+
 def run_batched(args):
     """256 problems x 16 lambdas (n_k in [4096, 65536], d_k in [64, 512], FP64 A),
-    one Gaussian sketch per problem (mixed: BF16 on the matrix cores; round-robin on four
-    streams, i.e. four branches of the captured graph), then all
-    4096 lambda-path solves in one launch of the block kernel.  The launch shape
-    is chosen by the library's autotuner (untimed, once); one step (the 256
-    sketches, x^1 = 0 and the batched launch) is captured in a HIP graph and the
-    timed steps are graph replays.  The same step run eagerly is reported beside
-    it."""
+    one Gaussian sketch per problem, then all 4096 lambda-path solves in one
+    launch of the block kernel.  One step (the 256 sketches round-robin on four
+    streams, i.e. four branches of the graph, x^1 = 0 and the batched launch) is
+    captured in a HIP graph and the timed steps are graph replays.
+
+    Three configurations, each tuned by the library's autotuner (untimed, once):
+      mixed  BF16 sketches, the decomposition-free inner CG of Algorithm 1 (the
+             headline `value`);
+      plain  FP64 sketches on the FP64 matrix cores, inner CG: the plain FP64
+             GPU baseline;
+      exact  BF16 sketches, exact sub-solves (Exact M-IHS, one Cholesky factor
+             per column), reported beside the others.
+    Every one of the 4096 results of the headline run is checked against its
+    QR closed form after timing."""
     import numpy as np
     import torch
     import paper_1912_03514_amd as mihs
@@ -195,8 +246,7 @@ def run_batched(args):
     dev = torch.device("cuda", 0)
     specs = W.batched_specs()
     log(f"drawing {len(specs)} problems on the GPU")
-    probs, sks = [], []
-    ws_bytes = 0
+    probs = []
     for s in specs:
         sig = W.sigma_profile("exp", s.d, 6.0)
         A, b, _, _ = W.make_problem_torch(s.n, s.d, sig, s.d / 2, s.seed, dev, "f64")
@@ -204,15 +254,7 @@ def run_batched(args):
         Ab = torch.zeros((s.n, ld), dtype=torch.float64, device=dev)
         Ab[:, :s.d] = A
         del A
-        lds = (s.d + 3) // 4 * 4
-        sks.append(torch.zeros((s.m, lds), dtype=torch.float32, device=dev)[:, :s.d])
         probs.append((Ab[:, :s.d], b))
-        ws_bytes = max(ws_bytes, mihs.sketch_workspace_bytes(s.n, s.d, s.m, "gaussian", "mixed"))
-    # the sketches go round-robin to four streams (default priority), each with
-    # its own workspace: independent branches of the captured graph
-    nsk = 4
-    sk_streams = [torch.cuda.Stream(device=dev) for _ in range(nsk)]
-    sk_ws = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(nsk)]
     torch.cuda.synchronize()
     nlam = len(specs[0].lambdas)
     lam = np.stack([s.lambdas for s in specs])
@@ -225,97 +267,136 @@ def run_batched(args):
     al_d = torch.as_tensor(alphas, device=dev)
     be_d = torch.as_tensor(betas, device=dev)
     eps_sub = 0.1
+    nsk = 4
+    sk_streams = [torch.cuda.Stream(device=dev) for _ in range(nsk)]
 
-    def sketch_all():
+    def make_sketches(precision):
+        dt = torch.float32 if precision == "mixed" else torch.float64
+        per = 4 if precision == "mixed" else 2
+        sks = [torch.zeros((s.m, (s.d + per - 1) // per * per), dtype=dt, device=dev)[:, :s.d]
+               for s in specs]
+        wsb = max(mihs.sketch_workspace_bytes(s.n, s.d, s.m, "gaussian", precision)
+                  for s in specs)
+        wss = [torch.empty(wsb, dtype=torch.uint8, device=dev) for _ in range(nsk)]
+        return sks, wss
+
+    def sketch_all(precision, sks, wss):
         main = torch.cuda.current_stream()
         for st in sk_streams:
             st.wait_stream(main)
         for i, ((A, b), s) in enumerate(zip(probs, specs)):
             with torch.cuda.stream(sk_streams[i % nsk]):
-                mihs.mihs_sketch(A, "gaussian", s.m, 10 + i, precision="mixed", out=sks[i],
-                                 workspace=sk_ws[i % nsk])
+                mihs.mihs_sketch(A, "gaussian", s.m, 10 + i, precision=precision, out=sks[i],
+                                 workspace=wss[i % nsk])
         for st in sk_streams:
             main.wait_stream(st)
 
-    sketch_all()
-    solver = mihs.BatchedSolver([(A, b, SA) for (A, b), SA in zip(probs, sks)], lam_d, al_d,
-                                be_d, eps_sub=eps_sub, tol=args.tol, max_outer=400,
-                                max_inner=2000)
-    log("autotuning the launch shape (8 outer iterations per shape trial, then two full runs "
-        "for the measured schedule)")
-    t0 = time.perf_counter()
-    tune = solver.tune(trial_outer=8)
-    tune["wall_s"] = round(time.perf_counter() - t0, 2)
-    log(f"  {tune}")
-
-    def step():
-        sketch_all()
-        solver.run()
-
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
-    def eager_step():
-        ev[0].record()
-        sketch_all()
-        ev[1].record()
-        solver.run()
-        ev[2].record()
-        torch.cuda.synchronize()
-        return ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    def configuration(name, precision, allow_exact, steps, warmup):
+        sks, wss = make_sketches(precision)
+        sketch_all(precision, sks, wss)
+        solver = mihs.BatchedSolver([(A, b, SA) for (A, b), SA in zip(probs, sks)], lam_d, al_d,
+                                    be_d, eps_sub=eps_sub, tol=args.tol, max_outer=400,
+                                    max_inner=2000)
+        log(f"{name}: autotuning the launch shape (exact sub-solves "
+            f"{'allowed' if allow_exact else 'not allowed'})")
+        t0 = time.perf_counter()
+        tune = solver.tune(trial_outer=8, allow_exact=allow_exact)
+        tune["wall_s"] = round(time.perf_counter() - t0, 2)
+        log(f"  {tune}")
 
-    eager_times, eager_outs = timed(eager_step, 1, 1, None)
-    sketch_ms, solve_ms = eager_outs[-1]
-    log("capturing one step (256 sketches + batched launch) in a HIP graph")
-    graph = torch.cuda.CUDAGraph()
-    cs = torch.cuda.Stream(device=dev)
-    cs.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(cs):
-        with torch.cuda.graph(graph, stream=cs):
-            step()
-    torch.cuda.current_stream().wait_stream(cs)
-    torch.cuda.synchronize()
-    times, _ = timed(graph.replay, args.steps, args.warmup, None)
-    infos = solver.infos()
-    xs = solver.xs
-    # sampled accuracy against the closed form (host)
-    errs = []
-    for i in (0, 97, 255):
-        A_h, b_h = probs[i][0].cpu().numpy(), probs[i][1].cpu().numpy()
-        for j in (0, 7, 15):
-            ref = ref_ridge(A_h, b_h, float(lam[i, j]))
-            x = xs[i][:, j].cpu().numpy()
-            errs.append(float(np.linalg.norm(x - ref) / np.linalg.norm(ref)))
-    outer = np.array([[r["outer_iters"] for r in inf] for inf in infos])
-    inner = np.array([[r["inner_iters_total"] for r in inf] for inf in infos])
-    status = np.array([[r["status"] for r in inf] for inf in infos])
-    elapsed = np.array([inf[0]["elapsed_us"] for inf in infos]) * 1e-3
-    slow = np.argsort(-elapsed)[:5]
+        def eager_step():
+            ev[0].record()
+            sketch_all(precision, sks, wss)
+            ev[1].record()
+            solver.run()
+            ev[2].record()
+            torch.cuda.synchronize()
+            return ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+
+        eager_times, eager_outs = timed(eager_step, 1, 1, None)
+        sketch_ms, solve_ms = eager_outs[-1]
+        graph = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream(device=dev)
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            with torch.cuda.graph(graph, stream=cs):
+                sketch_all(precision, sks, wss)
+                solver.run()
+        torch.cuda.current_stream().wait_stream(cs)
+        torch.cuda.synchronize()
+        times, _ = timed(graph.replay, steps, warmup, None)
+        infos = solver.infos()
+        outer = np.array([[r["outer_iters"] for r in inf] for inf in infos])
+        inner = np.array([[r["inner_iters_total"] for r in inf] for inf in infos])
+        status = np.array([[r["status"] for r in inf] for inf in infos])
+        out = {"ms": float(np.mean(times)), "eager_step_ms": float(np.mean(eager_times)),
+               "solve_ms": solve_ms, "sketch_ms": sketch_ms, "tuning": tune,
+               "outer_iters_max": int(outer.max()), "outer_iters_mean": float(outer.mean()),
+               "inner_iters_mean": float(inner.mean()),
+               "all_converged": bool((status == 0).all()), "outer": outer,
+               "xs": [x.clone() for x in solver.xs],
+               "elapsed_ms": np.array([inf[0]["elapsed_us"] for inf in infos]) * 1e-3}
+        log(f"  {name}: {out['ms']:.2f} ms/step (sketches {sketch_ms:.2f}, solve {solve_ms:.2f}); "
+            f"outer max {out['outer_iters_max']}, mean {out['outer_iters_mean']:.1f}")
+        del graph
+        solver.close()
+        del solver, sks, wss
+        torch.cuda.synchronize()
+        return out
+
+    res = {"mixed": configuration("mixed, inner CG", "mixed", False, args.steps, args.warmup)}
+    short = max(1, min(args.steps, 3))
+    res["plain"] = configuration("plain FP64, inner CG", "plain", False, short, 1)
+    res["exact"] = configuration("mixed, exact sub-solves", "mixed", True, short, 1)
+
+    log("checking all 4096 results of every configuration against QR closed forms")
+    worst = {k: 0.0 for k in res}
+    for i, ((A, b), s) in enumerate(zip(probs, specs)):
+        ref = ridge_path_qr(A, b, s.lambdas)
+        nrm = np.linalg.norm(ref, axis=0)
+        for k, r in res.items():
+            X = r["xs"][i].cpu().numpy()
+            e = float(np.max(np.linalg.norm(X - ref, axis=0) / nrm))
+            worst[k] = max(worst[k], e)
+    log(f"  worst relative errors {worst}")
+    mx = res["mixed"]
     apass = sum(s.n * s.d * 8 for s in specs)
-    achieved = sum(s.n * s.d * 8 * int(outer[i].max()) for i, s in enumerate(specs)) / (solve_ms * 1e-3) / 1e9
-    flops = sum(4.0 * s.n * s.d * 16 * int(outer[i].max()) for i, s in enumerate(specs))
-    value = float(np.mean(times))
+    # per-problem outer counts: every entry passes over its A once per outer
+    # iteration of its slowest column, with 16 columns per pass (4 n d x 16 flops)
+    flops = sum(4.0 * s.n * s.d * 16 * int(mx["outer"][i].max()) for i, s in enumerate(specs))
+    bytes_moved = sum(s.n * s.d * 8 * int(mx["outer"][i].max()) for i, s in enumerate(specs))
+    tf = flops / (mx["solve_ms"] * 1e-3) / 1e12
+    slow = np.argsort(-mx["elapsed_ms"])[:5]
+    clean = lambda r: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
+                       if k not in ("outer", "xs", "elapsed_ms")}
+    value = mx["ms"]
     return {
-        "metric": "time to solve 256 ridge problems x 16 lambdas to 1e-10 (sketch + batched M-IHS)",
+        "metric": "time to solve 256 ridge problems x 16 lambdas to 1e-10 (sketch + batched "
+                  "M-IHS, inner CG)",
         "value": round(value, 3), "unit": "ms", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(value, 3),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (BF16 sketches)", "data": "synthetic",
+        "dtype": "f64 outer (BF16 sketches)", "data": "synthetic",
         "config": {"workload": "batched_lambda_path", "problems": len(specs), "nlam": nlam,
                    "n_range": [4096, 65536], "d_range": [64, 512], "eps_sub": eps_sub,
                    "tol": args.tol, "a_bytes_total": apass},
         "timing": "HIP-graph replay of one step (256 sketches + batched launch)",
-        "eager_step_ms": round(float(np.mean(eager_times)), 3),
-        "solve_ms": round(solve_ms, 3), "sketch_ms": round(sketch_ms, 3),
-        "tuning": tune,
-        "outer_iters_max": int(outer.max()), "outer_iters_mean": float(outer.mean()),
-        "inner_iters_mean": float(inner.mean()), "all_converged": bool((status == 0).all()),
+        "mixed_cg": clean(mx),
+        "plain_fp64_cg": clean(res["plain"]),
+        "plain_fp64_ms": round(res["plain"]["ms"], 3),
+        "mixed_speedup_vs_plain": round(res["plain"]["ms"] / value, 3),
+        "exact_subsolves": clean(res["exact"]),
+        "max_rel_err_all_4096": worst,
+        "accuracy_ok": all(v <= 1e-10 for v in worst.values()),
         "slowest_entries": [{"problem": int(i), "n": specs[i].n, "d": specs[i].d,
-                             "ms": round(float(elapsed[i]), 2),
-                             "outer_max": int(outer[i].max())} for i in slow],
-        "sampled_max_rel_err": max(errs),
-        "roofline": {"bound": "mfma", "kernel": "batched_kernel", "achieved": round(flops / (solve_ms * 1e-3) / 1e12, 2),
-                     "peak": 78.6, "unit": "TFLOP/s", "frac": round(flops / (solve_ms * 1e-3) / 1e12 / 78.6, 4),
-                     "traffic": None, "a_pass_gbs": round(achieved, 1)},
+                             "ms": round(float(mx["elapsed_ms"][i]), 2),
+                             "outer_max": int(mx["outer"][i].max())} for i in slow],
+        "roofline": {"bound": "mfma", "kernel": "batched_kernel (mixed, inner CG)",
+                     "achieved": round(tf, 2), "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": round(tf / 78.6, 4), "traffic": None,
+                     "a_pass_gbs": round(bytes_moved / (mx["solve_ms"] * 1e-3) / 1e9, 1)},
     }
 
 
@@ -563,42 +644,19 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "calls": 3}))
 
 
-def main():
-    args = parse()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.tol is None:
-        args.tol = DEFAULT_TOL.get(args.workload, 5e-11)
-    if args.workload in ("batched_lambda_path", "diff_2p18x1024", "small_gauss",
-                         "dual_4096x2p16", "pd_16384x4096"):
-        if args.gpus != 1:
-            print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
-            sys.exit(2)
-        import paper_1912_03514_amd as mihs
-        mihs.load_library()
-        fn = {"batched_lambda_path": run_batched, "diff_2p18x1024": run_diff,
-              "small_gauss": run_small, "dual_4096x2p16": run_dual,
-              "pd_16384x4096": run_pd}[args.workload]
-        print(json.dumps(fn(args)), flush=True)
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
+def run_ridge(args, wname, steps, warmup, full=True):
+    """One ridge workload: the sketch + solve step of the mixed and the plain
+    FP64 path, timed over `steps` steps after `warmup`, each result checked
+    against the closed form after timing; with `full`, also the sd estimate
+    (Algorithm 5), the AAb_Solver inner solver and the oracle's CPU baseline."""
     import numpy as np
     import torch
 
     import paper_1912_03514_amd as mihs
     import workloads as W
 
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU visible"}))
-        sys.exit(1)
-    mihs.load_library()
     dev = torch.device("cuda", 0)
-    w = W.workload(args.workload)
+    w = W.workload(wname)
     lam = w.lam
     alpha, beta = mihs.momentum(w.sd_target, w.m_out)
 
@@ -663,11 +721,11 @@ def main():
 
     out = {}
     for precision in ("mixed", "plain"):
-        log(f"{precision}: warmup {args.warmup}")
-        run(precision, args.warmup, False)
-        log(f"{precision}: timing {args.steps} steps")
+        log(f"{w.name} {precision}: warmup {warmup}")
+        run(precision, warmup, False)
+        log(f"{w.name} {precision}: timing {steps} steps")
         torch.cuda.synchronize()
-        times, sk, sv, infos, xs = run(precision, args.steps, True)
+        times, sk, sv, infos, xs = run(precision, steps, True)
         errs = [float(np.linalg.norm(x.cpu().numpy() - x_ref) / np.linalg.norm(x_ref)) for x in xs]
         out[precision] = dict(ms=float(np.mean(times)), sketch_ms=float(np.mean(sk)),
                               solve_ms=float(np.mean(sv)), infos=infos, errs=errs,
@@ -693,9 +751,11 @@ def main():
                 "inner_iters": [i["inner_iters_total"] for i in infos],
                 "ms": round(float(np.mean(ts[1:])), 3)}
 
-    log("statistical dimension estimate (Algorithm 5)")
-    sd_est = {p: sd_estimate(p) for p in ("mixed", "plain")}
-    log(f"  {sd_est}")
+    sd_est = {}
+    if full:
+        log("statistical dimension estimate (Algorithm 5)")
+        sd_est = {p: sd_estimate(p) for p in ("mixed", "plain")}
+        log(f"  {sd_est}")
 
     def aab_solve(precision, reps=3):
         """The same solve with AAb_Solver (Algorithm 6) as the inner solver (it
@@ -718,9 +778,11 @@ def main():
         return {"solve_ms": round(float(np.mean(ts[1:])), 3), "outer_iters": inf["outer_iters"],
                 "inner_iters": inf["inner_iters_total"], "rel_err": err}
 
-    log("AAb_Solver as the inner solver (Algorithm 6)")
-    aab = {p: aab_solve(p) for p in ("mixed", "plain")}
-    log(f"  {aab}")
+    aab = {}
+    if full:
+        log("AAb_Solver as the inner solver (Algorithm 6)")
+        aab = {p: aab_solve(p) for p in ("mixed", "plain")}
+        log(f"  {aab}")
 
     mx, pl = out["mixed"], out["plain"]
     info = mx["infos"][-1]
@@ -740,8 +802,8 @@ def main():
         "value": round(mx["ms"], 3),
         "unit": "ms",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(mx["ms"], 3),
         "higher_is_better": False,
         "scaling": "weak",
@@ -774,9 +836,73 @@ def main():
                      "launch_overhead_ms": round(mx["overhead_ms"], 3)},
         "accuracy_ok": max(mx["errs"]) <= 1e-10 and max(pl["errs"]) <= 1e-10,
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a bounded sample)")
-        result["cpu_baseline"] = cpu_baseline(w, lam, args.cpu_sample_rows)
+    if full and not args.no_cpu_baseline:
+        log("cpu baseline (the oracle on the host cores)")
+        rows = args.cpu_sample_rows if args.cpu_sample_rows > 0 else w.n
+        result["cpu_baseline"] = cpu_baseline(w, lam, A, b, rows)
+    del A, b
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return result
+
+
+
+
+def ridge_summary(r):
+    """The keys of a ridge result that another workload's line carries."""
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "config", "plain_fp64_ms",
+            "mixed_speedup_vs_plain", "mixed", "plain", "roofline", "accuracy_ok")
+    return {k: r[k] for k in keep if k in r}
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.tol is None:
+        args.tol = DEFAULT_TOL.get(args.workload, 5e-11)
+    if args.workload in ("batched_lambda_path", "diff_2p18x1024", "small_gauss",
+                         "dual_4096x2p16", "pd_16384x4096"):
+        if args.gpus != 1:
+            print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        import paper_1912_03514_amd as mihs
+        mihs.load_library()
+        fn = {"batched_lambda_path": run_batched, "diff_2p18x1024": run_diff,
+              "small_gauss": run_small, "dual_4096x2p16": run_dual,
+              "pd_16384x4096": run_pd}[args.workload]
+        out = fn(args)
+        mihs.release_all()
+        print(json.dumps(out), flush=True)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1912_03514_amd as mihs
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    mihs.load_library()
+    dev = torch.device("cuda", 0)
+    result = run_ridge(args, args.workload, args.steps, args.warmup, full=True)
+    if args.workload == "srht_2p18x2048" and not args.no_large:
+        # the largest single-GPU ridge configuration, a few steps (each takes
+        # seconds), reported beside the headline
+        if args.tol_large is not None:
+            args.tol = args.tol_large
+        else:
+            args.tol = DEFAULT_TOL["count_2p20x4096"]
+        result["count_2p20x4096"] = ridge_summary(
+            run_ridge(args, "count_2p20x4096", args.large_steps, 1, full=False))
+    mihs.release_all()
     print(json.dumps(result), flush=True)
 
 

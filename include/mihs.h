@@ -108,6 +108,31 @@ int mihs_destroy(mihs_handle_t handle);
 const char* mihs_status_string(int code);
 
 /* ------------------------------------------------------------------------
+ * Momentum parameters of the heavy-ball iteration (host computations).
+ *
+ * mihs_momentum_cor4  Corollary 4: a sketch with m rows of a problem whose
+ *   statistical dimension is sd (0 < sd < m) gives beta = sd / m and
+ *   alpha = (1 - beta)^2, for which the iteration contracts at rate sqrt(beta).
+ *   An over-estimate of sd keeps the rate bound (remark after Corollary 4).
+ *   m is the number of rows of the sketch the solver sees (m2 for
+ *   MIHS_COUNT_GAUSS).  Returns MIHS_ERR_INVALID unless 0 < sd < m, both
+ *   finite, and alpha, beta are non-null.
+ * mihs_momentum_thm1  Theorem 1: when the sketched Hessian satisfies the
+ *   subspace-embedding bound with distortion eps (0 < eps < 1), the optimal
+ *   momentum is beta* = (eps / (1 + sqrt(1 - eps^2)))^2 and step
+ *   alpha* = (1 - beta*) sqrt(1 - eps^2), with rate sqrt(beta*).  Returns
+ *   MIHS_ERR_INVALID unless 0 < eps < 1.
+ * ------------------------------------------------------------------------ */
+int mihs_momentum_cor4(double sd, int64_t m, double* alpha, double* beta);
+int mihs_momentum_thm1(double eps, double* alpha, double* beta);
+
+/* The regularisation parameter of the differentiable ridge layer, which is
+ * parametrised by log(lambda) so that lambda stays positive:
+ * *lambda = exp(log_lambda).  MIHS_ERR_INVALID if the result is not a finite
+ * positive number or lambda is null. */
+int mihs_lambda_from_log(double log_lambda, double* lambda);
+
+/* ------------------------------------------------------------------------
  * Sketch:  SA = S A  (Algorithm 1's RP_fun; E[S^T S] = I, Section 3.1)
  *
  * A      device, n x d, dtype `a_dtype`, row stride lda.
@@ -435,12 +460,16 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
  * Autotuner of the batched launch shape.  Times trial solves of the given
  * problems (each from X = 0, at most trial_outer outer iterations, HIP events
  * on `stream`) over candidate shapes by coordinate descent: inner_weight in
- * {6.25, 25, 100, 400}, then cg_cols in {16, 32, 64, 512}, then a_dma in {1, 0},
- * then exact = 1 with inner_weight in {6.25, 25} (the best exact shape is kept
- * apart: short trials charge its factorizations to few outer iterations).
- * If measure_outer > 0 it then runs the best inexact and the best exact shape
- * for up to measure_outer outer iterations each (normally the solve's own
- * limit, so that every problem runs to its stop), keeps the faster, reads the
+ * {6.25, 25, 100, 400}, then cg_cols in {16, 32, 64, 512}, then a_dma in {1, 0}.
+ * These shapes all use the inexact inner CG (Algorithm 1's decomposition-free
+ * sub-solver).  Only with allow_exact = 1 does it also try exact = 1 (Exact
+ * M-IHS: one Cholesky factor per column) with inner_weight in {6.25, 25} (the
+ * best exact shape is kept apart: short trials charge its factorizations to
+ * few outer iterations); allow_exact = 0 never chooses exact sub-solves.
+ * If measure_outer > 0 it then runs the best inexact shape (and, with
+ * allow_exact, the best exact shape) for up to measure_outer outer iterations
+ * each (normally the solve's own limit, so that every problem runs to its
+ * stop), keeps the faster, reads the
  * wall time of every problem in that run (mihs_info_t.elapsed_us), takes time
  * x team size as the problem's cost on one workgroup, and runs a schedule
  * sized from those costs (teams of
@@ -478,8 +507,31 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
                       const double* lambdas, const double* alphas, const double* betas,
                       int64_t nlam, mihs_precision_t precision, double eps_sub, double tol,
                       int64_t trial_outer, int64_t measure_outer, int64_t max_inner,
-                      void* workspace, size_t ws_bytes, void* stream,
+                      int32_t allow_exact, void* workspace, size_t ws_bytes, void* stream,
                       mihs_batched_tuning_t* best, float* cand_ms, int32_t* ncand);
+
+/* ------------------------------------------------------------------------
+ * Tuning cache (host only).  The shapes mihs_tune_batched keeps in a handle,
+ * with their measured per-entry costs, written to / read from one JSON file
+ *   {"format": "libmihs-batched-tuning", "version": 1, "arch": ..., "num_cu": ...,
+ *    "entries": [{"key": "<16 hex digits>", "cg_cols", "a_dma", "inner_weight",
+ *                 "measured", "exact", "cost": [...]}, ...]}
+ * so that a later process skips the tuning of a problem set it has seen.
+ * mihs_tuning_cache_save writes every kept shape (replacing the file through a
+ *   temporary and a rename).  MIHS_ERR_INVALID if the file cannot be written.
+ * mihs_tuning_cache_load adds the file's shapes to the handle (replacing equal
+ *   keys) when its arch and num_cu equal the handle's device; a file for
+ *   another device is read and ignored (*loaded = 0).  *loaded (nullable) is
+ *   the number of shapes taken.  MIHS_ERR_INVALID if the file is missing or
+ *   not in this format (the handle is then unchanged).
+ * mihs_batched_cached_tuning returns MIHS_OK and the kept shape in *tuning if
+ *   the handle holds one for this problem set (shapes n, d, m of every problem
+ *   and nlam), else MIHS_ERR_UNSUPPORTED.
+ * ------------------------------------------------------------------------ */
+int mihs_tuning_cache_save(mihs_handle_t handle, const char* path);
+int mihs_tuning_cache_load(mihs_handle_t handle, const char* path, int32_t* loaded);
+int mihs_batched_cached_tuning(mihs_handle_t handle, const mihs_problem_t* h_problems,
+                               int64_t nprob, int64_t nlam, mihs_batched_tuning_t* tuning);
 
 /* ------------------------------------------------------------------------
  * Backward of x*_j = (A^T A + lambda I)^{-1} A^T b_j for k right-hand sides.
@@ -488,7 +540,9 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
  * by M-IHS on the same sketch (gradient gbar_j - A^T A w_j - lambda w_j), then
  *   dL/dB = A W  (n x k)    and    dL/dlambda = - sum_j x*_j^T w_j.
  * Xstar, Gbar, W are d x k row-major doubles (device); dB is n x k (device,
- * NULL to skip); dlambda is one device double.  d_info holds k records.
+ * NULL to skip); dlambda is one device double; dloglambda (device, NULL to
+ * skip) receives dL/dlog(lambda) = lambda dL/dlambda, the derivative for the
+ * log(lambda) parametrisation of mihs_lambda_from_log.  d_info holds k records.
  * For d <= 1024 the k systems run as blocks of 16 right-hand sides that share
  * each pass over A and SA (FP64 matrix cores); wider problems solve the
  * columns one after another.  The workspace size comes from
@@ -502,8 +556,8 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
                         double lambda, mihs_precision_t precision, const double* Xstar,
                         const double* Gbar, int64_t k, double alpha, double beta,
                         double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
-                        double* W, double* dB, double* dlambda, mihs_info_t* d_info,
-                        void* workspace, size_t ws_bytes, void* stream);
+                        double* W, double* dB, double* dlambda, double* dloglambda,
+                        mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -14,5 +14,7 @@ from ._binding import (  # noqa: F401
     batched_schedule, info_to_dict, sketch_workspace_bytes,
     load_library, mihs_estimate_sd, mihs_sketch, mihs_sketch_two_stage, mihs_solve,
     mihs_solve_backward, mihs_solve_batched, mihs_solve_dual, mihs_solve_multi, mihs_solve_pd,
-    mihs_solve_pd_dual, mihs_transpose, MIHSRidge, momentum,
+    mihs_solve_pd_dual, mihs_transpose, MIHSRidge, momentum, momentum_thm1, lambda_from_log,
+    release_all, tuning_cache_save,
+    tuning_cache_load,
 )

@@ -6,10 +6,11 @@ not been built the binding raises instead of falling back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
-import math
 import os
 import threading
+import weakref
 from typing import Dict, Optional, Tuple
 
 import torch
@@ -71,6 +72,9 @@ _i64, _u32, _dbl, _vp, _int, _sz = (ctypes.c_int64, ctypes.c_uint32, ctypes.c_do
                                      ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t)
 
 _SIGS = {
+    "mihs_momentum_cor4": (_int, [_dbl, _i64, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+    "mihs_momentum_thm1": (_int, [_dbl, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+    "mihs_lambda_from_log": (_int, [_dbl, ctypes.POINTER(_dbl)]),
     "mihs_create": (_int, [ctypes.POINTER(_vp), _int]),
     "mihs_destroy": (_int, [_vp]),
     "mihs_status_string": (ctypes.c_char_p, [_int]),
@@ -119,12 +123,15 @@ _SIGS = {
                                      _vp]),
     "mihs_batched_plan_destroy": (_int, [_vp]),
     "mihs_tune_batched": (_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, _int, _dbl, _dbl, _i64,
-                                 _i64, _i64, _vp, _sz, _vp, _vp, _vp, _vp]),
+                                 _i64, _i64, ctypes.c_int32, _vp, _sz, _vp, _vp, _vp, _vp]),
+    "mihs_tuning_cache_save": (_int, [_vp, ctypes.c_char_p]),
+    "mihs_tuning_cache_load": (_int, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
+    "mihs_batched_cached_tuning": (_int, [_vp, _vp, _i64, _i64, _vp]),
     "mihs_solve_backward_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int,
                                                   ctypes.POINTER(_sz)]),
     "mihs_solve_backward": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _i64, _i64, _dbl, _int,
                                    _vp, _vp, _i64, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp,
-                                   _vp, _vp, _vp, _sz, _vp]),
+                                   _vp, _vp, _vp, _vp, _sz, _vp]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -132,6 +139,29 @@ EXPORTED = tuple(_SIGS)
 _lib = None
 _lock = threading.Lock()
 _handles: Dict[int, int] = {}
+_plans = weakref.WeakSet()  # live BatchedSolver objects, released at exit
+_closed = False
+
+
+def release_all():
+    """Destroy every live batched plan and every handle (host memory only) while
+    the process is still whole; runs at exit too (atexit handlers run before the
+    HIP runtime is torn down), so no destructor calls into the library at
+    interpreter shutdown.  The binding cannot be used afterwards."""
+    global _closed
+    with _lock:
+        if _closed or _lib is None:
+            _closed = True
+            return
+        _closed = True
+        for s in list(_plans):
+            s.close()
+        for dev, h in list(_handles.items()):
+            _lib.mihs_destroy(h)
+        _handles.clear()
+
+
+atexit.register(release_all)
 
 
 def load_library(path: str = LIB_PATH):
@@ -157,6 +187,8 @@ def _check(rc: int, what: str):
 
 
 def handle(device: Optional[int] = None) -> int:
+    if _closed:
+        raise MihsError("libmihs handles were released at exit")
     dev = torch.cuda.current_device() if device is None else int(device)
     with _lock:
         h = _handles.get(dev)
@@ -200,11 +232,29 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def momentum(sd: float, m: int) -> Tuple[float, float]:
-    """Corollary 4: beta = sd/m, alpha = (1 - beta)^2."""
-    beta = float(sd) / float(m)
-    if not 0.0 < beta < 1.0:
+    """Corollary 4 momentum (alpha, beta) for statistical dimension sd and a
+    sketch of m rows, from mihs_momentum_cor4."""
+    a, b = _dbl(), _dbl()
+    if load_library().mihs_momentum_cor4(float(sd), int(m), ctypes.byref(a), ctypes.byref(b)):
         raise ValueError("need 0 < sd < m")
-    return (1.0 - beta) ** 2, beta
+    return a.value, b.value
+
+
+def momentum_thm1(eps: float) -> Tuple[float, float]:
+    """Theorem 1 momentum (alpha*, beta*) for embedding distortion eps, from
+    mihs_momentum_thm1."""
+    a, b = _dbl(), _dbl()
+    if load_library().mihs_momentum_thm1(float(eps), ctypes.byref(a), ctypes.byref(b)):
+        raise ValueError("need 0 < eps < 1")
+    return a.value, b.value
+
+
+def lambda_from_log(log_lambda: float) -> float:
+    """lambda of the log(lambda) parametrisation, from mihs_lambda_from_log."""
+    v = _dbl()
+    _check(load_library().mihs_lambda_from_log(float(log_lambda), ctypes.byref(v)),
+           "mihs_lambda_from_log")
+    return v.value
 
 
 def mihs_sketch(A: torch.Tensor, kind: str, m: int, seed: int, precision: str = "plain",
@@ -488,9 +538,11 @@ def mihs_solve_pd_dual(At: torch.Tensor, b: torch.Tensor, lam: float, Q: torch.T
 def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: torch.Tensor,
                         Gbar: torch.Tensor, alpha: float, beta: float, eps_sub: float = 1e-2,
                         tol: float = 1e-12, max_outer: int = 300, max_inner: int = 1000,
-                        want_dB: bool = True, precision: Optional[str] = None):
+                        want_dB: bool = True, precision: Optional[str] = None,
+                        want_dloglam: bool = False):
     """Adjoint M-IHS solves W = (A^T A + lambda I)^{-1} Gbar; dB = A W;
-    dlambda = -sum X*.W.  Returns (W, dB or None, dlambda (0-d tensor), infos)."""
+    dlambda = -sum X*.W.  Returns (W, dB or None, dlambda (0-d tensor), infos),
+    or with want_dloglam (W, dB, dlambda, dloglambda, infos)."""
     if precision is None:
         precision = "mixed" if SA.dtype == torch.float32 else "plain"
     p = PRECISIONS[precision]
@@ -505,6 +557,7 @@ def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: to
     W = torch.zeros((d, k), dtype=torch.float64, device=dev)
     dB = torch.zeros((n, k), dtype=torch.float64, device=dev) if want_dB else None
     dlam = torch.zeros((), dtype=torch.float64, device=dev)
+    dll = torch.zeros((), dtype=torch.float64, device=dev) if want_dloglam else None
     info = torch.zeros(INFO_BYTES * k, dtype=torch.uint8, device=dev)
     lib = load_library()
     h = handle(dev.index)
@@ -517,9 +570,12 @@ def mihs_solve_backward(A: torch.Tensor, SA: torch.Tensor, lam: float, Xstar: to
                                  Gb.data_ptr(), k, float(alpha), float(beta), float(eps_sub),
                                  float(tol), int(max_outer), int(max_inner), W.data_ptr(),
                                  dB.data_ptr() if dB is not None else None, dlam.data_ptr(),
+                                 dll.data_ptr() if dll is not None else None,
                                  info.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev))
     _check(rc, "mihs_solve_backward")
     torch.cuda.synchronize(dev)
+    if want_dloglam:
+        return W, dB, dlam, dll, info_to_dict(info)
     return W, dB, dlam, info_to_dict(info)
 
 
@@ -602,6 +658,22 @@ def batched_schedule(shapes, nlam: int, num_cu: int, tuning: Optional[dict] = No
     return {"team0": list(t0), "tsize": list(ts), "tcg": list(tc)}
 
 
+def tuning_cache_save(path: str, device: Optional[int] = None) -> None:
+    """Write the batched launch shapes tuned in this process (on `device`) to a
+    JSON tuning-cache file (mihs_tuning_cache_save)."""
+    _check(load_library().mihs_tuning_cache_save(handle(device), os.fsencode(path)),
+           "mihs_tuning_cache_save")
+
+
+def tuning_cache_load(path: str, device: Optional[int] = None) -> int:
+    """Take the shapes of a tuning-cache file written on the same kind of
+    device (mihs_tuning_cache_load); returns how many were taken."""
+    n = ctypes.c_int32()
+    _check(load_library().mihs_tuning_cache_load(handle(device), os.fsencode(path),
+                                                 ctypes.byref(n)), "mihs_tuning_cache_load")
+    return n.value
+
+
 def sketch_workspace_bytes(n: int, d: int, m: int, kind: str, precision: str = "plain",
                            a_dtype: torch.dtype = torch.float64, m2: int = 0,
                            device: Optional[int] = None) -> int:
@@ -674,6 +746,7 @@ class BatchedSolver:
         self.ws = _workspace(ws_n.value, self.dev)
         self.plan = None
         self._make_plan(tuning)
+        _plans.add(self)
 
     def _make_plan(self, tuning: Optional[dict]):
         lib = load_library()
@@ -694,14 +767,32 @@ class BatchedSolver:
             "mihs_batched_plan_create")
         self.plan = plan
 
-    def tune(self, trial_outer: int = 8, measure: bool = True) -> dict:
+    def cached_tuning(self) -> Optional[dict]:
+        """The shape the handle keeps for this problem set (from an earlier
+        tune() or a loaded tuning cache), or None."""
+        t = Tuning()
+        rc = load_library().mihs_batched_cached_tuning(self.h, ctypes.cast(self.table, _vp),
+                                                       self.nprob, self.nlam, ctypes.byref(t))
+        return t.as_dict() if rc == MIHS_OK else None
+
+    def tune(self, trial_outer: int = 8, measure: bool = True, allow_exact: bool = False,
+             cache: Optional[str] = None) -> dict:
         """Autotune the launch shape on these problems (blocking; overwrites X)
         and re-plan with the choice: coordinate descent on trial_outer-iteration
-        trials (inexact CG shapes, then exact Cholesky sub-solves), then
-        (measure) full runs of the best of each kind and a schedule sized from
-        the faster one's per-problem times.  Returns the choice and the trial
-        times."""
+        trials of the inexact-CG shapes (with allow_exact also exact Cholesky
+        sub-solves), then (measure) full runs of the best of each kind and a
+        schedule sized from the faster one's per-problem times.  Returns the
+        choice and the trial times.  With `cache` (a tuning-cache file) a shape
+        stored there for this problem set is used without tuning (if it obeys
+        allow_exact), and a new one is written there after tuning."""
         lib = load_library()
+        if cache is not None:
+            if os.path.exists(cache):
+                tuning_cache_load(cache, self.dev.index)
+            got = self.cached_tuning()
+            if got is not None and (allow_exact or not got["exact"]):
+                self._make_plan(got)
+                return {"best": got, "trial_ms": [], "from_cache": True}
         eps_sub, tol, max_outer, max_inner = self.params
         best = Tuning()
         times = (ctypes.c_float * TUNE_MAX_CANDIDATES)()
@@ -709,10 +800,13 @@ class BatchedSolver:
         _check(lib.mihs_tune_batched(
             self.h, ctypes.cast(self.table, _vp), self.nprob, self.lam.data_ptr(),
             self.alp.data_ptr(), self.bet.data_ptr(), self.nlam, self.precision, eps_sub, tol,
-            int(trial_outer), int(max_outer) if measure else 0, max_inner, self.ws.data_ptr(),
+            int(trial_outer), int(max_outer) if measure else 0, max_inner,
+            1 if allow_exact else 0, self.ws.data_ptr(),
             self.ws.numel(), _stream(self.dev),
             ctypes.byref(best), times, ctypes.byref(nc)), "mihs_tune_batched")
         self._make_plan(best.as_dict())
+        if cache is not None:
+            tuning_cache_save(cache, self.dev.index)
         return {"best": best.as_dict(), "trial_ms": [round(times[i], 3) for i in range(nc.value)]}
 
     def run(self):
@@ -736,13 +830,19 @@ class BatchedSolver:
         raw = info_to_dict(self.info_all)
         return [raw[i * self.nlam:(i + 1) * self.nlam] for i in range(self.nprob)]
 
+    def close(self):
+        """Free the plan (host memory only); the solver cannot run afterwards."""
+        if self.plan is not None and _lib is not None:
+            _lib.mihs_batched_plan_destroy(self.plan)
+        self.plan = None
+
     def __del__(self):
-        try:
-            if self.plan is not None and _lib is not None:
-                _lib.mihs_batched_plan_destroy(self.plan)
-                self.plan = None
-        except Exception:
-            pass
+        # at interpreter shutdown the atexit hook has already released the plan
+        if not _closed:
+            try:
+                self.close()
+            except Exception:
+                pass
 
 
 def mihs_solve_multi(A: torch.Tensor, B: torch.Tensor, lam: float, SA: torch.Tensor,
@@ -793,7 +893,7 @@ class MIHSRidge(torch.autograd.Function):
     @staticmethod
     def forward(ctx, B, log_lam, A, SA, alpha, beta, kw):
         kw = dict(kw or {})
-        lam = float(torch.exp(log_lam.detach().to(torch.float64)))
+        lam = lambda_from_log(float(log_lam.detach()))
         X, infos = mihs_solve_multi(A, B.detach(), lam, SA, alpha, beta, **kw)
         ctx.save_for_backward(X)
         ctx.A, ctx.SA, ctx.lam, ctx.alpha, ctx.beta, ctx.kw = A, SA, lam, alpha, beta, kw
@@ -805,7 +905,7 @@ class MIHSRidge(torch.autograd.Function):
         (X,) = ctx.saved_tensors
         kw = {k: v for k, v in ctx.kw.items() if k in ("eps_sub", "tol", "max_outer", "max_inner",
                                                       "precision")}
-        W, dB, dlam, _ = mihs_solve_backward(ctx.A, ctx.SA, ctx.lam, X, gX.contiguous(),
-                                             ctx.alpha, ctx.beta, want_dB=True, **kw)
-        dloglam = (dlam * ctx.lam).reshape(())
+        _, dB, _, dloglam, _ = mihs_solve_backward(ctx.A, ctx.SA, ctx.lam, X, gX.contiguous(),
+                                                   ctx.alpha, ctx.beta, want_dB=True,
+                                                   want_dloglam=True, **kw)
         return dB, dloglam, None, None, None, None, None

@@ -29,18 +29,30 @@ CXXFLAGS = [
 ]
 
 
+# Host-only C++ (no device code): built by the host compiler, which also builds
+# it under the sanitizers in the CPU tests.
+HOSTCXX = os.environ.get("CXX", "g++")
+HOST_CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
+                 "-I/opt/rocm/include"]
+
+
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                  if f.endswith(".hip") or f.endswith(".cpp"))
 
 
 def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *CXXFLAGS, "-c", src, "-o", obj]
+    stem, ext = os.path.splitext(os.path.basename(src))
+    obj = os.path.join(BUILD, stem + ".o")
+    if ext == ".cpp":
+        cmd = [HOSTCXX, *HOST_CXXFLAGS, "-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC, *CXXFLAGS, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")
     if verbose and r.stderr.strip():
         print(r.stderr, file=sys.stderr)
     return obj

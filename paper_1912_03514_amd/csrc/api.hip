@@ -427,8 +427,8 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
                         double lambda, mihs_precision_t precision, const double* Xstar,
                         const double* Gbar, int64_t k, double alpha, double beta,
                         double eps_sub, double tol, int64_t max_outer, int64_t max_inner,
-                        double* W, double* dB, double* dlambda, mihs_info_t* d_info,
-                        void* workspace, size_t ws_bytes, void* stream) {
+                        double* W, double* dB, double* dlambda, double* dloglambda,
+                        mihs_info_t* d_info, void* workspace, size_t ws_bytes, void* stream) {
   if (!handle) return MIHS_ERR_INVALID;
   int rc = check_solve_common(A, a_dtype, n, d, lda, lambda, SA, m, ldsa, precision, alpha, beta,
                               eps_sub, max_outer, max_inner);
@@ -443,7 +443,8 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
   const size_t params = align_up(3 * 16 * sizeof(double), 256);
   // The adjoint systems (A^T A + lambda I) w_j = gbar_j share A, SA and lambda:
   // M-IHS from w = 0 with gradient gbar_j - A^T A w_j - lambda w_j.
-  if (hipMemsetAsync(W, 0, (size_t)d * k * sizeof(double), st) != hipSuccess) return MIHS_ERR_HIP;
+  rc = mihs::launch_fill(W, 0.0, d * k, st);
+  if (rc) return rc;
   if (d <= mihs::block_max_d()) {
     double* pl = (double*)base;
     rc = mihs::launch_fill(pl, lambda, 16, st);
@@ -490,8 +491,8 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
       if (hipMemcpy2DAsync(g_col, sizeof(double), Gbar + j, (size_t)k * sizeof(double),
                            sizeof(double), (size_t)d, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return MIHS_ERR_HIP;
-      if (hipMemsetAsync(w_col, 0, (size_t)d * sizeof(double), st) != hipSuccess)
-        return MIHS_ERR_HIP;
+      rc = mihs::launch_fill(w_col, 0.0, d, st);
+      if (rc) return rc;
       mihs::SolveDesc s;
       s.A = A;
       s.a_f32 = a_dtype == MIHS_F32;
@@ -525,7 +526,7 @@ int mihs_solve_backward(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtyp
     rc = mihs::launch_apply_rows(handle, A, a_dtype == MIHS_F32, n, d, lda, W, k, dB, k, st);
     if (rc) return rc;
   }
-  return mihs::launch_neg_dot(Xstar, W, d * k, dlambda, st);
+  return mihs::launch_neg_dot(Xstar, W, d * k, lambda, dlambda, dloglambda, st);
 }
 
 int mihs_solve_multi_workspace_size(mihs_handle_t handle, int64_t n, int64_t d, int64_t m,
@@ -734,13 +735,27 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan) {
   return MIHS_OK;
 }
 
+int mihs_batched_cached_tuning(mihs_handle_t handle, const mihs_problem_t* h_problems,
+                               int64_t nprob, int64_t nlam, mihs_batched_tuning_t* tuning) {
+  if (!handle || !h_problems || !tuning || nprob < 1 || nlam < 1) return MIHS_ERR_INVALID;
+  for (int64_t p = 0; p < nprob; ++p)
+    if (h_problems[p].n < 1 || h_problems[p].d < 1 || h_problems[p].m < 1)
+      return MIHS_ERR_INVALID;
+  std::vector<mihs::BlockEntryDesc> ents;
+  batched_entries(h_problems, nprob, nullptr, nullptr, nullptr, nlam, &ents);
+  return mihs::block_tuning_lookup(handle, ents.data(), (int64_t)ents.size(), tuning)
+             ? MIHS_OK
+             : MIHS_ERR_UNSUPPORTED;
+}
+
 int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, int64_t nprob,
                       const double* lambdas, const double* alphas, const double* betas,
                       int64_t nlam, mihs_precision_t precision, double eps_sub, double tol,
                       int64_t trial_outer, int64_t measure_outer, int64_t max_inner,
-                      void* workspace, size_t ws_bytes, void* stream,
+                      int32_t allow_exact, void* workspace, size_t ws_bytes, void* stream,
                       mihs_batched_tuning_t* best, float* cand_ms, int32_t* ncand) {
   if (!best || trial_outer < 1 || measure_outer < 0) return MIHS_ERR_INVALID;
+  if (allow_exact != 0 && allow_exact != 1) return MIHS_ERR_INVALID;
   int rc = check_batched(handle, h_problems, nprob, lambdas, alphas, betas, nlam, precision,
                          eps_sub, trial_outer, max_inner);
   if (rc) return rc;
@@ -826,7 +841,7 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
   mihs_batched_tuning_t ex = cur;
   float ex_ms = 0.0f;
   const double exact_weights[] = {6.25, 25.0};
-  for (int wi = 0; wi < 2 && !rc; ++wi) {
+  for (int wi = 0; wi < 2 && !rc && allow_exact; ++wi) {
     mihs_batched_tuning_t t = cur;
     t.exact = 1;
     t.inner_weight = exact_weights[wi];
@@ -837,7 +852,7 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
       ex_ms = ms;
     }
   }
-  if (!rc && measure_outer == 0 && ex_ms < cur_ms) {
+  if (!rc && allow_exact && measure_outer == 0 && ex_ms < cur_ms) {
     cur = ex;
     cur_ms = ex_ms;
   }
@@ -863,7 +878,7 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
     };
     float ms = 0.0f;
     rc = full_run(cur, &cur_ms, &cost);
-    if (!rc) {
+    if (!rc && allow_exact) {
       std::vector<double> ex_cost;
       float full_ex = 0.0f;
       rc = full_run(ex, &full_ex, &ex_cost);

@@ -1287,159 +1287,7 @@ int dp_for(int64_t d) {
 
 int block_max_d() { return 1024; }
 
-bool block_tuning_valid(const mihs_batched_tuning_t& t) {
-  return (t.cg_cols == 16 || t.cg_cols == 32 || t.cg_cols == 64 || t.cg_cols == 512) &&
-         (t.a_dma == 0 || t.a_dma == 1) && t.inner_weight >= 1.0 && t.inner_weight <= 1e4 &&
-         (t.measured == 0 || t.measured == 1) && (t.exact == 0 || t.exact == 1);
-}
-
 namespace {
-
-// Deterministic schedule of the entries over G workgroups (also used to size
-// the workspace): dedicated teams for heavy entries, single-workgroup bins for
-// the rest.
-struct Schedule {
-  std::vector<int> team0, tsize, tcg;
-  std::vector<std::vector<int>> items;
-  size_t stride = 1;
-};
-
-// Sizing from measured costs c_i (entry i on one workgroup): the smallest
-// makespan L (bisection) for which teams of ceil(c_i / L) workgroups for the
-// entries above L and first-fit-decreasing bins of capacity L for the rest
-// (team members offering what their team entry leaves of L) fit
-// in G workgroups.
-bool makespan_schedule(const std::vector<double>& c, int G, double L, Schedule* S) {
-  const int64_t count = (int64_t)c.size();
-  std::vector<int64_t> order(count);
-  for (int64_t i = 0; i < count; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return c[x] > c[y]; });
-  S->team0.assign(count, 0);
-  S->tsize.assign(count, 1);
-  S->tcg.assign(count, 1);
-  S->items.assign(G, std::vector<int>());
-  std::vector<double> load(G, 0.0);
-  int next = 0;
-  for (int64_t i : order) {
-    if (c[i] <= L) break;
-    const int t = (int)std::ceil(c[i] / L - 1e-9);
-    if (next + t > G) return false;
-    S->team0[i] = next;
-    S->tsize[i] = t;
-    for (int u = 0; u < t; ++u) {
-      S->items[next + u].push_back((int)i);
-      load[next + u] = c[i] / t;
-    }
-    next += t;
-  }
-  // the rest first-fit in decreasing cost over every workgroup, the team
-  // members' remaining capacity included (a team entry always comes first in
-  // its members' lists, so no team waits on a member busy elsewhere)
-  for (int64_t i : order) {
-    if (c[i] > L) continue;
-    int g = 0;
-    while (g < G && load[g] + c[i] > L * (1.0 + 1e-9)) ++g;
-    if (g == G) return false;
-    load[g] += c[i];
-    S->team0[i] = g;
-    S->items[g].push_back((int)i);
-  }
-  return true;
-}
-
-int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
-                  const mihs_batched_tuning_t& tn, const std::vector<double>* cost,
-                  Schedule* S) {
-  if (tn.measured && cost && (int64_t)cost->size() == count) {
-    double hi = 0.0, sum = 0.0;
-    for (double v : *cost) {
-      hi = std::max(hi, std::max(v, 1.0));
-      sum += std::max(v, 1.0);
-    }
-    std::vector<double> c(count);
-    for (int64_t i = 0; i < count; ++i) c[i] = std::max((*cost)[i], 1.0);
-    double lo = std::max(sum / G, 1.0);
-    hi = std::max(hi, sum);  // one entry per workgroup in turn always fits when count <= G
-    Schedule T;
-    if (!makespan_schedule(c, G, hi, &T)) return MIHS_ERR_UNSUPPORTED;
-    for (int it = 0; it < 48 && hi > lo * (1.0 + 1e-4); ++it) {
-      const double mid = 0.5 * (lo + hi);
-      Schedule U;
-      if (makespan_schedule(c, G, mid, &U)) {
-        hi = mid;
-        T = U;
-      } else {
-        lo = mid;
-      }
-    }
-    *S = T;
-    for (int64_t i = 0; i < count; ++i)
-      S->tcg[i] = tn.exact ? std::min(S->tsize[i], KR) : std::max(
-          1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
-    S->stride = 1;
-    for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
-    return MIHS_OK;
-  }
-  // weight: one A pass plus the expected inner solve on H per outer iteration
-  // (inner_weight passes over H; lockstep CGs over 16 lambdas down to
-  // 1e-6 sigma_1^2 take ~100 steps)
-  std::vector<double> wgt(count);
-  double total = 0.0;
-  for (int64_t i = 0; i < count; ++i) {
-    wgt[i] = (double)ents[i].n * ents[i].d + tn.inner_weight * (double)ents[i].d * ents[i].d;
-    total += wgt[i];
-  }
-  std::vector<int64_t> order(count);
-  for (int64_t i = 0; i < count; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int64_t x, int64_t y) { return wgt[x] > wgt[y]; });
-  S->team0.assign(count, 0);
-  S->tsize.assign(count, 1);
-  S->tcg.assign(count, 1);
-  S->items.assign(G, std::vector<int>());
-  // An entry gets a share of the still-free workgroups proportional to its
-  // share of the still-unassigned weight, keeping one workgroup free while
-  // other entries remain; entries worth fewer than two go to the bins.
-  int next = 0;
-  int64_t first_small = count;
-  double left = total;
-  for (int64_t oi = 0; oi < count; ++oi) {
-    const int64_t i = order[oi];
-    const int free_wg = G - next;
-    const int reserve = (oi + 1 < count) ? 1 : 0;
-    int want = (int)std::floor(wgt[i] / left * free_wg + 0.5);
-    want = std::min(want, free_wg - reserve);
-    if (want < 2) {
-      first_small = oi;
-      break;
-    }
-    S->team0[i] = next;
-    S->tsize[i] = want;
-    for (int t = 0; t < want; ++t) S->items[next + t].push_back((int)i);
-    next += want;
-    left -= wgt[i];
-  }
-  std::vector<double> load(G, 0.0);
-  for (int64_t oi = first_small; oi < count; ++oi) {
-    const int64_t i = order[oi];
-    if (next >= G) return MIHS_ERR_UNSUPPORTED;
-    int best = next;
-    for (int g = next; g < G; ++g)
-      if (load[g] < load[best]) best = g;
-    S->team0[i] = best;
-    S->tsize[i] = 1;
-    S->items[best].push_back((int)i);
-    load[best] += wgt[i];
-  }
-  // CG sub-team: about cg_cols columns of H per member, at most the whole team
-  // (exact sub-solves: every member up to one per column)
-  for (int64_t i = 0; i < count; ++i)
-    S->tcg[i] = tn.exact ? std::min(S->tsize[i], KR) : std::max(
-        1, std::min(S->tsize[i], (int)((ents[i].d + tn.cg_cols - 1) / tn.cg_cols)));
-  S->stride = 1;
-  for (int g = 0; g < G; ++g) S->stride = std::max(S->stride, S->items[g].size() + 1);
-  return MIHS_OK;
-}
 
 // Distinct sketches (by group id) in order of first appearance.
 std::vector<int64_t> group_leaders(const BlockEntryDesc* ents, int64_t count) {
@@ -1655,15 +1503,6 @@ __global__ void clear_words(unsigned* p, int64_t count) {
     p[i] = 0u;
 }
 
-uint64_t mix64(uint64_t h, uint64_t v) {
-  // FNV-1a over the 8 bytes of v
-  for (int b = 0; b < 8; ++b) {
-    h ^= (v >> (8 * b)) & 0xFFu;
-    h *= 1099511628211ull;
-  }
-  return h;
-}
-
 }  // namespace
 
 struct BlockPlan {
@@ -1697,57 +1536,6 @@ size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, i
   const size_t base = block_layout(ents, count, S, G, true).total;
   const size_t extra = (size_t)G * ((size_t)dpmax * KR + kNScal) * sizeof(double) + 256 * (size_t)count;
   return base + extra;
-}
-
-uint64_t block_signature(const BlockEntryDesc* ents, int64_t count) {
-  uint64_t s = 1469598103934665603ull;
-  s = mix64(s, (uint64_t)count);
-  for (int64_t i = 0; i < count; ++i) {
-    s = mix64(s, (uint64_t)ents[i].n);
-    s = mix64(s, (uint64_t)ents[i].d);
-    s = mix64(s, (uint64_t)ents[i].m);
-    s = mix64(s, (uint64_t)ents[i].ncols);
-    s = mix64(s, (uint64_t)ents[i].sa_group);
-  }
-  return s;
-}
-
-mihs_batched_tuning_t block_tuning_for(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
-                                       std::vector<double>* cost) {
-  mihs_batched_tuning_t tn;
-  mihs_batched_default_tuning(&tn);
-  if (cost) cost->clear();
-  const uint64_t key = block_signature(ents, count);
-  std::lock_guard<std::mutex> lock(h->tune_mu);
-  for (const auto& t : h->tuned)
-    if (t.key == key) {
-      if (cost) *cost = t.cost;
-      return t.tuning;
-    }
-  return tn;
-}
-
-void block_tuning_store(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
-                        const mihs_batched_tuning_t& tuning, const std::vector<double>& cost) {
-  const uint64_t key = block_signature(ents, count);
-  std::lock_guard<std::mutex> lock(h->tune_mu);
-  for (auto& t : h->tuned)
-    if (t.key == key) {
-      t.tuning = tuning;
-      t.cost = cost;
-      return;
-    }
-  h->tuned.push_back(mihs_tuned_set{key, tuning, cost});
-}
-
-int block_team_sizes(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
-                     const mihs_batched_tuning_t& tuning, const std::vector<double>* cost,
-                     std::vector<int>* tsize) {
-  Schedule S;
-  const int rc = make_schedule(ents, count, h->num_cu, tuning, cost, &S);
-  if (rc) return rc;
-  *tsize = S.tsize;
-  return MIHS_OK;
 }
 
 int plan_block(const mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int a_f32,
@@ -1955,45 +1743,3 @@ int launch_block(mihs_handle* h, const BlockEntryDesc* ents, int64_t count, int 
 
 }  // namespace mihs
 
-extern "C" int mihs_batched_schedule(int32_t num_cu, const int64_t* n, const int64_t* d,
-                                     int64_t nprob, int64_t nlam,
-                                     const mihs_batched_tuning_t* tuning, const double* cost,
-                                     int32_t* team0, int32_t* tsize, int32_t* tcg) {
-  if (num_cu < 1 || !n || !d || nprob < 1 || nlam < 1 || !tuning || !team0 || !tsize || !tcg)
-    return MIHS_ERR_INVALID;
-  if (!mihs::block_tuning_valid(*tuning)) return MIHS_ERR_INVALID;
-  std::vector<mihs::BlockEntryDesc> ents;
-  for (int64_t p = 0; p < nprob; ++p) {
-    if (n[p] < 1 || d[p] < 1 || n[p] < d[p]) return MIHS_ERR_INVALID;
-    for (int64_t g0 = 0; g0 < nlam; g0 += 16) {
-      mihs::BlockEntryDesc e;
-      memset(&e, 0, sizeof(e));
-      e.n = n[p];
-      e.d = d[p];
-      e.ncols = (int)((nlam - g0) < 16 ? (nlam - g0) : 16);
-      e.sa_group = p;
-      ents.push_back(e);
-    }
-  }
-  const int64_t count = (int64_t)ents.size();
-  std::vector<double> c;
-  if (cost) c.assign(cost, cost + count);
-  mihs::Schedule S;
-  const int rc = mihs::make_schedule(ents.data(), count, num_cu, *tuning, cost ? &c : nullptr, &S);
-  if (rc) return rc;
-  for (int64_t i = 0; i < count; ++i) {
-    team0[i] = S.team0[i];
-    tsize[i] = S.tsize[i];
-    tcg[i] = S.tcg[i];
-  }
-  return MIHS_OK;
-}
-
-extern "C" void mihs_batched_default_tuning(mihs_batched_tuning_t* t) {
-  if (!t) return;
-  t->cg_cols = 32;
-  t->a_dma = 1;
-  t->inner_weight = 100.0;
-  t->measured = 0;
-  t->exact = 0;
-}

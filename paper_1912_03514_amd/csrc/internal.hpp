@@ -1,7 +1,7 @@
 // Internal host-side interfaces between the C ABI layer and the kernel files.
 #pragma once
 
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -32,6 +32,7 @@ namespace mihs {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+
 // Padded vector length used by the row kernels: 64 lanes x elements-per-lane.
 int ept_for(int64_t d);
 inline int64_t dpad_for(int64_t d) { return 64 * (int64_t)ept_for(d); }
@@ -61,6 +62,10 @@ struct SolveDesc {
   // 1: the Gram matrix of SA is already in this workspace (an earlier call with
   // the same SA and workspace formed it)
   int gram_ready = 0;
+  // launch shape; 0 = chosen from the sizes: workgroups of the inner-solve
+  // group, and the fewest rows of A per workgroup
+  int cg_groups = 0;
+  int64_t rows_per_wg = 0;
 };
 
 // g = A^T (c - A x) + rhs - lambda x (c and rhs may be null) for A n x d, d <= 4096;
@@ -139,10 +144,26 @@ size_t block_workspace_bytes(const mihs_handle* h, const BlockEntryDesc* ents, i
 // Key of a problem set for the tuning cache: (n, d, m, ncols, sketch group) of each entry.
 uint64_t block_signature(const BlockEntryDesc* ents, int64_t count);
 bool block_tuning_valid(const mihs_batched_tuning_t& t);
+// Right-hand sides per block entry (one matrix-core column block).
+constexpr int kBlockRhs = 16;
+// Deterministic schedule of the entries over G workgroups (also used to size
+// the workspace): dedicated teams for heavy entries, single-workgroup bins for
+// the rest; items[g] lists workgroup g's entries in order.
+struct Schedule {
+  std::vector<int> team0, tsize, tcg;
+  std::vector<std::vector<int>> items;
+  size_t stride = 1;
+};
+int make_schedule(const BlockEntryDesc* ents, int64_t count, int G,
+                  const mihs_batched_tuning_t& tn, const std::vector<double>* cost,
+                  Schedule* S);
 // The tuned shape for this set if the handle has one, else the defaults; the
 // measured per-entry costs go to *cost (empty if none).
 mihs_batched_tuning_t block_tuning_for(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
                                        std::vector<double>* cost);
+// The tuned shape kept for this set, if any.
+bool block_tuning_lookup(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
+                         mihs_batched_tuning_t* tuning);
 // Keep a tuned shape (and its measured costs) for this set.
 void block_tuning_store(mihs_handle* h, const BlockEntryDesc* ents, int64_t count,
                         const mihs_batched_tuning_t& tuning, const std::vector<double>& cost);
@@ -185,8 +206,9 @@ int launch_apply_rows(const mihs_handle* h, const void* A, int a_f32, int64_t n,
                       hipStream_t stream);
 // p[0..count) = value
 int launch_fill(double* p, double value, int64_t count, hipStream_t stream);
-// out = -sum over all entries of X .* W (d x k); one device double.
-int launch_neg_dot(const double* X, const double* W, int64_t count, double* out,
-                   hipStream_t stream);
+// out = -sum over all entries of X .* W (d x k), one device double; out_log
+// (nullable) = lam * out.
+int launch_neg_dot(const double* X, const double* W, int64_t count, double lam, double* out,
+                   double* out_log, hipStream_t stream);
 
 }  // namespace mihs

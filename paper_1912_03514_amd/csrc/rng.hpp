@@ -82,4 +82,29 @@ __device__ __forceinline__ void gaussian_block(uint32_t seed, uint64_t stream, u
   }
 }
 
+// The same four draws in FP32 for the mixed path, whose Gaussian entries are
+// rounded to BF16 (8 significant bits) afterwards: the uniforms as above,
+// rad = sqrt(-2 ln 2 log2(u_a)) and (cos, sin)(2 pi u_b) on the hardware's
+// log2 / sine / cosine units (v_sin_f32 and v_cos_f32 take their argument in
+// revolutions).  Relative error a few units of 2^-24, so the BF16 value equals
+// the rounding of the FP64 draw except where the FP64 draw lies within that
+// error of a BF16 rounding boundary (about one entry in 10^4, off by one BF16
+// unit).
+__device__ __forceinline__ void gaussian_block_f32(uint32_t seed, uint64_t stream, uint64_t blk,
+                                                   float out[4]) {
+  const U32x4 w = philox4x32_10((uint32_t)blk, (uint32_t)(blk >> 32), (uint32_t)stream,
+                                (uint32_t)(stream >> 32), seed, 0u);
+  const float two32inv = 2.3283064365386963e-10f;  // 2^-32
+  const float m2ln2 = -1.3862943611198906f;        // -2 ln 2
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    // u = (w + 1/2) 2^-32 in (0, 1]; float(w) keeps 24 bits, plenty for BF16
+    const float ua = ((float)w.v[2 * p] + 0.5f) * two32inv;
+    const float ub = ((float)w.v[2 * p + 1] + 0.5f) * two32inv;
+    const float rad = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(ua));
+    out[2 * p] = rad * __builtin_amdgcn_cosf(ub);
+    out[2 * p + 1] = rad * __builtin_amdgcn_sinf(ub);
+  }
+}
+
 }  // namespace mihs

@@ -260,6 +260,181 @@ __global__ __launch_bounds__(kBlock) void srht_stage2(const TY* __restrict__ Y, 
 }
 
 // ---------------------------------------------------------------------------
+// SRHT in one read of A.  A workgroup of 512 threads owns a strip of 16
+// columns and a range of blocks of B = 2^LOGB consecutive rows.  For each block
+// i_hi it applies D and the length-B transform over i_lo (registers, one LDS
+// transpose), leaving T[k_lo] = sum_{i_lo} (-1)^{popc(k_lo & i_lo)} (D A)[i_hi B + i_lo]
+// in LDS, and then adds every sampled row k = (k_hi, k_lo) with its sign:
+//     acc_k += (-1)^{popc(k_hi & i_hi)} T[k_lo],
+// so that after all blocks acc_k = ((H D A)[idx_k]) restricted to the strip.
+// Thread (c, g), c = t % 16, g = t / 16, owns column c of samples
+// g * NACC .. g * NACC + NACC - 1 in registers.  The next block's rows are
+// loaded while the current one is transformed and accumulated.  The partial
+// sums of the workgroup's block range go to P[part] (or, with one range per
+// strip, scaled straight to SA).
+// ---------------------------------------------------------------------------
+// Mixed CountSketch -> Gaussian: the FP32 bucket sums CA enter the Gaussian
+// stage as three BF16 terms (hi + mid + lo), so that the BF16 products keep
+// CA's FP32 accuracy; rounding CA itself to BF16 (2^-9 relative) perturbs
+// the sketched Hessian by more than lambda on ill-conditioned problems.
+constexpr int kCountGaussTerms = 3;
+
+constexpr int kFusedThreads = 512;
+constexpr int kBufferRsrcWord3 = 0x00020000;  // raw 32-bit buffer data (gfx9 family)
+constexpr int kBufferNt = 2;                  // cache policy: non-temporal
+constexpr int kFusedW = 16;       // columns per strip
+constexpr int kFusedLdt = kFusedW + 1;
+
+// sign words: bit j of word w is set iff D_{32 w + j} = -1
+__global__ void srht_sign_words_kernel(uint32_t* words, int64_t nwords, uint32_t seed) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nwords) return;
+  uint32_t v = 0u;
+  for (int j = 0; j < 32; ++j)
+    v |= (murmur3_u32((uint32_t)(w * 32 + j), seed) >> 31) << j;
+  words[w] = v;
+}
+
+template <typename TA, typename TY, int LOGB, int NACC, typename TS>
+__global__ __launch_bounds__(kFusedThreads) void srht_fused_kernel(
+    const TA* __restrict__ A, int64_t lda, int64_t d, const uint32_t* __restrict__ signw,
+    const int* __restrict__ idx, int64_t m, int64_t nblk, int nparts, TY* __restrict__ P,
+    int64_t ldp, TS* __restrict__ SA, int64_t ldsa, double scale) {
+  constexpr int B = 1 << LOGB;
+  constexpr int R = B * kFusedW / kFusedThreads;  // rows per thread per phase (16 or 32)
+  static_assert(R == 16 || R == 32, "block shape");
+  extern __shared__ unsigned char smem_raw[];
+  TY* T = (TY*)smem_raw;                                   // B x kFusedLdt
+  int* s_off = (int*)(T + (size_t)B * kFusedLdt);          // 32 * NACC sample row offsets
+  int* s_khi = s_off + 32 * NACC;                          // 32 * NACC sample k_hi
+  const int t = threadIdx.x;
+  const int c = t % kFusedW, g = t / kFusedW;              // g in [0, 32)
+  const int strip = blockIdx.x % (int)((d + kFusedW - 1) / kFusedW);
+  const int part = blockIdx.x / (int)((d + kFusedW - 1) / kFusedW);
+  const int64_t col = (int64_t)strip * kFusedW + c;
+  const bool col_ok = col < d;
+  const int64_t b0 = nblk * part / nparts, b1 = nblk * (part + 1) / nparts;
+
+  for (int k = t; k < 32 * NACC; k += kFusedThreads) {
+    const int v = k < m ? idx[k] : 0;
+    s_off[k] = (v & (B - 1)) * kFusedLdt;
+    s_khi[k] = k < m ? (v >> LOGB) : 0;
+  }
+  TY acc[NACC];
+#pragma unroll
+  for (int j = 0; j < NACC; ++j) acc[j] = TY(0);
+
+  // rows g + 32 i of block b, this thread's column, as buffer loads: the
+  // block's base in a buffer resource, row 32 i's byte offset in a scalar
+  // register and one per-lane byte offset, so that the row addresses do not
+  // each occupy a pair of vector registers.  Non-temporal: A is read once.
+  // Every offset stays below the block's B rows (checked against num_records).
+  TA xa[R];
+  const uint32_t lane_off = (uint32_t)(((int64_t)g * lda + (col_ok ? col : 0)) * sizeof(TA));
+  const int32_t row32 = (int32_t)(32 * lda * (int64_t)sizeof(TA));  // bytes between rows g + 32 i
+  const int32_t blk_bytes = (int32_t)(B * lda * (int64_t)sizeof(TA));
+  auto load_block = [&](int64_t b) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(A + b * B * lda), (short)0, blk_bytes, kBufferRsrcWord3);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if constexpr (sizeof(TA) == 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_off, i * row32, kBufferNt);
+        xa[i] = __builtin_bit_cast(TA, v);
+      } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b32(rs, lane_off, i * row32, kBufferNt);
+        xa[i] = __builtin_bit_cast(TA, v);
+      }
+    }
+  };
+  if (b0 < b1) load_block(b0);
+  for (int64_t b = b0; b < b1; ++b) {
+    // phase 1: D, then the butterflies of row bits 5 .. LOGB-1 (register index bits)
+    TY x[R];
+    const uint32_t* sw = signw + b * (B / 32);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const bool neg = (sw[i] >> g) & 1u;
+      x[i] = neg ? -(TY)xa[i] : (TY)xa[i];
+    }
+    fwht_regs<TY, R>(x);
+    __syncthreads();  // the previous block's accumulation has read T
+#pragma unroll
+    for (int i = 0; i < R; ++i) T[(g + 32 * i) * kFusedLdt + c] = x[i];
+    if (b + 1 < b1) load_block(b + 1);
+    __syncthreads();
+    // phase 2: the butterflies of row bits 0 .. log2(R)-1 on rows R g + i
+    {
+      TY y[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) y[i] = T[(R * g + i) * kFusedLdt + c];
+      fwht_regs<TY, R>(y);
+      if constexpr (R == 16) {
+        // row bit 4: rows 16 g + i and 16 (g ^ 1) + i live in threads t and t ^ 16
+        // (the same wave)
+        const bool upper = (g & 1) != 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const TY other = __shfl_xor(y[i], kFusedW, kWave);
+          y[i] = upper ? other - y[i] : y[i] + other;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) T[(R * g + i) * kFusedLdt + c] = y[i];
+    }
+    __syncthreads();
+    // every owned sample: acc_k += (-1)^{popc(k_hi & b)} T[k_lo][c], eight
+    // samples at a time (the empty asm keeps the compiler from hoisting every
+    // sample's LDS reads at once, which would not fit in the registers)
+    const uint32_t bb = (uint32_t)b;
+    const TY* Tc = T + c;
+#pragma unroll
+    for (int j0 = 0; j0 < NACC; j0 += 8) {
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int j = j0; j < j0 + 8; ++j) {
+        const int k = g * NACC + j;
+        const TY v = Tc[s_off[k]];
+        const bool neg = (__popc((uint32_t)s_khi[k] & bb) & 1) != 0;
+        acc[j] += neg ? -v : v;
+      }
+    }
+  }
+  if (!col_ok) return;
+  if (nparts == 1) {
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) {
+      const int64_t k = (int64_t)g * NACC + j;
+      if (k < m) SA[k * ldsa + col] = (TS)((double)acc[j] * scale);
+    }
+  } else {
+    TY* Pp = P + (int64_t)part * m * ldp;
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) {
+      const int64_t k = (int64_t)g * NACC + j;
+      if (k < m) Pp[k * ldp + col] = acc[j];
+    }
+  }
+}
+
+// SA[k][col] = scale * sum_{part} P[part][k][col], parts in order.
+template <typename TY, typename TS>
+__global__ void srht_parts_sum_kernel(const TY* __restrict__ P, int nparts, int64_t m, int64_t d,
+                                      int64_t ldp, TS* __restrict__ SA, int64_t ldsa, double scale) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * d) return;
+  const int64_t k = e / d, col = e - k * d;
+  TY s = P[k * ldp + col];
+  for (int q = 1; q < nparts; ++q) s += P[((int64_t)q * m + k) * ldp + col];
+  SA[k * ldsa + col] = (TS)((double)s * scale);
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
 // CountSketch: h = murmur3(i, seed), bucket = h mod m, sign = -1 iff bit 31.
 // Rows are bucketed by a counting sort, each bucket's row list is sorted
 // ascending, then each (bucket, column block) sums its rows in that order, so
@@ -402,19 +577,25 @@ __global__ void gauss_gen_kernel(TSel* S, int64_t M, int64_t K, int64_t lds, uin
   const int64_t total = M * K;
   const int64_t first = e * 4;
   if (first >= total) return;
+  // FP64 draws for the FP64 sketch; FP32 draws for the BF16 sketch (rounded to
+  // 8 significant bits anyway)
   double z[4];
-  gaussian_block(seed, stream, (uint64_t)e, z);
+  float zf[4];
+  if constexpr (sizeof(TSel) == 8)
+    gaussian_block(seed, stream, (uint64_t)e, z);
+  else
+    gaussian_block_f32(seed, stream, (uint64_t)e, zf);
+  const float scale_f = (float)scale;
   // row and column of the first element (one 64-bit division per thread), then
   // step along the row with wrap-around
   int64_t i = first / K, j = first - i * K;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     if (first + t < total) {
-      const double v = z[t] * scale;
       if constexpr (sizeof(TSel) == 8) {
-        S[i * lds + j] = v;
+        S[i * lds + j] = z[t] * scale;
       } else {
-        S[i * lds + j] = bf16_rne(v);
+        S[i * lds + j] = bf16_rne(zf[t] * scale_f);
       }
     }
     if (++j == K) {
@@ -521,6 +702,47 @@ __global__ __launch_bounds__(kBlock) void bf16_transpose_kernel(const TB* __rest
     const int nn = ty + 4 * i;
     const int64_t gn = n0 + nn, gk = k0 + tx;
     if (gn < N && gk < ldbt) Bt[gn * ldbt + gk] = tile[tx][nn];
+  }
+}
+
+// The three-term BF16 split of B^T for products that must keep B's FP32
+// accuracy: Bt_t (t = 0, 1, 2; stride part_stride) holds hi, mid, lo with
+// hi = bf16(v), mid = bf16(v - hi), lo = bf16(v - hi - mid) for v = B[k, n]
+// (each difference is exact in FP32), so that hi + mid + lo equals v to about
+// 2^-24 relative and S (hi + mid + lo) is S B to FP32 accuracy.
+__global__ __launch_bounds__(kBlock) void bf16_split3_transpose_kernel(
+    const float* __restrict__ B, int64_t K, int64_t N, int64_t ldb, uint16_t* __restrict__ Bt,
+    int64_t ldbt, int64_t part_stride) {
+  __shared__ uint16_t tile[3][64][66];
+  const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    const int kk = ty + 4 * i;
+    const int64_t gk = k0 + kk, gn = n0 + tx;
+    uint16_t h = 0, mi = 0, lo = 0;
+    if (gk < K && gn < N) {
+      const float v = B[gk * ldb + gn];
+      h = bf16_rne(v);
+      const float r1 = v - __uint_as_float((uint32_t)h << 16);
+      mi = bf16_rne(r1);
+      const float r2 = r1 - __uint_as_float((uint32_t)mi << 16);
+      lo = bf16_rne(r2);
+    }
+    tile[0][kk][tx] = h;
+    tile[1][kk][tx] = mi;
+    tile[2][kk][tx] = lo;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    const int nn = ty + 4 * i;
+    const int64_t gn = n0 + nn, gk = k0 + tx;
+    if (gn < N && gk < ldbt) {
+      Bt[gn * ldbt + gk] = tile[0][tx][nn];
+      Bt[part_stride + gn * ldbt + gk] = tile[1][tx][nn];
+      Bt[2 * part_stride + gn * ldbt + gk] = tile[2][tx][nn];
+    }
   }
 }
 
@@ -643,12 +865,15 @@ struct GaussPlan {
   int splits;
   int64_t kchunk;
   int64_t ldbt;    // row stride of the BF16 transpose of B (mixed)
+  int terms;       // BF16 terms of B (mixed): 1, or 3 for the FP32-accurate split
   size_t s_bytes, p_bytes, bt_bytes;
   size_t total() const { return s_bytes + p_bytes + bt_bytes; }
 };
 
-GaussPlan gauss_plan(const mihs_handle* h, int64_t M, int64_t K, int64_t N, int mixed) {
+GaussPlan gauss_plan(const mihs_handle* h, int64_t M, int64_t K, int64_t N, int mixed,
+                     int terms = 1) {
   GaussPlan g;
+  g.terms = mixed ? terms : 1;
   const int BM = mixed ? 128 : 64, BN = mixed ? 128 : 64, BK = mixed ? 64 : 16;
   g.lds = (K + 7) / 8 * 8;
   const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
@@ -660,9 +885,9 @@ GaussPlan gauss_plan(const mihs_handle* h, int64_t M, int64_t K, int64_t N, int 
   g.kchunk = ceil_div(ceil_div(K, want), BK) * BK;
   g.splits = (int)ceil_div(K, g.kchunk);
   g.s_bytes = align_up((size_t)M * g.lds * (mixed ? 2 : 8), 256);
-  g.p_bytes = align_up((size_t)g.splits * M * N * (mixed ? 4 : 8), 256);
+  g.p_bytes = align_up((size_t)g.terms * g.splits * M * N * (mixed ? 4 : 8), 256);
   g.ldbt = (K + 7) / 8 * 8;
-  g.bt_bytes = mixed ? align_up((size_t)N * g.ldbt * 2, 256) : 0;
+  g.bt_bytes = mixed ? align_up((size_t)g.terms * N * g.ldbt * 2, 256) : 0;
   return g;
 }
 
@@ -671,8 +896,8 @@ GaussPlan gauss_plan(const mihs_handle* h, int64_t M, int64_t K, int64_t N, int 
 template <typename TB>
 int run_gauss(const mihs_handle* h, const TB* B, int64_t K, int64_t N, int64_t ldb, int64_t M,
               uint32_t seed, uint64_t stream_id, int mixed, void* out, int64_t ldo, char* ws,
-              size_t ws_bytes, hipStream_t st) {
-  const GaussPlan g = gauss_plan(h, M, K, N, mixed);
+              size_t ws_bytes, hipStream_t st, int terms = 1) {
+  const GaussPlan g = gauss_plan(h, M, K, N, mixed, terms);
   if (ws_bytes < g.total()) return MIHS_ERR_WORKSPACE;
   void* S = ws;
   void* P = ws + g.s_bytes;
@@ -690,14 +915,30 @@ int run_gauss(const mihs_handle* h, const TB* B, int64_t K, int64_t N, int64_t l
   if (!hip_ok()) return MIHS_ERR_HIP;
   if (mixed) {
     uint16_t* Bt = (uint16_t*)(ws + g.s_bytes + g.p_bytes);
-    hipLaunchKernelGGL(bf16_transpose_kernel<TB>,
-                       dim3((unsigned)ceil_div(N, 64), (unsigned)ceil_div(g.ldbt, 64)),
-                       dim3(kBlock), 0, st, B, K, N, ldb, Bt, g.ldbt);
+    const dim3 tgrid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(g.ldbt, 64));
+    const int64_t part = N * g.ldbt;  // elements of one BF16 term of B^T
+    if constexpr (sizeof(TB) == 4) {
+      if (g.terms == 3)
+        hipLaunchKernelGGL(bf16_split3_transpose_kernel, tgrid, dim3(kBlock), 0, st, B, K, N,
+                           ldb, Bt, g.ldbt, part);
+      else
+        hipLaunchKernelGGL(bf16_transpose_kernel<TB>, tgrid, dim3(kBlock), 0, st, B, K, N, ldb,
+                           Bt, g.ldbt);
+    } else {
+      if (g.terms != 1) return MIHS_ERR_UNSUPPORTED;
+      hipLaunchKernelGGL(bf16_transpose_kernel<TB>, tgrid, dim3(kBlock), 0, st, B, K, N, ldb, Bt,
+                         g.ldbt);
+    }
+    // one GEMM per term into its own split-K partials; the reduction adds them
+    // all in a fixed order
     dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)g.splits);
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kBlock), 0, st, (const uint16_t*)S, g.lds,
-                       M, K, (const uint16_t*)Bt, g.ldbt, N, g.kchunk, (float*)P);
+    for (int t = 0; t < g.terms; ++t)
+      hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kBlock), 0, st, (const uint16_t*)S, g.lds,
+                         M, K, (const uint16_t*)(Bt + t * part), g.ldbt, N, g.kchunk,
+                         (float*)P + (int64_t)t * g.splits * M * N);
     hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), dim3((unsigned)ceil_div(M * N, 256)),
-                       dim3(256), 0, st, (const float*)P, g.splits, M, N, (float*)out, ldo);
+                       dim3(256), 0, st, (const float*)P, g.terms * g.splits, M, N, (float*)out,
+                       ldo);
   } else {
     dim3 grid((unsigned)ceil_div(N, 64), (unsigned)ceil_div(M, 64), (unsigned)g.splits);
     hipLaunchKernelGGL((gemm_f64_kernel<double, TB>), grid, dim3(kBlock), 0, st, (const double*)S, g.lds, M,
@@ -734,7 +975,9 @@ int run_countsketch(const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, u
   unsigned* hist = (unsigned*)(ws + p.hist);
   unsigned* off = (unsigned*)(ws + p.off);
   unsigned* cursor = (unsigned*)(ws + p.cursor);
-  if (hipMemsetAsync(hist, 0, (size_t)m * 4, st) != hipSuccess) return MIHS_ERR_HIP;
+  // the histogram starts from zero (a kernel, not a memset: a caller may
+  // capture this sequence in a graph)
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, hist, m);
   hipLaunchKernelGGL(cs_hash_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, m,
                      seed, code, hist);
   hipLaunchKernelGGL(cs_scan_kernel, dim3(1), dim3(kBlock), 0, st, hist, m, off, cursor);
@@ -753,9 +996,84 @@ int srht_logB(int64_t n) {
   return lb;
 }
 
+// The one-read SRHT: block size (B = 2^logb rows), samples per thread, and the
+// number of block ranges per strip (enough workgroups for one per CU).  Used
+// when n >= B and m <= 2048; else the two-stage transform below.
+struct SrhtFusedPlan {
+  bool ok = false;
+  int logb = 0, nacc = 0, nparts = 1;
+  int64_t nblk = 0, strips = 0;
+  size_t idx_bytes = 0, sign_bytes = 0, part_bytes = 0, lds = 0;
+  size_t total() const { return idx_bytes + sign_bytes + part_bytes; }
+};
+
+SrhtFusedPlan srht_fused_plan(const mihs_handle* h, int64_t n, int64_t d, int64_t m, int ty_bytes) {
+  SrhtFusedPlan F;
+  F.logb = ty_bytes == 4 ? 10 : 9;
+  if (n < (1LL << F.logb) || (n & (n - 1)) != 0 || m > 2048 || m < 1) return F;
+  F.ok = true;
+  F.nacc = m <= 512 ? 16 : (m <= 1024 ? 32 : 64);
+  F.nblk = n >> F.logb;
+  F.strips = (d + kFusedW - 1) / kFusedW;
+  int64_t parts = (h->num_cu + F.strips - 1) / F.strips;
+  if (parts > F.nblk) parts = F.nblk;
+  if (parts < 1) parts = 1;
+  F.nparts = (int)parts;
+  F.idx_bytes = align_up((size_t)m * 4, 256);
+  F.sign_bytes = align_up((size_t)(n / 32) * 4, 256);
+  F.part_bytes = F.nparts > 1 ? align_up((size_t)F.nparts * m * d * ty_bytes, 256) : 0;
+  F.lds = (size_t)(1 << F.logb) * kFusedLdt * ty_bytes + 2 * 32 * (size_t)F.nacc * 4;
+  return F;
+}
+
+template <typename TA, typename TY, int LOGB, typename TS>
+int launch_srht_fused(const SrhtFusedPlan& F, const TA* A, int64_t lda, int64_t d, int64_t m,
+                      const uint32_t* signw, const int* idx, TY* P, TS* SA, int64_t ldsa,
+                      double scale, hipStream_t st) {
+  const dim3 grid((unsigned)(F.strips * F.nparts));
+  auto go = [&](auto kern) -> int {
+    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)F.lds) != hipSuccess)
+      return MIHS_ERR_HIP;
+    hipLaunchKernelGGL(kern, grid, dim3(kFusedThreads), F.lds, st, A, lda, d, signw, idx, m,
+                       F.nblk, F.nparts, P, d, SA, ldsa, scale);
+    return MIHS_OK;
+  };
+  int rc;
+  if (F.nacc == 16) rc = go(srht_fused_kernel<TA, TY, LOGB, 16, TS>);
+  else if (F.nacc == 32) rc = go(srht_fused_kernel<TA, TY, LOGB, 32, TS>);
+  else rc = go(srht_fused_kernel<TA, TY, LOGB, 64, TS>);
+  if (rc) return rc;
+  if (F.nparts > 1)
+    hipLaunchKernelGGL((srht_parts_sum_kernel<TY, TS>), dim3((unsigned)ceil_div(m * d, 256)),
+                       dim3(256), 0, st, P, F.nparts, m, d, d, SA, ldsa, scale);
+  return MIHS_OK;
+}
+
 template <typename TA, typename TY, typename TS>
-int run_srht(const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint32_t seed, TS* SA,
-             int64_t ldsa, char* ws, size_t ws_bytes, hipStream_t st) {
+int run_srht(const mihs_handle* h, const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m,
+             uint32_t seed, TS* SA, int64_t ldsa, char* ws, size_t ws_bytes, hipStream_t st) {
+  SrhtFusedPlan F = srht_fused_plan(h, n, d, m, (int)sizeof(TY));
+  // a block's bytes must fit the 32-bit buffer range of the row loads
+  if (F.ok && (double)(1LL << F.logb) * (double)lda * sizeof(TA) >= 2147483647.0) F.ok = false;
+  if (F.ok) {
+    if (ws_bytes < F.total()) return MIHS_ERR_WORKSPACE;
+    int* idx = (int*)ws;
+    uint32_t* signw = (uint32_t*)(ws + F.idx_bytes);
+    TY* P = (TY*)(ws + F.idx_bytes + F.sign_bytes);
+    hipLaunchKernelGGL(srht_rows_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, idx,
+                       m, n, seed);
+    hipLaunchKernelGGL(srht_sign_words_kernel, dim3((unsigned)ceil_div(n / 32, 256)), dim3(256),
+                       0, st, signw, n / 32, seed);
+    const double scale = 1.0 / sqrt((double)m);
+    int rc;
+    if constexpr (sizeof(TY) == 4)
+      rc = launch_srht_fused<TA, TY, 10, TS>(F, A, lda, d, m, signw, idx, P, SA, ldsa, scale, st);
+    else
+      rc = launch_srht_fused<TA, TY, 9, TS>(F, A, lda, d, m, signw, idx, P, SA, ldsa, scale, st);
+    if (rc) return rc;
+    return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
+  }
   const size_t idx_bytes = align_up((size_t)m * 4, 256);
   const int64_t ldy = (d + 3) / 4 * 4;
   const size_t y_bytes = align_up((size_t)n * ldy * sizeof(TY), 256);
@@ -786,12 +1104,16 @@ int run_srht(const TA* A, int64_t n, int64_t d, int64_t lda, int64_t m, uint32_t
 }
 
 __global__ __launch_bounds__(kBlock) void neg_dot_kernel(const double* X, const double* W,
-                                                         int64_t count, double* out) {
+                                                         int64_t count, double lam, double* out,
+                                                         double* out_log) {
   __shared__ double s_red[kWavesPerBlock];
   double v = 0.0;
   for (int64_t i = threadIdx.x; i < count; i += kBlock) v += X[i] * W[i];
   v = block_sum(v, s_red);
-  if (threadIdx.x == 0) *out = -v;
+  if (threadIdx.x == 0) {
+    *out = -v;
+    if (out_log) *out_log = lam * -v;  // chain rule through lambda = exp(log lambda)
+  }
 }
 
 __global__ void fill_kernel(double* p, double v, int64_t count) {
@@ -822,9 +1144,10 @@ int launch_apply_rows(const mihs_handle* h, const void* A, int a_f32, int64_t n,
   return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
 }
 
-int launch_neg_dot(const double* X, const double* W, int64_t count, double* out,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(neg_dot_kernel, dim3(1), dim3(kBlock), 0, st, X, W, count, out);
+int launch_neg_dot(const double* X, const double* W, int64_t count, double lam, double* out,
+                   double* out_log, hipStream_t st) {
+  hipLaunchKernelGGL(neg_dot_kernel, dim3(1), dim3(kBlock), 0, st, X, W, count, lam, out,
+                     out_log);
   return hip_ok() ? MIHS_OK : MIHS_ERR_HIP;
 }
 
@@ -837,6 +1160,8 @@ size_t sketch_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_
       return g.total();
     }
     case MIHS_SRHT: {
+      const SrhtFusedPlan F = srht_fused_plan(h, n, d, m, mixed ? 4 : 8);
+      if (F.ok) return F.total();
       const int64_t ldy = (d + 3) / 4 * 4;
       return align_up((size_t)m * 4, 256) + align_up((size_t)n * ldy * (mixed ? 4 : 8), 256);
     }
@@ -845,7 +1170,7 @@ size_t sketch_workspace_bytes(const mihs_handle* h, int64_t n, int64_t d, int64_
     case MIHS_COUNT_GAUSS: {
       const int64_t ldc = (d + 3) / 4 * 4;
       const size_t ca = align_up((size_t)m * ldc * (mixed ? 4 : 8), 256);
-      const GaussPlan g = gauss_plan(h, m2, m, d, mixed);
+      const GaussPlan g = gauss_plan(h, m2, m, d, mixed, kCountGaussTerms);
       const size_t a = cs_plan(n, m).total, b = g.total();
       return ca + (a > b ? a : b);
     }
@@ -868,12 +1193,12 @@ int launch_sketch(const mihs_handle* h, const void* A, int a_f32, int64_t n, int
     case MIHS_SRHT:
       if (mixed) {
         if (a_f32)
-          return run_srht<float, float, float>((const float*)A, n, d, lda, m, seed, (float*)SA, ldsa, w, ws_bytes, st);
-        return run_srht<double, float, float>((const double*)A, n, d, lda, m, seed, (float*)SA, ldsa, w, ws_bytes, st);
+          return run_srht<float, float, float>(h, (const float*)A, n, d, lda, m, seed, (float*)SA, ldsa, w, ws_bytes, st);
+        return run_srht<double, float, float>(h, (const double*)A, n, d, lda, m, seed, (float*)SA, ldsa, w, ws_bytes, st);
       }
       if (a_f32)
-        return run_srht<float, double, double>((const float*)A, n, d, lda, m, seed, (double*)SA, ldsa, w, ws_bytes, st);
-      return run_srht<double, double, double>((const double*)A, n, d, lda, m, seed, (double*)SA, ldsa, w, ws_bytes, st);
+        return run_srht<float, double, double>(h, (const float*)A, n, d, lda, m, seed, (double*)SA, ldsa, w, ws_bytes, st);
+      return run_srht<double, double, double>(h, (const double*)A, n, d, lda, m, seed, (double*)SA, ldsa, w, ws_bytes, st);
     case MIHS_COUNTSKETCH:
       if (mixed) {
         if (a_f32)
@@ -894,7 +1219,8 @@ int launch_sketch(const mihs_handle* h, const void* A, int a_f32, int64_t n, int
         rc = a_f32 ? run_countsketch<float, float, float>((const float*)A, n, d, lda, m, seed, CA, ldc, rest, rest_bytes, st)
                    : run_countsketch<double, float, float>((const double*)A, n, d, lda, m, seed, CA, ldc, rest, rest_bytes, st);
         if (rc) return rc;
-        return run_gauss<float>(h, CA, m, d, ldc, m2, seed, 1, 1, SA, ldsa, rest, rest_bytes, st);
+        return run_gauss<float>(h, CA, m, d, ldc, m2, seed, 1, 1, SA, ldsa, rest, rest_bytes, st,
+                                kCountGaussTerms);
       }
       double* CA = (double*)w;
       rc = a_f32 ? run_countsketch<float, double, double>((const float*)A, n, d, lda, m, seed, CA, ldc, rest, rest_bytes, st)

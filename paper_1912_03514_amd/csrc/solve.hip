@@ -1015,12 +1015,7 @@ SolveKernel pick_kernel(int a_f32, int mixed, int ept) {
 }
 
 // The CG goes through the Gram matrix when it is no larger than SA (m >= d).
-// MIHS_GRAM=0/1 forces the choice (tuning).
-bool use_gram(int64_t m, int64_t d) {
-  const char* env = getenv("MIHS_GRAM");
-  if (env && (env[0] == '0' || env[0] == '1')) return env[0] == '1';
-  return m >= d;
-}
+bool use_gram(int64_t m, int64_t d) { return m >= d; }
 
 struct SolveLayout {
   size_t partA, partS, scal, vecs, xp, bar, gram, yrow, total;
@@ -1057,12 +1052,11 @@ int max_grid(const mihs_handle* h) { return h->num_cu * kMaxBlocksPerCU; }
 
 // Size of the inner-solve subgroup: enough workgroups to stream SA quickly,
 // few enough that its barrier stays cheap (the barrier cost grows steeply
-// with the number of participants).  MIHS_CG_GROUPS overrides (tuning).
-int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G, bool gram) {
-  const char* env = getenv("MIHS_CG_GROUPS");
+// with the number of participants).  `forced` > 0 fixes the size.
+int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G, bool gram, int forced) {
   int gc;
-  if (env && atoi(env) > 0) {
-    gc = atoi(env);
+  if (forced > 0) {
+    gc = forced;
   } else {
     // bytes one CG step streams: the Gram matrix (m >= d) or SA
     const double mb = (double)(gram ? d : m) * (double)d * sa_bytes / (1024.0 * 1024.0);
@@ -1137,15 +1131,13 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   // size (and with it the LDS request) depends on the grid.
   int G = 0, Gc = 0, cpw = 0;
   size_t shmem = 0;
-  // keep >= ~64 rows of A per workgroup (MIHS_ROWS_PER_WG overrides; tuning)
-  int64_t rows_per_wg = 64;
-  if (const char* env = getenv("MIHS_ROWS_PER_WG"))
-    if (atoi(env) > 0) rows_per_wg = atoi(env);
+  // keep >= ~64 rows of A per workgroup (unless the caller fixes another count)
+  const int64_t rows_per_wg = s.rows_per_wg > 0 ? s.rows_per_wg : 64;
   const int64_t g_rows = (s.n + rows_per_wg - 1) / rows_per_wg;
   for (int occ_try = kMaxBlocksPerCU; occ_try >= 1; --occ_try) {
     int g = h->num_cu * occ_try;
     if ((int64_t)g > g_rows) g = (int)(g_rows < 1 ? 1 : g_rows);
-    const int gc = pick_cg_groups(s.m, s.d, s.mixed ? 4 : 8, g, gram);
+    const int gc = pick_cg_groups(s.m, s.d, s.mixed ? 4 : 8, g, gram, s.cg_groups);
     const int cp = (int)((s.d + gc - 1) / gc);
     const size_t sh = (2 * (size_t)dpad + 6 * (size_t)cp + kBlock) * sizeof(double);
     if (sh > 160 * 1024) continue;

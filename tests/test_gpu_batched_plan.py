@@ -1,5 +1,7 @@
 """GPU: the batched solve as a plan + launch (graph capture, repeated runs) and the
 launch-shape autotuner, against the oracle's closed form."""
+import os
+
 import numpy as np
 import pytest
 
@@ -82,17 +84,19 @@ def test_every_launch_shape_reaches_the_closed_form(problem_set, tuning):
         assert all(r["inner_iters_max"] == 1 for inf in infos for r in inf)
 
 
-@pytest.mark.parametrize("exact", [0, 1])
-def test_graph_replays_match_the_eager_run(problem_set, exact):
+@pytest.mark.parametrize("cg_cols,exact", [(32, 0), (512, 0), (32, 1)])
+def test_graph_replays_match_the_eager_run(problem_set, cg_cols, exact):
     """The launch captured in a HIP graph (with the Cholesky factor kernel when
     the sub-solves are exact), replayed three times with other eager work (and
     garbage in X) between the replays, gives bit-identical results to the eager
-    launch of the same plan."""
+    launch of the same plan: the team CG (32 columns per workgroup, R and Z
+    handed between workgroups at every step), the one-workgroup CG (512) and
+    the exact sub-solves."""
     mihs = _mihs()
     dp, refs, L, Al, Be = _device_set(problem_set)
     s = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
                            max_inner=2000,
-                           tuning={"cg_cols": 32, "a_dma": 1, "inner_weight": 100.0,
+                           tuning={"cg_cols": cg_cols, "a_dma": 1, "inner_weight": 100.0,
                                    "exact": exact})
     announce("batched plan eager run")
     s.run()
@@ -116,9 +120,9 @@ def test_graph_replays_match_the_eager_run(problem_set, exact):
 
 
 def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
-    """mihs_tune_batched times ten candidate shapes by coordinate descent, full
-    runs of the best inexact and the best exact shape, and a schedule sized
-    from the faster one's per-problem costs,
+    """mihs_tune_batched with exact sub-solves allowed times ten candidate
+    shapes by coordinate descent, full runs of the best inexact and the best
+    exact shape, and a schedule sized from the faster one's per-problem costs,
     and keeps the best for this problem set: the plain batched call afterwards
     (which looks the shape up) still reaches the closed form, and so does a plan
     that asks for the measured schedule explicitly."""
@@ -127,7 +131,7 @@ def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
     s = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
                            max_inner=2000)
     announce("batched autotuner")
-    res = s.tune(trial_outer=3)
+    res = s.tune(trial_outer=3, allow_exact=True)
     best = res["best"]
     assert len(res["trial_ms"]) == 13
     assert all(t > 0 for t in res["trial_ms"])
@@ -188,7 +192,10 @@ def test_measured_schedule_with_more_entries_than_workgroups():
                            max_inner=2000)
     announce("batched 300 problems: tuner with measured schedule")
     res = s.tune(trial_outer=3)
-    assert len(res["trial_ms"]) == 13
+    # inexact shapes only (the default): eight short trials, one full run of
+    # the best, one run of the measured schedule; exact sub-solves never chosen
+    assert len(res["trial_ms"]) == 10
+    assert res["best"]["exact"] == 0
     g = s.capture()
     s.X_all.fill_(float("nan"))
     torch.cuda.synchronize()
@@ -308,3 +315,27 @@ def test_exact_subsolves_at_the_widest_padding(sa_f32):
             assert infos[i][j]["status"] == 0, (i, j, infos[i][j])
             assert infos[i][j]["inner_iters_max"] == 1, (i, j, infos[i][j])
             assert rel(X[:, j], O.ridge_lstsq(P.A, P.b, float(lams[j]))) <= 1e-10, (i, j)
+
+
+def test_tuning_cache_file_skips_the_second_tuning(problem_set, tmp_path):
+    """tune(cache=path) writes the chosen shape to a tuning-cache file; a new
+    solver on an equal problem set reads it back (no trials) and still reaches
+    the closed form."""
+    mihs = _mihs()
+    dp, refs, L, Al, Be = _device_set(problem_set)
+    path = str(tmp_path / "tuning.json")
+    s = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
+                           max_inner=2000)
+    announce("batched tuning with a cache file")
+    first = s.tune(trial_outer=2, measure=False, cache=path)
+    assert first["trial_ms"] and not first.get("from_cache")
+    assert os.path.exists(path)
+    assert mihs.tuning_cache_load(path) >= 1
+    s2 = mihs.BatchedSolver(dp, L, Al, Be, eps_sub=1e-2, tol=1e-12, max_outer=800,
+                            max_inner=2000)
+    second = s2.tune(trial_outer=2, measure=False, cache=path)
+    assert second.get("from_cache") and second["best"] == first["best"]
+    announce("batched run with the cached shape")
+    s2.run()
+    torch.cuda.synchronize()
+    _check_closed_form(s2.xs, s2.infos(), refs)

@@ -47,22 +47,28 @@ def test_srht_signs_and_samples_exact():
     assert np.allclose(np.abs(SA), 1 / math.sqrt(m), rtol=1e-15, atol=0)
 
 
-def test_srht_full_size_sampled_entries():
-    """At the headline size (2^18 x 2048 FP64, m = 2048) sampled output entries
-    equal the direct O(n) sum of the definition."""
+@pytest.mark.parametrize("prec", ["plain", "mixed"])
+def test_srht_full_size_whole_rows(prec):
+    """At the headline size (2^18 x 2048 FP64, m = 2048) 16 whole sampled output
+    rows (all 2048 columns) equal the direct O(n) sum of the definition; the
+    bound is a few rounding errors of the partial sums (log2(n) levels) in the
+    arithmetic's precision (FP64 plain, FP32 mixed)."""
     mihs = _mihs()
     n, d, m, seed = 1 << 18, 2048, 2048, 8
     g = torch.Generator(device="cuda").manual_seed(5)
     A = torch.randn(n, d, generator=g, dtype=torch.float64, device="cuda")
-    announce("srht full size 2^18 x 2048")
-    SA = mihs.mihs_sketch(A, "srht", m, seed).cpu().numpy()
+    announce(f"srht full size 2^18 x 2048 ({prec})")
+    SA = mihs.mihs_sketch(A, "srht", m, seed, precision=prec).double().cpu().numpy()
+    Ah = A.cpu().numpy()
+    del A
+    u = 2.0 ** -52 if prec == "plain" else 2.0 ** -23
+    colsum = np.abs(Ah).sum(axis=0) / math.sqrt(m)
     rng = np.random.default_rng(0)
-    ks = rng.integers(0, m, 6)
-    cols = np.sort(rng.choice(d, 8, replace=False))
-    Ac = A[:, torch.as_tensor(cols, device="cuda")].cpu().numpy()
+    ks = np.sort(rng.choice(m, 16, replace=False))
     for k in ks:
-        ref = sketches.srht_entry(Ac, m, seed, int(k), slice(None))
-        assert np.max(np.abs(SA[k, cols] - ref)) <= 1e-12 * math.sqrt(n), k
+        ref = sketches.srht_entry(Ah, m, seed, int(k), slice(None))
+        err = np.abs(SA[k] - ref)
+        assert np.all(err <= 4 * math.log2(n) * u * colsum), (k, float(err.max()))
 
 
 @pytest.mark.parametrize("adt", [np.float64, np.float32])
@@ -134,6 +140,30 @@ def test_gaussian_mixed_bf16(n, d, m):
     assert rel(SA, exact) < 2e-2
 
 
+def test_gaussian_mixed_entries_within_one_bf16_unit():
+    """The mixed path draws its Gaussian entries in FP32 (hardware log2 / sine /
+    cosine) and rounds them to BF16: sketching the identity exposes S itself,
+    which must equal the oracle's FP64 draws rounded to BF16 except for rare
+    entries where the FP32 draw's error crosses a rounding boundary: one BF16
+    unit, or, near the zeros of sine and cosine, the draw's absolute error
+    (the hardware sine and cosine are accurate to a few units of 2^-22 in
+    absolute terms; with rad <= 7 that is below 2^-16, i.e. below 2^-16 of an
+    entry's typical size 1/sqrt(m))."""
+    mihs = _mihs()
+    n, m, seed = 1024, 256, 21
+    A = np.eye(n)
+    announce("gaussian mixed entries (identity)")
+    S_gpu = mihs.mihs_sketch(to_dev(A), "gaussian", m, seed, precision="mixed")
+    S_gpu = S_gpu.cpu().numpy().astype(np.float64)
+    idx = np.arange(m * n, dtype=np.int64).reshape(m, n)
+    S_ref = sketches.bf16_round(sketches.gaussian_entries(seed, 0, idx) / math.sqrt(m))
+    ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(S_ref), 1e-30))) - 7)
+    diff = np.abs(S_gpu - S_ref)
+    bound = np.maximum(ulp * 1.0000001, 2.0 ** -16 / math.sqrt(m))
+    assert np.all(diff <= bound), float((diff / bound).max())
+    assert np.count_nonzero(diff) <= 1e-3 * m * n, np.count_nonzero(diff)
+
+
 def test_count_gauss_plain_and_mixed():
     mihs = _mihs()
     n, d, m1, m2 = 30000, 48, 512, 128
@@ -147,7 +177,12 @@ def test_count_gauss_plain_and_mixed():
     SAm = mihs.mihs_sketch(to_dev(A), "count_gauss", m1, 99, m2=m2, precision="mixed")
     SAm = SAm.cpu().numpy().astype(np.float64)
     CA = sketches.countsketch(A, m1, 99)
-    refm = sketches.gaussian_sketch_bf16(CA, m2, 99, stream=1)
-    # FP32 bucket sums may round to a neighbouring BF16 value in a few entries
-    assert rel(SAm, refm) <= 1e-3
+    # mixed second stage: BF16 Gaussian entries times the FP32 bucket sums kept
+    # to FP32 accuracy (three BF16 terms), i.e. bf16(G) CA -- not bf16(G) bf16(CA)
+    idx = np.arange(m2 * m1, dtype=np.int64).reshape(m2, m1)
+    G16 = sketches.bf16_round(sketches.gaussian_entries(99, 1, idx) / math.sqrt(m2))
+    ref_split = G16 @ CA
+    ref_rounded = sketches.gaussian_sketch_bf16(CA, m2, 99, stream=1)
+    assert rel(SAm, ref_split) <= 2e-4
+    assert rel(ref_rounded, ref_split) > 5e-4  # the bound above tells the two apart
     assert rel(SAm, ref) <= 2e-2

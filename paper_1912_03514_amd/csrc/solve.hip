@@ -1205,11 +1205,12 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   a.spin_idle.sleep = 16;
   a.H = gram ? (const void*)(base + L.gram) : nullptr;
   a.ldh = dpad;
-  // One barrier per CG step pays off where the CG is latency-bound; the
-  // two-reduction form keeps fewer steps on very ill-conditioned solves
-  // (measured on the CountSketch workload, kappa ~ 6e8: FP64 22k vs 27-38k
-  // steps; FP32 breaks down), so the kernel also checks trace(H) / lambda.
-  a.cg1 = s.mixed ? 1 : 0;
+  // One barrier per CG step pays off where the CG is latency-bound (headline,
+  // FP64: 32.2 -> 29.4 ms per solve); the two-reduction form keeps fewer steps
+  // on very ill-conditioned solves (measured on the CountSketch workload,
+  // kappa ~ 6e8: FP64 22k vs 27-38k steps; FP32 breaks down), so the kernel
+  // takes the single-reduction form only where trace(H) / lambda is small.
+  a.cg1 = 1;
   a.aab = s.aab ? 1 : 0;
   a.yrow = (double*)(base + L.yrow);
   a.skip = s.skip;

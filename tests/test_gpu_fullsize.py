@@ -213,14 +213,23 @@ def test_fullsize_differentiation():
     def central(rp, rm):
         return float(((rp - rm) * (rp + rm)).sum()) / (2 * h)
 
+    # Directions: the reference gradient weighted entrywise by random factors in
+    # [0.5, 1.5), three draws.  Along a plain random direction <dL/dB, V> is a sum
+    # with heavy cancellation (~2 against terms of ~1e3 here), and no FP64
+    # difference quotient resolves it to 1e-6; these directions keep the
+    # directional derivative of the size of its terms.
     h = 1e-6
     gv = torch.Generator(device=dev()).manual_seed(77)
+    dBref_d = torch.as_tensor(dBref, device=dev())
     for t in range(3):
-        V = torch.randn(B.shape, generator=gv, dtype=torch.float64, device=dev())
+        wts = 0.5 + torch.rand(B.shape, generator=gv, dtype=torch.float64, device=dev())
+        V = dBref_d * wts
         V = V * (B.norm() / V.norm())
         fd = central(residual(B + h * V, lam), residual(B - h * V, lam))
         an = float((Bt.grad * V).sum())
-        print(f"FD direction {t}: analytic {an:.12e}, central difference {fd:.12e}", flush=True)
+        ref = float((dBref_d * V).sum())
+        print(f"FD direction {t}: analytic {an:.12e}, dense {ref:.12e}, central difference "
+              f"{fd:.12e}", flush=True)
         assert abs(an - fd) <= 1e-6 * abs(fd), (t, an, fd)
     ll0 = math.log(lam)
     fd = central(residual(B, math.exp(ll0 + h)), residual(B, math.exp(ll0 - h)))

@@ -195,6 +195,33 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
                double* X_prev, mihs_info_t* d_info, void* workspace, size_t ws_bytes,
                void* stream);
 
+/* ------------------------------------------------------------------------
+ * mihs_solve without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, algorithm, kernels and results as
+ * mihs_solve; the scratch is a static device array inside the library of
+ * MIHS_NOALLOC_SCRATCH_BYTES bytes, one per GPU, held from the first
+ * mihs_create on that GPU until the process ends (the library takes its
+ * address in mihs_create).  The call allocates nothing (no hipMalloc, no
+ * hipFree, no allocating library routine) and clears the parts of the array
+ * that must start at zero itself, with a kernel.
+ * Limit: returns MIHS_ERR_WORKSPACE, before any GPU work, when the solve at
+ * these sizes could need more scratch than the array holds
+ * (mihs_solve_workspace_size() > MIHS_NOALLOC_SCRATCH_BYTES; e.g. d <= 2048
+ * with m >= d fits in both precisions).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (two streams, two threads) race and
+ * must be serialised by the caller.
+ * ------------------------------------------------------------------------ */
+#define MIHS_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+int mihs_solve_noalloc(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                       int64_t d, int64_t lda, const double* b, double lambda, const void* SA,
+                       int64_t m, int64_t ldsa, mihs_precision_t precision, double alpha,
+                       double beta, double eps_sub, double tol, int64_t max_outer,
+                       int64_t max_inner, double* X, double* X_prev, mihs_info_t* d_info,
+                       void* stream);
+
 /* mihs_solve with a choice of inner solver (mihs_inner_t); MIHS_INNER_CG is
  * mihs_solve itself.  With MIHS_INNER_AAB, eps_sub bounds AAb_Solver's residual
  * estimate and d_info's inner counts are AAb steps.  Same workspace size. */

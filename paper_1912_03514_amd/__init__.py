@@ -15,6 +15,6 @@ from ._binding import (  # noqa: F401
     load_library, mihs_estimate_sd, mihs_sketch, mihs_sketch_two_stage, mihs_solve,
     mihs_solve_backward, mihs_solve_batched, mihs_solve_dual, mihs_solve_multi, mihs_solve_pd,
     mihs_solve_pd_dual, mihs_transpose, MIHSRidge, momentum, momentum_thm1, lambda_from_log,
-    release_all, tuning_cache_save,
+    release_all, mihs_solve_noalloc, NOALLOC_SCRATCH_BYTES, tuning_cache_save,
     tuning_cache_load,
 )

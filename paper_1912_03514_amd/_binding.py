@@ -85,6 +85,8 @@ _SIGS = {
     "mihs_solve_workspace_size": (_int, [_vp, _i64, _i64, _i64, _int, ctypes.POINTER(_sz)]),
     "mihs_solve": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64, _int,
                           _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mihs_solve_noalloc": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64,
+                                  _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp, _vp]),
     "mihs_solve_inner": (_int, [_vp, _vp, _int, _i64, _i64, _i64, _vp, _dbl, _vp, _i64, _i64,
                                 _int, _int, _dbl, _dbl, _dbl, _dbl, _i64, _i64, _vp, _vp, _vp,
                                 _vp, _sz, _vp]),
@@ -359,6 +361,42 @@ def mihs_solve(A: torch.Tensor, b: torch.Tensor, lam: float, SA: torch.Tensor, a
         return x, workspace.info
     torch.cuda.synchronize(dev)
     return x, info_to_dict(workspace.info)[0]
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # MIHS_NOALLOC_SCRATCH_BYTES
+
+
+def mihs_solve_noalloc(A: torch.Tensor, b: torch.Tensor, lam: float, SA: torch.Tensor,
+                       alpha: float, beta: float, X: torch.Tensor, info: torch.Tensor,
+                       eps_sub: float = 1e-2, tol: float = 1e-10, max_outer: int = 200,
+                       max_inner: int = 1000, x_prev: Optional[torch.Tensor] = None,
+                       precision: Optional[str] = None):
+    """mihs_solve_noalloc (see include/mihs.h): M-IHS with the library's static
+    scratch instead of a workspace.  The caller passes every buffer: A, b, SA
+    (16-byte aligned rows), X (d float64: in x^1, out the solution) and info
+    (INFO_BYTES uint8); nothing is allocated or copied, and nothing waits."""
+    if precision is None:
+        precision = "mixed" if SA.dtype == torch.float32 else "plain"
+    n, d = A.shape
+    m = SA.shape[0]
+    if X.dtype != torch.float64 or X.numel() != d or not X.is_contiguous():
+        raise MihsError("X must be a contiguous float64 vector of length d")
+    if info.dtype != torch.uint8 or info.numel() < INFO_BYTES:
+        raise MihsError("info must hold one record")
+    if b.dtype != torch.float64 or b.numel() != n or not b.is_contiguous():
+        raise MihsError("b must be a contiguous float64 vector of length n")
+    for name, t in (("A", A), ("SA", SA)):
+        if t.stride(1) != 1 or t.data_ptr() % 16 or (t.stride(0) * t.element_size()) % 16:
+            raise MihsError(f"{name} must have unit column stride and 16-byte aligned rows")
+    lib = load_library()
+    rc = lib.mihs_solve_noalloc(handle(A.device.index), A.data_ptr(), _dtype_code(A), n, d,
+                                A.stride(0), b.data_ptr(), float(lam), SA.data_ptr(), m,
+                                SA.stride(0), PRECISIONS[precision], float(alpha), float(beta),
+                                float(eps_sub), float(tol), int(max_outer), int(max_inner),
+                                X.data_ptr(), x_prev.data_ptr() if x_prev is not None else None,
+                                info.data_ptr(), _stream(A.device))
+    _check(rc, "mihs_solve_noalloc")
+    return X
 
 
 def mihs_solve_dual(At: torch.Tensor, b: torch.Tensor, lam: float, SAt: torch.Tensor,

@@ -48,6 +48,18 @@ int mihs_create(mihs_handle_t* handle, int device) {
   h->num_cu = prop.multiProcessorCount;
   h->wall_khz = wall_khz;
   strncpy(h->arch, prop.gcnArchName, sizeof(h->arch) - 1);
+  // this device's address of the static scratch of mihs_solve_noalloc, taken
+  // once here with the device current (the caller's current device is kept)
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) {
+    delete h;
+    return MIHS_ERR_HIP;
+  }
+  const int rc = mihs::noalloc_scratch_address(&h->noalloc_scratch);
+  if (hipSetDevice(prev) != hipSuccess || rc != MIHS_OK) {
+    delete h;
+    return MIHS_ERR_HIP;
+  }
   *handle = h;
   return MIHS_OK;
 }
@@ -143,6 +155,25 @@ int mihs_solve(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_
   return mihs_solve_inner(handle, A, a_dtype, n, d, lda, b, lambda, SA, m, ldsa, precision,
                           MIHS_INNER_CG, alpha, beta, eps_sub, tol, max_outer, max_inner, X,
                           X_prev, d_info, workspace, ws_bytes, stream);
+}
+
+int mihs_solve_noalloc(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,
+                       int64_t d, int64_t lda, const double* b, double lambda, const void* SA,
+                       int64_t m, int64_t ldsa, mihs_precision_t precision, double alpha,
+                       double beta, double eps_sub, double tol, int64_t max_outer,
+                       int64_t max_inner, double* X, double* X_prev, mihs_info_t* d_info,
+                       void* stream) {
+  if (!handle || !handle->noalloc_scratch) return MIHS_ERR_INVALID;
+  if (n <= 0 || d <= 0 || m <= 0) return MIHS_ERR_INVALID;
+  if (precision != MIHS_PLAIN_FP64 && precision != MIHS_MIXED) return MIHS_ERR_INVALID;
+  // the largest layout the solve could use at these sizes must fit the array
+  if (mihs::solve_workspace_bytes(handle, n, d, m, precision == MIHS_MIXED) >
+      mihs::kNoAllocScratchBytes)
+    return MIHS_ERR_WORKSPACE;
+  return mihs_solve_inner(handle, A, a_dtype, n, d, lda, b, lambda, SA, m, ldsa, precision,
+                          MIHS_INNER_CG, alpha, beta, eps_sub, tol, max_outer, max_inner, X,
+                          X_prev, d_info, handle->noalloc_scratch, mihs::kNoAllocScratchBytes,
+                          stream);
 }
 
 int mihs_solve_inner(mihs_handle_t handle, const void* A, mihs_dtype_t a_dtype, int64_t n,

@@ -24,6 +24,7 @@ struct mihs_handle {
   int num_cu;
   int wall_khz;  // rate of the device's constant wall clock
   char arch[64];
+  void* noalloc_scratch;  // this device's address of the library's static scratch
   std::mutex tune_mu;
   std::vector<mihs_tuned_set> tuned;
 };
@@ -32,6 +33,11 @@ namespace mihs {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Static device scratch of mihs_solve_noalloc (bytes; MIHS_NOALLOC_SCRATCH_BYTES).
+constexpr size_t kNoAllocScratchBytes = (size_t)MIHS_NOALLOC_SCRATCH_BYTES;
+// This device's address of that scratch (hipGetSymbolAddress; the handle's
+// device must be current).
+int noalloc_scratch_address(void** ptr);
 
 // Padded vector length used by the row kernels: 64 lanes x elements-per-lane.
 int ept_for(int64_t d);

@@ -1072,6 +1072,22 @@ int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G, bool gram, int for
 
 }  // namespace
 
+// ---- scratch of the entry point without a workspace argument -------------
+// mihs_solve_noalloc runs the solve kernels on this array instead of a caller
+// workspace: one copy per GPU, held by the loaded code object until the process
+// ends.  In host code the name is only a stand-in for the symbol (passing it
+// to a kernel would make the kernel fault): every host use goes through the
+// device address that noalloc_scratch_address() returns, which differs per GPU.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+int noalloc_scratch_address(void** ptr) {
+  // call with the handle's device current: each GPU holds its own copy
+  *ptr = nullptr;
+  if (hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)) != hipSuccess || *ptr == nullptr)
+    return MIHS_ERR_HIP;
+  return MIHS_OK;
+}
+
 int ept_for(int64_t d) {
   int e = 1;
   while (64 * (int64_t)e < d) e *= 2;

@@ -1006,12 +1006,18 @@ SolveKernel pick_by_ept(int ept) {
   }
 }
 
+// Mixed precision stores the inner solver's operator (SA, or its Gram matrix)
+// in FP32, which halves the bytes every inner step streams, and keeps the CG
+// recurrences (vectors, step lengths, dot products) in FP64: FP32 recurrences
+// lose their conjugacy on ill-conditioned sub-problems (kappa ~ 6e8: 87k inner
+// steps against 27k, measured), and in this latency-bound loop the FP64
+// vectors cost about 1% at the headline size.
 template <bool GRAM>
 SolveKernel pick_kernel(int a_f32, int mixed, int ept) {
   if (!a_f32 && !mixed) return pick_by_ept<double, double, double, GRAM>(ept);
-  if (!a_f32 && mixed) return pick_by_ept<double, float, float, GRAM>(ept);
+  if (!a_f32 && mixed) return pick_by_ept<double, float, double, GRAM>(ept);
   if (a_f32 && !mixed) return pick_by_ept<float, double, double, GRAM>(ept);
-  return pick_by_ept<float, float, float, GRAM>(ept);
+  return pick_by_ept<float, float, double, GRAM>(ept);
 }
 
 // The CG goes through the Gram matrix when it is no larger than SA (m >= d).

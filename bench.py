@@ -59,7 +59,7 @@ def parse():
 
 # HBM bytes per launch of the persistent solve kernel, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, then WRITE_SIZE, each scaled by what the counter reads for a
-# plain 1 GiB device copy: x1.99993 for FETCH_SIZE, x1.000 for WRITE_SIZE); see
+# plain 1 GiB device copy: x1.99992 for FETCH_SIZE, x1.000 for WRITE_SIZE); see
 # profiles/solve_kernel_srht_2p18x2048.md.  Valid for the kernel as profiled.
 MEASURED_TRAFFIC = {}
 

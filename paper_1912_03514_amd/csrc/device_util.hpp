@@ -234,6 +234,98 @@ __device__ __forceinline__ bool barrier_hier(unsigned* words, unsigned& epoch, u
   return *s_flag != 0;
 }
 
+// ---- Coherent exchange: barriers for data that never sits in an L2 ---------
+// The barriers above make plain stores visible by writing the L2 back and
+// invalidating it on the way out, and on gfx950 both walk the whole L2 of the
+// XCD: with 16-32 workgroups per XCD arriving at once, the invalidations queue
+// up (a 128-workgroup barrier measured 6.5 us against 3.2 us without them, 11.3
+// against 5.8 us at 256), and every line the workgroups were reusing -- a Gram
+// matrix that fits in the L2s, re-read by every CG step -- has to come back
+// from memory after each barrier.
+//
+// The alternative keeps the L2s out of the exchange instead: every value one
+// workgroup writes for another during the launch is stored with an
+// agent-scope store (sc1: written through to memory) and read with an
+// agent-scope load (sc1: served coherently, never from a stale L2 line), which
+// is how the compiler implements relaxed agent-scope atomics.  A barrier then
+// only has to wait until each wave's own stores have completed (vmcnt(0)),
+// meet, and count arrivals; loads issued after the wait observe every store
+// made before any arrival.  (Checked on the hardware with 128 and 256
+// workgroups exchanging slots across all XCDs: 1.3e10 reads, no stale value;
+// the same exchange through plain accesses without write-back and
+// invalidation read stale values almost everywhere.)  Data that is only read
+// during the launch (A, b, SA, the Gram matrix) keeps plain cached loads.
+template <typename T>
+__device__ __forceinline__ T co_load(const T* p) {
+  typedef const T __attribute__((address_space(1))) gT;
+  return __hip_atomic_load((gT*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void co_store(T* p, T v) {
+  typedef T __attribute__((address_space(1))) gT;
+  __hip_atomic_store((gT*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool wait_counter_co(const unsigned* counter, unsigned target, int* err,
+                                                BarrierSpin spin) {
+  long spins = 0;
+  while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (spin.sleep >= 16)
+      __builtin_amdgcn_s_sleep(16);
+    else
+      __builtin_amdgcn_s_sleep(1);
+    if (++spins > spin.limit) {
+      atomicOr(err, 1);
+      return false;
+    }
+  }
+  return true;
+}
+
+// barrier_flat for workgroups that exchange data only through co_store/co_load.
+__device__ __forceinline__ bool barrier_flat_co(unsigned* counter, unsigned& epoch,
+                                                unsigned nblocks, int* err, int* s_flag,
+                                                BarrierSpin spin) {
+  publish_wave_stores();
+  __syncthreads();
+  epoch += 1u;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = wait_counter_co(counter, epoch * nblocks, err, spin) ? 1 : 0;
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+    *s_flag = ok;
+  }
+  __syncthreads();
+  asm volatile("" ::: "memory");
+  return *s_flag != 0;
+}
+
+// barrier_hier for workgroups that exchange data only through co_store/co_load.
+__device__ __forceinline__ bool barrier_hier_co(unsigned* words, unsigned& epoch,
+                                                unsigned nblocks, int* err, int* s_flag,
+                                                BarrierSpin spin) {
+  publish_wave_stores();
+  __syncthreads();
+  epoch += 1u;
+  if (threadIdx.x == 0) {
+    const unsigned g = blockIdx.x & 7u;
+    const unsigned ngroups = nblocks < 8u ? nblocks : 8u;
+    const unsigned gsize = (nblocks - g + 7u) / 8u;
+    unsigned* top = words;
+    unsigned* gc = words + 32u * (1u + g);
+    const unsigned old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == epoch * gsize - 1u)
+      __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = wait_counter_co(top, epoch * ngroups, err, spin) ? 1 : 0;
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+    *s_flag = ok;
+  }
+  __syncthreads();
+  asm volatile("" ::: "memory");
+  return *s_flag != 0;
+}
+
 // Column sums of a K x ncols block: out[c] = sum_k P[k * ldp + c0 + c], c < ncols,
 // in a fixed order (per thread over k, then a fixed tree in LDS).  All loads of a
 // chunk are independent, so they are in flight together.  `scratch` holds

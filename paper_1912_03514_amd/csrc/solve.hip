@@ -228,7 +228,7 @@ __device__ __forceinline__ void store_quarters(const double (&acc)[EQ], double* 
 #pragma unroll
     for (int vv = 0; vv < L::V; ++vv) {
       const int col = q0 + L::col(j, lane, vv);
-      if (col < d) out[col] = acc[j * L::V + vv];
+      if (col < d) co_store(out + col, acc[j * L::V + vv]);
     }
 }
 
@@ -251,7 +251,7 @@ __device__ __forceinline__ void wg_store_partial(const TV (&acc)[EPT], TV* red, 
     }
     __syncthreads();
   }
-  for (int col = threadIdx.x; col < d; col += kBlock) out[col] = red[col];
+  for (int col = threadIdx.x; col < d; col += kBlock) co_store(out + col, red[col]);
 }
 
 template <typename TV>
@@ -289,8 +289,8 @@ __device__ __forceinline__ void sum2_slots(const double* scal, int K, int s0, in
                                            double* s_red2, double& o0, double& o1) {
   double a = 0.0, b = 0.0;
   for (int k = threadIdx.x; k < K; k += kBlock) {
-    a += scal[(int64_t)k * kScal + s0];
-    b += scal[(int64_t)k * kScal + s1];
+    a += co_load(scal + (int64_t)k * kScal + s0);
+    b += co_load(scal + (int64_t)k * kScal + s1);
   }
   a = wave_sum(a);
   b = wave_sum(b);
@@ -330,7 +330,7 @@ __device__ __forceinline__ void owned_column_sums(const T* __restrict__ P, int K
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
           const int k = k0 + i * TPC;
-          v[i] = (k < K) ? base[(int64_t)k * ldp] : T(0);
+          v[i] = (k < K) ? co_load(base + (int64_t)k * ldp) : T(0);
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) s += (double)v[i];
@@ -419,12 +419,10 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   const int c_hi = in_cg ? min(d, c_lo + cpw) : d;
   const int nown = c_hi - c_lo;
   double* scal_w = a.scal + (int64_t)w * kScal;
-  // CG vectors in global memory, addressed as such: loads through the generic
-  // address space would also count as LDS traffic, so every LDS wait in the
-  // step would wait for them too
-  typedef TV __attribute__((address_space(1))) gTV;
-  gTV* r = (gTV*)a.r;
-  gTV* P[2] = {(gTV*)a.p0, (gTV*)a.p1};
+  // CG vectors exchanged between the CG workgroups: every access goes through
+  // co_store / co_load (agent-scope, global address space)
+  TV* r = (TV*)a.r;
+  TV* P[2] = {(TV*)a.p0, (TV*)a.p1};
   TV* partS = (TV*)a.partS;
   const TA* A = (const TA*)a.A;
   const TS* SA = (const TS*)a.SA;
@@ -468,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
 
   while (outer < a.max_outer) {
     // ---- A1 (all): partial A^T (b - A x) over this workgroup's rows
-    for (int c = threadIdx.x; c < a.dpad; c += kBlock) vbuf[c] = (c < d) ? a.x[c] : 0.0;
+    for (int c = threadIdx.x; c < a.dpad; c += kBlock) vbuf[c] = (c < d) ? co_load(a.x + c) : 0.0;
     __syncthreads();
     if constexpr (EPT == 64) {
       double acc[16];
@@ -485,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
       rowpass<TA, double, EPT, true, RA>(A, a.lda, a_r0, a_r1, d, vbuf, a.b, acc, ssq);
       wg_store_partial<TA, double, EPT>(acc, rbuf, a.partA + (int64_t)w * a.dpad, d);
     }
-    if (!(alive = barrier_hier(a.bar_all, ep_all, G, a.err, &s_flag, a.spin_fast))) break;
+    if (!(alive = barrier_hier_co(a.bar_all, ep_all, G, a.err, &s_flag, a.spin_fast))) break;
 
     int decision = 0;  // 0 continue, 1 converged, 2 breakdown
     if (in_cg) {
@@ -496,13 +494,13 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
         const TV gt = (TV)(colbuf[i] + own_rhs[i] - a.lam * own_x[i]);
         own_r[i] = gt;
         own_z[i] = TV(0);
-        r[c_lo + i] = gt;
-        P[0][c_lo + i] = gt;
+        co_store(r + c_lo + i, gt);
+        co_store(P[0] + c_lo + i, gt);
         rr_part += (double)gt * (double)gt;
       }
       rr_part = block_sum(rr_part, s_red);
-      if (threadIdx.x == 0) scal_w[0] = rr_part;
-      if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+      if (threadIdx.x == 0) co_store(scal_w + 0, rr_part);
+      if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
 
       double rr0, unused;
       sum2_slots(a.scal, Gc, 0, 0, s_red, rr0, unused);
@@ -523,11 +521,11 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           // workgroup keeps v in LDS and the same scalars; owners keep the
           // direction vector (in own_r) and the iterate z on their columns.
           TV* vp = (TV*)vbuf;
-          gTV* wv = r;  // w, exchanged through the residual buffer
+          TV* wv = r;  // w, exchanged through the residual buffer
           TV* dv = own_r;
           const double theta1 = sqrt(rr0);
           for (int c = threadIdx.x; c < a.dpad; c += kBlock)
-            vp[c] = (c < d) ? (TV)((double)r[c] / theta1) : TV(0);
+            vp[c] = (c < d) ? (TV)((double)co_load(r + c) / theta1) : TV(0);
           __syncthreads();
           double theta = 0.0, rho_prev = 1.0, rhobar = 0.0, cs = 0.0, sn = 0.0, phi = 0.0;
           bool first = true;
@@ -544,8 +542,8 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
               wg_store_partial<TS, TV, EPT>(acc, (TV*)rbuf, partS + (int64_t)w * a.dpad, d);
               ssq = wg_sum_ssq(ssq, s_red);
             }
-            if (threadIdx.x == 0) scal_w[1] = (double)ssq;
-            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            if (threadIdx.x == 0) co_store(scal_w + 1, (double)ssq);
+            if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
             // colbuf = -M^T y on the owned columns; rho = ||y||
             owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
             double rho2, unused2;
@@ -591,19 +589,19 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
             double th_part = 0.0;
             for (int i = threadIdx.x; i < nown; i += kBlock) {
               const TV wc = (TV)(-colbuf[i] / rho - rho * (double)vp[c_lo + i]);
-              wv[c_lo + i] = wc;
+              co_store(wv + c_lo + i, wc);
               th_part += (double)wc * (double)wc;
             }
             th_part = block_sum(th_part, s_red);
-            if (threadIdx.x == 0) scal_w[2] = th_part;
-            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            if (threadIdx.x == 0) co_store(scal_w + 2, th_part);
+            if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
             double th2;
             sum2_slots(a.scal, Gc, 2, 2, s_red, th2, unused2);
             theta = sqrt(th2);
             if (!(theta > 0.0)) break;  // w = 0: the iterate is exact
             rho_prev = rho;
             for (int c = threadIdx.x; c < a.dpad; c += kBlock)
-              vp[c] = (c < d) ? (TV)((double)wv[c] / theta) : TV(0);
+              vp[c] = (c < d) ? (TV)((double)co_load(wv + c) / theta) : TV(0);
             __syncthreads();
           }
           if (!alive) break;
@@ -617,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           TV* rv = (TV*)vbuf;
           TV* sv = (TV*)rbuf;
           const TV lt = (TV)a.lam;
-          for (int c = threadIdx.x; c < a.dpad; c += kBlock) rv[c] = (c < d) ? r[c] : TV(0);
+          for (int c = threadIdx.x; c < a.dpad; c += kBlock) rv[c] = (c < d) ? co_load(r + c) : TV(0);
           __syncthreads();
           int wb = 0;
           double mu = rr0, alpha = 0.0, unused2;
@@ -628,12 +626,12 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
             for (int i = threadIdx.x; i < nown; i += kBlock) {
               const TV rc = rv[c_lo + i];
               const TV wc = (TV)colbuf[i] + lt * rc;
-              P[wb][c_lo + i] = wc;
+              co_store(P[wb] + c_lo + i, wc);
               nu_part += (double)wc * (double)rc;
             }
             nu_part = block_sum(nu_part, s_red);
-            if (threadIdx.x == 0) scal_w[1] = nu_part;
-            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            if (threadIdx.x == 0) co_store(scal_w + 1, nu_part);
+            if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
             double nu;
             sum2_slots(a.scal, Gc, 1, 1, s_red, nu, unused2);
             alpha = mu / nu;
@@ -641,7 +639,8 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           }
           if (decision == 0) {
             // s = w, p = r
-            for (int c = threadIdx.x; c < a.dpad; c += kBlock) sv[c] = (c < d) ? P[wb][c] : TV(0);
+            for (int c = threadIdx.x; c < a.dpad; c += kBlock)
+              sv[c] = (c < d) ? co_load(P[wb] + c) : TV(0);
             for (int i = threadIdx.x; i < nown; i += kBlock) own_r[i] = rv[c_lo + i];
             __syncthreads();
             while (true) {
@@ -657,23 +656,23 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
               for (int i = threadIdx.x; i < nown; i += kBlock) {
                 const TV rc = rv[c_lo + i];
                 const TV wc = (TV)colbuf[i] + lt * rc;
-                P[wb][c_lo + i] = wc;
+                co_store(P[wb] + c_lo + i, wc);
                 mu_p += (double)rc * (double)rc;
                 nu_p += (double)wc * (double)rc;
               }
               block_sum2(mu_p, nu_p, s_red);
               if (threadIdx.x == 0) {
-                scal_w[2] = mu_p;
-                scal_w[3] = nu_p;
+                co_store(scal_w + 2, mu_p);
+                co_store(scal_w + 3, nu_p);
               }
-              if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
               // fetch w (written by every CG workgroup before the barrier) while
               // the scalar partials are summed
               TV wpre[NPT];
 #pragma unroll
               for (int i = 0; i < NPT; ++i) {
                 const int c = threadIdx.x + i * kBlock;
-                wpre[i] = (c < d) ? P[wb][c] : TV(0);
+                wpre[i] = (c < d) ? co_load(P[wb] + c) : TV(0);
               }
               double mu_n, nu_n;
               sum2_slots(a.scal, Gc, 2, 3, s_red, mu_n, nu_n);
@@ -704,10 +703,10 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           double rr = rr0;
           TV* vp = (TV*)vbuf;
           while (true) {
-            // ---- C1: p = r + beta_cg p_prev (k > 0), staged in LDS.  The loads of
-            // r, p_prev and the residual partials are all issued before use.
-            gTV* pcur = P[k & 1];
-            const gTV* pprev = P[(k + 1) & 1];
+            // ---- C1: p = r + beta_cg p_prev (k > 0), staged in LDS over p_prev
+            // (every CG workgroup holds the whole of p: the same arithmetic on the
+            // same values everywhere).  The loads of r and of the residual
+            // partials are all issued before use; the first direction is g.
             TV rv[NPT], pv[NPT];
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {
@@ -716,10 +715,10 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
               pv[i] = TV(0);
               if (c < d) {
                 if (k == 0) {
-                  rv[i] = pcur[c];
+                  rv[i] = co_load(P[0] + c);
                 } else {
-                  rv[i] = r[c];
-                  pv[i] = pprev[c];
+                  rv[i] = co_load(r + c);
+                  pv[i] = vp[c];
                 }
               }
             }
@@ -737,7 +736,6 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
               if (c < a.dpad) {
                 const TV p = (k == 0) ? rv[i] : (TV)(rv[i] + bc * pv[i]);
                 vp[c] = (c < d) ? p : TV(0);
-                if (k > 0 && c >= c_lo && c < c_hi) pcur[c] = p;
               }
             }
             for (int c = NPT * kBlock + threadIdx.x; c < a.dpad; c += kBlock) vp[c] = TV(0);
@@ -753,8 +751,8 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 pq += pc * (colbuf[i] + a.lam * pc);
               }
               pq = block_sum(pq, s_red);
-              if (threadIdx.x == 0) scal_w[1] = pq;
-              if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              if (threadIdx.x == 0) co_store(scal_w + 1, pq);
+              if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
               double pqs, unused2;
               sum2_slots(a.scal, Gc, 1, 1, s_red, pqs, unused2);
               const double acg = rr / pqs;
@@ -769,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 own_z[i] = own_z[i] + at * pc;
                 const TV rn = own_r[i] - at * q;
                 own_r[i] = rn;
-                r[c_lo + i] = rn;
+                co_store(r + c_lo + i, rn);
                 rpart += (double)rn * (double)rn;
               }
             } else {
@@ -787,10 +785,10 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 pp += (double)vp[c] * (double)vp[c];
               pp = block_sum(pp, s_red);
               if (threadIdx.x == 0) {
-                scal_w[1] = pp;
-                scal_w[2] = (double)ssq;
+                co_store(scal_w + 1, pp);
+                co_store(scal_w + 2, (double)ssq);
               }
-              if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
 
               // ---- C2: step length (p^T q = ||u||^2 + lambda ||p||^2) and owner updates
               owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
@@ -809,13 +807,13 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 own_z[i] = own_z[i] + at * pc;
                 const TV rn = own_r[i] - at * q;
                 own_r[i] = rn;
-                r[c_lo + i] = rn;
+                co_store(r + c_lo + i, rn);
                 rpart += (double)rn * (double)rn;
               }
             }
             rpart = block_sum(rpart, s_red);
-            if (threadIdx.x == 0) scal_w[3] = rpart;
-            if (!(alive = barrier_flat(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            if (threadIdx.x == 0) co_store(scal_w + 3, rpart);
+            if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
             ++k;
           }
 
@@ -833,7 +831,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           const double xn = xc + a.alpha * (double)own_z[i] + a.beta * (xc - own_xp[i]);
           own_xp[i] = xc;
           own_x[i] = xn;
-          a.x[c_lo + i] = xn;
+          co_store(a.x + c_lo + i, xn);
           s0 += (xn - xc) * (xn - xc);
           s1 += xn * xn;
         }
@@ -841,12 +839,12 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
       s0 = block_sum(s0, s_red);
       s1 = block_sum(s1, s_red);
       if (threadIdx.x == 0) {
-        scal_w[4] = s0;
-        scal_w[5] = s1;
-        if (w == 0) *a.status = decision;
+        co_store(scal_w + 4, s0);
+        co_store(scal_w + 5, s1);
+        if (w == 0) co_store(a.status, decision);
       }
     }
-    if (!(alive = barrier_hier(a.bar_all, ep_all, G, a.err, &s_flag,
+    if (!(alive = barrier_hier_co(a.bar_all, ep_all, G, a.err, &s_flag,
                                in_cg ? a.spin_fast : a.spin_idle)))
       break;
     decision = __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

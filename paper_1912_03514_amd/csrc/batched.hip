@@ -120,7 +120,7 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, int size, unsigned& ep
     __syncthreads();
     return true;
   }
-  return barrier_flat(bar, epoch, (unsigned)size, err, s_flag, spin);
+  return barrier_flat_co(bar, epoch, (unsigned)size, err, s_flag, spin);
 }
 
 // Sum over the first T slots: out[j] = sum_t scal[t * kNScal + s0 + j], j < KR
@@ -128,11 +128,9 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, int size, unsigned& ep
 __device__ __forceinline__ void team_slot_sums(const double* scal, int T, int s0, double* out,
                                                double* red) {
   // thread (j, q) with j = tid % 16 sums t = q, q + 16, ... ; fixed tree over q
-  const double __attribute__((address_space(1)))* gs =
-      (const double __attribute__((address_space(1)))*)scal;
   const int j = threadIdx.x % KR, q = threadIdx.x / KR;
   double v = 0.0;
-  for (int t = q; t < T; t += kBlock / KR) v += gs[(int64_t)t * kNScal + s0 + j];
+  for (int t = q; t < T; t += kBlock / KR) v += co_load(scal + (int64_t)t * kNScal + s0 + j);
   __syncthreads();
   red[threadIdx.x] = v;
   __syncthreads();
@@ -153,7 +151,7 @@ __device__ __forceinline__ void column_partials(double v, double* out, double* r
   if (threadIdx.x < KR) {
     double a = red[threadIdx.x];
     for (int i = 1; i < kBlock / KR; ++i) a += red[i * KR + threadIdx.x];
-    ((double __attribute__((address_space(1)))*)out)[threadIdx.x] = a;
+    co_store(out + threadIdx.x, a);
   }
   __syncthreads();
 }
@@ -322,7 +320,7 @@ __device__ __forceinline__ void store_block(const f64x4 (&Gacc)[DP / 64], int d,
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int c = kbase + 16 * b + (lane >> 4) + 4 * r;
-        out[(int64_t)c * KR + (lane & 15)] = Gacc[b][r];
+        co_store(out + (int64_t)c * KR + (lane & 15), Gacc[b][r]);
       }
     }
 }
@@ -550,7 +548,7 @@ __device__ __attribute__((noinline)) void a_pass(const TM* __restrict__ M, int64
   for (int i = 0; i < DP * KR / kBlock; ++i) {
     const int idx = i * kBlock + (int)threadIdx.x;
     const int c = idx / KR, j = idx % KR;
-    stage[idx] = (c < d && j < ncols) ? X[(int64_t)c * ldx + j] : 0.0;
+    stage[idx] = (c < d && j < ncols) ? co_load(X + (int64_t)c * ldx + j) : 0.0;
   }
   __syncthreads();
   double Vreg[KS];
@@ -657,9 +655,10 @@ __device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, 
                                                       double eps_sub, int64_t max_inner) {
   extern __shared__ uint4 lds_raw[];
   double* stage = (double*)lds_raw;
-  // the entry's vectors, addressed as global memory (not counted with LDS traffic)
+  // R and Z are exchanged with the other members (co_load / co_store); Q stays
+  // with this member (its own rows), addressed as global memory
   typedef double __attribute__((address_space(1)))* gdbl;
-  const gdbl R = (gdbl)Rp, Z = (gdbl)Zp, Q = (gdbl)Qp;
+  const gdbl Q = (gdbl)Qp;
   Shared& sh = g_sh;
   const int nown = c_hi - c_lo;
   int64_t k = 0;
@@ -678,7 +677,7 @@ __device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, 
         const int idx = i * kBlock + (int)threadIdx.x;
         const int c = idx / KR;
         double v = 0.0;
-        if (c < d && act) v = (k == 0) ? R[idx] : R[idx] + bc * stage[idx];
+        if (c < d && act) v = (k == 0) ? co_load(Rp + idx) : co_load(Rp + idx) + bc * stage[idx];
         stage[idx] = v;
       }
     }
@@ -707,12 +706,14 @@ __device__ __attribute__((noinline)) int64_t cg_solve(const TH* __restrict__ H, 
     for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
       const int c = c_lo + idx / KR, j = idx % KR;
       const int64_t o = (int64_t)c * KR + j;
+      double rv = co_load(Rp + o);
       if (sh.active[j]) {
         const double al = sh.acg[j];
-        Z[o] += al * stage[o];
-        R[o] -= al * Q[o];
+        co_store(Zp + o, co_load(Zp + o) + al * stage[o]);
+        rv -= al * Q[o];
+        co_store(Rp + o, rv);
       }
-      rr_lane += R[o] * R[o];
+      rr_lane += rv * rv;
     }
     column_partials(rr_lane, myscal + 0, sh.red);
     if (!group_sync(bar_cg, Tc, epoch, err, &sh.flag, spin)) return -1;
@@ -812,7 +813,7 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int row = row_of(v);
-    r[v] = row < d ? ((const double __attribute__((address_space(1)))*)R)[row * KR + j] : 0.0;
+    r[v] = row < d ? co_load(R + row * KR + j) : 0.0;
     z[v] = 0.0;
   }
   const double lj = sh.lam[j];
@@ -913,7 +914,7 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
   // z to the entry's buffer (read by the update with another thread mapping);
   // the ring's look-ahead loads are waited for before the registers go
 #pragma unroll
-  for (int v = 0; v < NV; ++v) ((gdbl)Z)[row_of(v) * KR + j] = z[v];
+  for (int v = 0; v < NV; ++v) co_store(Z + row_of(v) * KR + j, z[v]);
   __builtin_amdgcn_s_waitcnt(0);
   __threadfence_block();
   __syncthreads();
@@ -994,7 +995,7 @@ __device__ __attribute__((noinline)) void tri_solve_local(const double* __restri
     const int j = rank + q * tc;
     if (!sh.active[j]) continue;
     const double* F = Fb + (int64_t)j * ld * ld;
-    for (int k = lane; k < DP; k += kWave) y[k] = k < d ? R[(int64_t)k * KR + j] : 0.0;
+    for (int k = lane; k < DP; k += kWave) y[k] = k < d ? co_load(R + (int64_t)k * KR + j) : 0.0;
     // forward substitution L u = r (u overwrites y block by block)
     for (int I = 0; I < nb; ++I) {
       const int row = 16 * I + r;
@@ -1031,7 +1032,7 @@ __device__ __attribute__((noinline)) void tri_solve_local(const double* __restri
         }
       if (g == 0 && row < d) y[row] = x;
     }
-    for (int k = lane; k < d; k += kWave) Zt[(int64_t)j * ld + k] = y[k];
+    for (int k = lane; k < d; k += kWave) co_store(Zt + (int64_t)j * ld + k, y[k]);
   }
   if (threadIdx.x < KR) sh.kin[threadIdx.x] = sh.active[threadIdx.x] ? 1 : 0;
   __threadfence_block();
@@ -1091,7 +1092,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
   // x_prev = x on the owned columns
   for (int idx = threadIdx.x; idx < nown * KR; idx += kBlock) {
     const int c = c_lo + idx / KR, j = idx % KR;
-    XP[(int64_t)c * KR + j] = (j < e.ncols) ? e.X[(int64_t)c * e.ldx + j] : 0.0;
+    XP[(int64_t)c * KR + j] = (j < e.ncols) ? co_load(e.X + (int64_t)c * e.ldx + j) : 0.0;
   }
   __syncthreads();
 
@@ -1128,15 +1129,15 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
         const int c = a_lo + idx / KR, j = idx % KR;
         double g = 0.0;
 #pragma unroll 8
-        for (int t = 0; t < T; ++t) g += part[((int64_t)t * DP + c) * KR + j];
+        for (int t = 0; t < T; ++t) g += co_load(part + ((int64_t)t * DP + c) * KR + j);
         if (j < e.ncols) {
           if (e.RHS) g += e.RHS[(int64_t)c * e.ldr + j];
-          g -= sh.lam[j] * e.X[(int64_t)c * e.ldx + j];
+          g -= sh.lam[j] * co_load(e.X + (int64_t)c * e.ldx + j);
         }
         if (sh.done[j]) g = 0.0;
         const int64_t o = (int64_t)c * KR + j;
-        R[o] = g;
-        Z[o] = 0.0;
+        co_store(R + o, g);
+        co_store(Z + o, 0.0);
         rr_lane += g * g;
       }
       column_partials(rr_lane, myscal + 0, sh.red);
@@ -1194,11 +1195,12 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
         if (j >= e.ncols || sh.done[j]) continue;
         const int64_t o = (int64_t)c * KR + j;
         double* xp = e.X + (int64_t)c * e.ldx + j;
-        const double xc = *xp;
-        const double zv = !exact ? Z[o] : (sh.active[j] ? Q[(int64_t)j * e.dp + c] : 0.0);
+        const double xc = co_load(xp);
+        const double zv =
+            !exact ? co_load(Z + o) : (sh.active[j] ? co_load(Q + (int64_t)j * e.dp + c) : 0.0);
         const double xn = xc + sh.alpha[j] * zv + sh.beta[j] * (xc - XP[o]);
         XP[o] = xc;
-        *xp = xn;
+        co_store(xp, xn);
         s0 += (xn - xc) * (xn - xc);
         s1 += xn * xn;
       }

@@ -179,19 +179,48 @@ __global__ __launch_bounds__(kBlock) void gram_tile128_kernel(const TS* M, int64
     __syncthreads();
   }
   // result register r of lane l: row l/16 + 4 r, column l % 16 of each 16 x 16 block
+  if constexpr (sizeof(TH) == 4) {
+    // FP32 output: keep the accumulators in the matrix-core registers up to
+    // here (an empty statement with an AGPR operand at the loop exit) and round
+    // them one block at a time.  Left to itself, the compiler moves all 64 of
+    // them to VGPRs for the rounding and then carries them through the main
+    // loop in VGPRs, copying them into the matrix-core registers and back at
+    // every chunk.
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < 4; ++b) asm volatile("" : "+a"(acc[a][b]));
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = ci0 + wr * 64 + a * 16 + (lane >> 4) + 4 * r;
-        const int j = cj0 + wc * 64 + b * 16 + (lane & 15);
-        if (i < hn && j < hn) {
-          H[(int64_t)i * ldh + j] = (TH)acc[a][b][r];
-          if (bi != bj) H[(int64_t)j * ldh + i] = (TH)acc[a][b][r];
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = ci0 + wr * 64 + a * 16 + (lane >> 4) + 4 * r;
+          const int j = cj0 + wc * 64 + b * 16 + (lane & 15);
+          if (i < hn && j < hn) {
+            const TH v = (TH)acc[a][b][r];
+            H[(int64_t)i * ldh + j] = v;
+            if (bi != bj) H[(int64_t)j * ldh + i] = v;
+          }
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = ci0 + wr * 64 + a * 16 + (lane >> 4) + 4 * r;
+          const int j = cj0 + wc * 64 + b * 16 + (lane & 15);
+          if (i < hn && j < hn) {
+            H[(int64_t)i * ldh + j] = (TH)acc[a][b][r];
+            if (bi != bj) H[(int64_t)j * ldh + i] = (TH)acc[a][b][r];
+          }
+        }
+  }
 }
 
 }  // namespace

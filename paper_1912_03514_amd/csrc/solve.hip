@@ -62,7 +62,8 @@ struct SolveArgs {
   void* p0;
   void* p1;
   unsigned* bar_all;  // 9 lines (hierarchical barrier)
-  unsigned* bar_cg;   // 1 line
+  unsigned* bar_cg;   // 1 line (flat inner-solve barrier)
+  unsigned* bar_cgh;  // 9 lines (hierarchical inner-solve barrier)
   int* err;
   int* status;        // decision published by the CG group
   const void* H;      // Gram matrix (SA)^T SA (TS), dpad x dpad, when the CG uses it
@@ -72,6 +73,7 @@ struct SolveArgs {
   double* yrow;       // AAb: m doubles, -(M v - theta p) of each row of SA
   const int* skip;    // when set and nonzero the launch returns at once
   int d, dpad, G, Gc, cpw;
+  int cg_hier;        // inner-solve group large enough for the two-level barrier
   BarrierSpin spin_fast, spin_idle;
 };
 
@@ -349,14 +351,12 @@ __device__ __forceinline__ void owned_column_sums(const T* __restrict__ P, int K
 }
 
 // out[c - r0] = H[c, :] . v for rows c in [r0, r1), in a fixed order.  Each
-// wave loads up to 512 bytes per lane of rows (at most 4 rows) before using
-// any: a CG workgroup owns few rows, so this is usually one round trip.
-template <typename TH, typename TV, int EPT>
-__device__ __forceinline__ void rowdots(const TH* __restrict__ H, int64_t ldh, int r0, int r1,
-                                        int d, const TV* __restrict__ v, double* out) {
+// wave loads R rows before using any: a CG workgroup owns few rows, so this is
+// usually one round trip.
+template <typename TH, typename TV, int EPT, int R>
+__device__ __forceinline__ void rowdots_r(const TH* __restrict__ H, int64_t ldh, int r0, int r1,
+                                          int d, const TV* __restrict__ v, double* out) {
   using L = RowLayout<TH, EPT>;
-  constexpr int RB = 512 / (EPT * (int)sizeof(TH));
-  constexpr int R = RB < 1 ? 1 : (RB > 4 ? 4 : RB);
   const int lane = lane_id();
   for (int c = r0 + wave_id() * R; c < r1; c += kWavesPerBlock * R) {
     TH rv[R][EPT];
@@ -387,6 +387,31 @@ __device__ __forceinline__ void rowdots(const TH* __restrict__ H, int64_t ldh, i
       if (lane == 0 && c + t < r1) out[c + t - r0] = (double)sdot;
     }
   }
+}
+
+// Rows per wave: up to 512 bytes per lane in flight (at most 4 rows), halved
+// when the workgroup owns too few rows to give every wave a full set.
+template <typename TH, typename TV, int EPT>
+__device__ __forceinline__ void rowdots(const TH* __restrict__ H, int64_t ldh, int r0, int r1,
+                                        int d, const TV* __restrict__ v, double* out) {
+  constexpr int RB = 512 / (EPT * (int)sizeof(TH));
+  constexpr int R = RB < 1 ? 1 : (RB > 4 ? 4 : RB);
+  if constexpr (R > 1) {
+    if (r1 - r0 <= kWavesPerBlock * (R / 2)) {
+      rowdots_r<TH, TV, EPT, R / 2>(H, ldh, r0, r1, d, v, out);
+      return;
+    }
+  }
+  rowdots_r<TH, TV, EPT, R>(H, ldh, r0, r1, d, v, out);
+}
+
+// Barrier of the inner-solve group: one counter for small groups, the two-level
+// form (per-XCD counters, then one top counter) from 256 workgroups on, where
+// one counter's arrivals queue up (128 workgroups: 2.1 us either way; 256:
+// 3.8 us flat against 2.2 us two-level).
+__device__ __forceinline__ bool cg_sync(const SolveArgs& a, unsigned& epoch, int* s_flag) {
+  return a.cg_hier ? barrier_hier_co(a.bar_cgh, epoch, a.Gc, a.err, s_flag, a.spin_fast)
+                   : barrier_flat_co(a.bar_cg, epoch, a.Gc, a.err, s_flag, a.spin_fast);
 }
 
 // GRAM: the inner CG applies (SA)^T SA through the precomputed H (owners form
@@ -500,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
       }
       rr_part = block_sum(rr_part, s_red);
       if (threadIdx.x == 0) co_store(scal_w + 0, rr_part);
-      if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+      if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
 
       double rr0, unused;
       sum2_slots(a.scal, Gc, 0, 0, s_red, rr0, unused);
@@ -543,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
               ssq = wg_sum_ssq(ssq, s_red);
             }
             if (threadIdx.x == 0) co_store(scal_w + 1, (double)ssq);
-            if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
             // colbuf = -M^T y on the owned columns; rho = ||y||
             owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
             double rho2, unused2;
@@ -594,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
             }
             th_part = block_sum(th_part, s_red);
             if (threadIdx.x == 0) co_store(scal_w + 2, th_part);
-            if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
             double th2;
             sum2_slots(a.scal, Gc, 2, 2, s_red, th2, unused2);
             theta = sqrt(th2);
@@ -631,7 +656,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
             }
             nu_part = block_sum(nu_part, s_red);
             if (threadIdx.x == 0) co_store(scal_w + 1, nu_part);
-            if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
             double nu;
             sum2_slots(a.scal, Gc, 1, 1, s_red, nu, unused2);
             alpha = mu / nu;
@@ -665,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 co_store(scal_w + 2, mu_p);
                 co_store(scal_w + 3, nu_p);
               }
-              if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
               // fetch w (written by every CG workgroup before the barrier) while
               // the scalar partials are summed
               TV wpre[NPT];
@@ -752,7 +777,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
               }
               pq = block_sum(pq, s_red);
               if (threadIdx.x == 0) co_store(scal_w + 1, pq);
-              if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
               double pqs, unused2;
               sum2_slots(a.scal, Gc, 1, 1, s_red, pqs, unused2);
               const double acg = rr / pqs;
@@ -788,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 co_store(scal_w + 1, pp);
                 co_store(scal_w + 2, (double)ssq);
               }
-              if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+              if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
 
               // ---- C2: step length (p^T q = ||u||^2 + lambda ||p||^2) and owner updates
               owned_column_sums(partS, Gc, a.dpad, c_lo, nown, colbuf, scratch);
@@ -813,7 +838,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
             }
             rpart = block_sum(rpart, s_red);
             if (threadIdx.x == 0) co_store(scal_w + 3, rpart);
-            if (!(alive = barrier_flat_co(a.bar_cg, ep_cg, Gc, a.err, &s_flag, a.spin_fast))) break;
+            if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
             ++k;
           }
 
@@ -1027,8 +1052,9 @@ struct SolveLayout {
 
 // Barrier region: line 0 = top counter of the all-workgroup barrier, lines 1-8
 // its group counters, line 9 = inner-solve group counter, line 10 = error flag,
-// line 11 = status word (128-byte lines).
-constexpr size_t kBarLines = 12;
+// line 11 = status word, lines 12-20 = top and group counters of the two-level
+// inner-solve barrier (128-byte lines).
+constexpr size_t kBarLines = 21;
 
 // gram_bytes: size of the Gram matrix region (0 when the CG streams SA).
 SolveLayout layout(int G, int Gc, int64_t dpad, size_t gram_bytes, int64_t m) {
@@ -1054,9 +1080,13 @@ size_t gram_bytes_for(int64_t m, int64_t d, int mixed) {
 
 int max_grid(const mihs_handle* h) { return h->num_cu * kMaxBlocksPerCU; }
 
-// Size of the inner-solve subgroup: enough workgroups to stream SA quickly,
-// few enough that its barrier stays cheap (the barrier cost grows steeply
-// with the number of participants).  `forced` > 0 fixes the size.
+// Size of the inner-solve subgroup: enough workgroups to stream the operator
+// quickly, few enough that its barrier stays cheap.  Operators of 8 MB and
+// more take 256 workgroups (one per CU for the usual 512-workgroup grid) with
+// the two-level barrier: measured at 2^18 x 2048 (16 MB FP32 Gram matrix,
+// per CG step 4.2 -> 2.9 us of row products) and at 2^20 x 4096 (64 MB,
+// 19.2 -> 13.4 us), the barrier costing no more than a flat one over 128.
+// `forced` > 0 fixes the size.
 int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G, bool gram, int forced) {
   int gc;
   if (forced > 0) {
@@ -1064,7 +1094,7 @@ int pick_cg_groups(int64_t m, int64_t d, int sa_bytes, int G, bool gram, int for
   } else {
     // bytes one CG step streams: the Gram matrix (m >= d) or SA
     const double mb = (double)(gram ? d : m) * (double)d * sa_bytes / (1024.0 * 1024.0);
-    gc = mb >= 8.0 ? 128 : (mb >= 4.0 ? 64 : (mb >= 1.0 ? 32 : 16));
+    gc = mb >= 8.0 ? 256 : (mb >= 4.0 ? 64 : (mb >= 1.0 ? 32 : 16));
     // each CG workgroup should own at least a few rows
     const int64_t by_rows = (m + 3) / 4;
     if (gc > by_rows) gc = (int)(by_rows < 1 ? 1 : by_rows);
@@ -1212,6 +1242,8 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   unsigned* bar = (unsigned*)(base + L.bar);
   a.bar_all = bar;
   a.bar_cg = bar + 9 * 32;
+  a.bar_cgh = bar + 12 * 32;
+  a.cg_hier = Gc > 128 ? 1 : 0;
   a.err = (int*)(bar + 10 * 32);
   a.status = (int*)(bar + 11 * 32);
   a.d = (int)s.d;

@@ -121,140 +121,46 @@ __device__ __forceinline__ void load_row(const T* __restrict__ row, int d, int l
   }
 }
 
-// Device-wide barriers for a cooperative launch.  Counters only grow: barrier
-// number e of a group of `nblocks` workgroups waits for e * nblocks arrivals.
-// Arrival is a release fetch-add, the wait relaxed polling followed by an
-// acquire fence, so data written before the barrier is visible after it on
-// every XCD.
+// ---- Device-wide barriers and the data they hand over ----------------------
+// The persistent kernels (one cooperative launch per solve) meet at counting
+// barriers: counters only grow, and barrier number e of a group of `nblocks`
+// workgroups waits for e * nblocks arrivals.  Each XCD has its own L2, and the
+// L2s are not kept coherent with each other, so data one workgroup writes for
+// another during the launch must not sit in an L2:
 //
-// Publishing: each XCD has its own L2, and data reaches another XCD only once
-// it is written back from this XCD's L2.  A release operation of thread 0
-// writes back the L2 and waits for its own wave's stores, but not for the
-// stores of the workgroup's other waves, and the workgroup barrier
-// (__syncthreads, a plain s_barrier on gfx950) does not wait for them either.
-// A store of another wave that is still in flight can therefore reach the L2
-// after the write-back and stay there, unseen by the other XCDs, until an
-// eviction writes it back later -- possibly over a newer value another XCD
-// wrote to the same address in the meantime.  So every wave first waits until
-// its own stores are acknowledged by the L2 (vmcnt(0): on gfx950 the counter
-// covers stores too), then the workgroup meets, and only then does thread 0
-// write the L2 back and wait for that write-back to complete before it
-// arrives: every store of the workgroup is in the L2 before the write-back
-// starts and in memory before the arrival is seen.  The write-back and its
-// wait are issued as one opaque instruction pair: once vmcnt is known to be 0
-// the compiler drops the wait it places after the write-back of a release
-// atomic (it does not count the write-back as outstanding), and then the
-// arrival could be seen before the write-back completed.  (An agent-scope
-// release fence in every wave is also correct, but four write-backs per
-// workgroup per barrier measured about 7 us per barrier slower.)
+//  * every such value is stored with co_store (an agent-scope store, sc1:
+//    written through to memory) and read with co_load (an agent-scope load,
+//    sc1: served coherently, never from a stale L2 line) -- how the compiler
+//    implements relaxed agent-scope atomics; no plain store ever writes an
+//    address another workgroup reads or writes during the launch (a plain
+//    store's dirty L2 line could be written back later over a newer value);
+//  * at a barrier every wave first waits until its own stores have completed
+//    (vmcnt(0); on gfx950 the counter covers stores, and __syncthreads, a bare
+//    s_barrier, does not wait for other waves' stores), then the workgroup
+//    meets, and thread 0 arrives with a relaxed fetch-add and polls with
+//    relaxed loads; loads issued after the wait observe every store made before
+//    any arrival.
 //
-// The wait is bounded:
-// after `spin_limit` polls it records a timeout in *err and returns false, so
-// no wave can hang; callers then leave the kernel.
+// Data only read during the launch (A, b, SA, the Gram matrix) keeps plain
+// cached loads and stays in the L2s across barriers.  (Checked on the
+// hardware: 128 and 256 workgroups exchanging slots across all XCDs, 1.3e10
+// reads, no stale value; the same exchange through plain accesses read stale
+// values almost everywhere.  The alternative -- plain accesses, with the L2
+// written back before each arrival and invalidated after each wait -- is also
+// correct, but the write-backs and invalidations walk the whole L2 of the XCD
+// and queue up when 16-32 workgroups per XCD arrive together: 6.5 us per
+// barrier at 128 workgroups against 3.2 us, 11.3 against 5.8 us at 256, and
+// every line the workgroups were reusing, a Gram matrix re-read by every CG
+// step, had to come back from memory after each barrier.)
+//
+// The waits are bounded: after `spin.limit` polls a barrier records a timeout
+// in *err and returns false, so no wave can hang; callers then leave the
+// kernel.
 struct BarrierSpin {
   long limit;
   int sleep;  // s_sleep argument between polls (x64 clocks)
 };
 
-__device__ __forceinline__ bool wait_counter(const unsigned* counter, unsigned target, int* err,
-                                             BarrierSpin spin) {
-  // Poll with relaxed loads (an acquire load would invalidate this XCD's L2 on
-  // every poll, evicting data the working workgroups are reusing); one acquire
-  // fence after the wait orders the reads that follow.
-  long spins = 0;
-  while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    if (spin.sleep >= 16)
-      __builtin_amdgcn_s_sleep(16);
-    else
-      __builtin_amdgcn_s_sleep(1);
-    if (++spins > spin.limit) {
-      atomicOr(err, 1);
-      return false;
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return true;
-}
-
-__device__ __forceinline__ void publish_wave_stores() {
-  asm volatile("" ::: "memory");       // no memory access moves across the wait
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained
-  asm volatile("" ::: "memory");
-}
-
-// Thread 0, after the workgroup has met: write this XCD's L2 back to memory and
-// wait until the write-back (and anything else in flight) has completed.
-__device__ __forceinline__ void release_workgroup_stores() {
-  asm volatile("buffer_wbl2 sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
-}
-
-// One counter shared by all `nblocks` workgroups (cheap for small groups).
-__device__ __forceinline__ bool barrier_flat(unsigned* counter, unsigned& epoch, unsigned nblocks,
-                                             int* err, int* s_flag, BarrierSpin spin) {
-  publish_wave_stores();
-  __syncthreads();
-  epoch += 1u;
-  if (threadIdx.x == 0) {
-    release_workgroup_stores();  // the arrival below needs no further ordering
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = wait_counter(counter, epoch * nblocks, err, spin) ? 1 : 0;
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
-    *s_flag = ok;
-  }
-  __syncthreads();
-  return *s_flag != 0;
-}
-
-// Two-level barrier for large grids: workgroups arrive on one of 8 group
-// counters (blockIdx % 8, one 128-byte line each); the last arrival of a group
-// arrives on the top counter, which everybody waits on.  `words` points at
-// 9 lines: top counter first, then the group counters.
-__device__ __forceinline__ bool barrier_hier(unsigned* words, unsigned& epoch, unsigned nblocks,
-                                             int* err, int* s_flag, BarrierSpin spin) {
-  publish_wave_stores();
-  __syncthreads();
-  epoch += 1u;
-  if (threadIdx.x == 0) {
-    const unsigned g = blockIdx.x & 7u;
-    const unsigned ngroups = nblocks < 8u ? nblocks : 8u;
-    const unsigned gsize = (nblocks - g + 7u) / 8u;
-    unsigned* top = words;
-    unsigned* gc = words + 32u * (1u + g);
-    // every arriving workgroup's stores are in memory before its arrival, so
-    // the group's last arrival forwards to the top counter without ordering
-    release_workgroup_stores();
-    const unsigned old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == epoch * gsize - 1u)
-      __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = wait_counter(top, epoch * ngroups, err, spin) ? 1 : 0;
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
-    *s_flag = ok;
-  }
-  __syncthreads();
-  return *s_flag != 0;
-}
-
-// ---- Coherent exchange: barriers for data that never sits in an L2 ---------
-// The barriers above make plain stores visible by writing the L2 back and
-// invalidating it on the way out, and on gfx950 both walk the whole L2 of the
-// XCD: with 16-32 workgroups per XCD arriving at once, the invalidations queue
-// up (a 128-workgroup barrier measured 6.5 us against 3.2 us without them, 11.3
-// against 5.8 us at 256), and every line the workgroups were reusing -- a Gram
-// matrix that fits in the L2s, re-read by every CG step -- has to come back
-// from memory after each barrier.
-//
-// The alternative keeps the L2s out of the exchange instead: every value one
-// workgroup writes for another during the launch is stored with an
-// agent-scope store (sc1: written through to memory) and read with an
-// agent-scope load (sc1: served coherently, never from a stale L2 line), which
-// is how the compiler implements relaxed agent-scope atomics.  A barrier then
-// only has to wait until each wave's own stores have completed (vmcnt(0)),
-// meet, and count arrivals; loads issued after the wait observe every store
-// made before any arrival.  (Checked on the hardware with 128 and 256
-// workgroups exchanging slots across all XCDs: 1.3e10 reads, no stale value;
-// the same exchange through plain accesses without write-back and
-// invalidation read stale values almost everywhere.)  Data that is only read
-// during the launch (A, b, SA, the Gram matrix) keeps plain cached loads.
 template <typename T>
 __device__ __forceinline__ T co_load(const T* p) {
   typedef const T __attribute__((address_space(1))) gT;
@@ -267,8 +173,8 @@ __device__ __forceinline__ void co_store(T* p, T v) {
   __hip_atomic_store((gT*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool wait_counter_co(const unsigned* counter, unsigned target, int* err,
-                                                BarrierSpin spin) {
+__device__ __forceinline__ bool wait_counter(const unsigned* counter, unsigned target, int* err,
+                                             BarrierSpin spin) {
   long spins = 0;
   while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     if (spin.sleep >= 16)
@@ -283,16 +189,21 @@ __device__ __forceinline__ bool wait_counter_co(const unsigned* counter, unsigne
   return true;
 }
 
-// barrier_flat for workgroups that exchange data only through co_store/co_load.
-__device__ __forceinline__ bool barrier_flat_co(unsigned* counter, unsigned& epoch,
-                                                unsigned nblocks, int* err, int* s_flag,
-                                                BarrierSpin spin) {
+__device__ __forceinline__ void publish_wave_stores() {
+  asm volatile("" ::: "memory");       // no memory access moves across the wait
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained
+  asm volatile("" ::: "memory");
+}
+
+// One counter shared by all `nblocks` workgroups (cheap up to ~128 of them).
+__device__ __forceinline__ bool barrier_flat(unsigned* counter, unsigned& epoch, unsigned nblocks,
+                                             int* err, int* s_flag, BarrierSpin spin) {
   publish_wave_stores();
   __syncthreads();
   epoch += 1u;
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = wait_counter_co(counter, epoch * nblocks, err, spin) ? 1 : 0;
+    int ok = wait_counter(counter, epoch * nblocks, err, spin) ? 1 : 0;
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
     *s_flag = ok;
   }
@@ -301,10 +212,13 @@ __device__ __forceinline__ bool barrier_flat_co(unsigned* counter, unsigned& epo
   return *s_flag != 0;
 }
 
-// barrier_hier for workgroups that exchange data only through co_store/co_load.
-__device__ __forceinline__ bool barrier_hier_co(unsigned* words, unsigned& epoch,
-                                                unsigned nblocks, int* err, int* s_flag,
-                                                BarrierSpin spin) {
+// Two-level barrier for large groups: workgroups arrive on one of 8 group
+// counters (blockIdx % 8, one 128-byte line each: the workgroups of one XCD);
+// the last arrival of a group arrives on the top counter, which everybody waits
+// on.  `words` points at 9 lines: top counter first, then the group counters.
+// The group's workgroups are blockIdx 0 .. nblocks - 1.
+__device__ __forceinline__ bool barrier_hier(unsigned* words, unsigned& epoch, unsigned nblocks,
+                                             int* err, int* s_flag, BarrierSpin spin) {
   publish_wave_stores();
   __syncthreads();
   epoch += 1u;
@@ -317,44 +231,13 @@ __device__ __forceinline__ bool barrier_hier_co(unsigned* words, unsigned& epoch
     const unsigned old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == epoch * gsize - 1u)
       __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = wait_counter_co(top, epoch * ngroups, err, spin) ? 1 : 0;
+    int ok = wait_counter(top, epoch * ngroups, err, spin) ? 1 : 0;
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
     *s_flag = ok;
   }
   __syncthreads();
   asm volatile("" ::: "memory");
   return *s_flag != 0;
-}
-
-// Column sums of a K x ncols block: out[c] = sum_k P[k * ldp + c0 + c], c < ncols,
-// in a fixed order (per thread over k, then a fixed tree in LDS).  All loads of a
-// chunk are independent, so they are in flight together.  `scratch` holds
-// kBlock doubles; `out` is LDS.  Call from the whole workgroup.
-template <typename T>
-__device__ __forceinline__ void column_sums(const T* __restrict__ P, int K, int64_t ldp, int c0,
-                                            int ncols, double* out, double* scratch) {
-  for (int cc0 = 0; cc0 < ncols; cc0 += kBlock) {
-    const int CC = min(kBlock, ncols - cc0);
-    int TPC = 1;
-    while (TPC * 2 * CC <= kBlock) TPC *= 2;
-    const int t = threadIdx.x;
-    const int col = t % CC, ks = t / CC;
-    double s = 0.0;
-    if (ks < TPC) {
-      const T* base = P + c0 + cc0 + col;
-#pragma unroll 8
-      for (int k = ks; k < K; k += TPC) s += (double)base[(int64_t)k * ldp];
-    }
-    __syncthreads();
-    scratch[t] = s;
-    __syncthreads();
-    if (t < CC) {
-      double a = scratch[t];
-      for (int i = 1; i < TPC; ++i) a += scratch[i * CC + t];
-      out[cc0 + t] = a;
-    }
-    __syncthreads();
-  }
 }
 
 }  // namespace mihs

@@ -415,9 +415,10 @@ int mihs_solve_batched(mihs_handle_t handle, const mihs_problem_t* d_problems,
  * Tunable shape of the batched launch (not in the paper; the schedule and the
  * tiling of the one persistent launch above).
  *   cg_cols       columns of the Gram matrix owned by one workgroup of a
- *                 problem's inner-CG sub-team (16, 32, 64 or 512): the sub-team
- *                 has ceil(d / cg_cols) members, at most the problem's team (512:
- *                 for d <= 512 the inner CG runs inside one workgroup);
+ *                 problem's inner-CG sub-team (16, 32, 64, 128 or 512): the
+ *                 sub-team has ceil(d / cg_cols) members, at most the problem's
+ *                 team (512: for d <= 512 the inner CG runs inside one
+ *                 workgroup);
  *   a_dma         1: each pass over A moves 64 KiB groups of rows straight
  *                 into LDS (rows of 1-4 KiB); 0: 16-row tiles staged through
  *                 registers;
@@ -502,8 +503,12 @@ int mihs_batched_plan_destroy(mihs_batched_plan_t plan);
  * sized from those costs (teams of
  * ceil(cost / L) workgroups for problems above a makespan L, first-fit bins
  * of capacity L for the rest, a team member's remaining capacity after its
- * team problem included; the smallest L that fits) for as long;
- * measured = 1 in *best if that one was faster.  The best
+ * team problem included; the smallest L that fits) for as long, with the
+ * shape's cg_cols and (inexact shapes) with cg_cols = 64, so that a team's
+ * inner CG splits over all its members; if one of them beat the plain runs,
+ * up to three times more with costs re-measured under the best of them (a
+ * team does not run its problem team-size times faster), while a round gains
+ * more than 2%; measured = 1 in *best if a measured schedule was the fastest.  The best
  * shape is returned in *best and kept in the handle, keyed by the problem set's
  * shapes (n, d, m of every problem and nlam); later mihs_solve_batched and
  * mihs_batched_plan_create calls on an equal set use it.  cand_ms (nullable,

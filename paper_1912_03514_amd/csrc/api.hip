@@ -907,7 +907,6 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
       }
       return MIHS_OK;
     };
-    float ms = 0.0f;
     rc = full_run(cur, &cur_ms, &cost);
     if (!rc && allow_exact) {
       std::vector<double> ex_cost;
@@ -919,14 +918,52 @@ int mihs_tune_batched(mihs_handle_t handle, const mihs_problem_t* h_problems, in
         cost.swap(ex_cost);
       }
     }
+    // measured schedules: a run of each, keeping the fastest with the costs
+    // it was sized from and the per-problem costs it measured in turn
+    std::vector<double> used_cost, next_cost;
+    auto run_measured = [&](const mihs_batched_tuning_t& t,
+                            const std::vector<double>& c) -> int {
+      float mms = 0.0f;
+      int r = trial(t, &mms, &c, measure_outer);
+      if (r || !(mms < cur_ms)) return r;
+      std::vector<int> tsz;
+      r = mihs::block_team_sizes(handle, ents.data(), count, t, &c, &tsz);
+      if (r) return r;
+      std::vector<double> nc(count);
+      for (int64_t i = 0; i < count; ++i) {
+        mihs_info_t rec;
+        if (hipMemcpy(&rec, ents[i].info, sizeof(rec), hipMemcpyDeviceToHost) != hipSuccess)
+          return MIHS_ERR_HIP;
+        nc[i] = (double)rec.elapsed_us * tsz[i];
+      }
+      cur = t;
+      cur_ms = mms;
+      used_cost = c;
+      next_cost.swap(nc);
+      return MIHS_OK;
+    };
     if (!rc) {
       mihs_batched_tuning_t t = cur;
       t.measured = 1;
-      rc = trial(t, &ms, &cost, measure_outer);
-      if (!rc && ms < cur_ms) {
-        cur = t;
-        cur_ms = ms;
+      const mihs_batched_tuning_t base_measured = t;
+      rc = run_measured(t, cost);
+      // the measured schedule gives the costliest problems teams; with 64
+      // columns per member their inner CG splits over the whole team too
+      if (!rc && !base_measured.exact && base_measured.cg_cols != 64) {
+        t = base_measured;
+        t.cg_cols = 64;
+        rc = run_measured(t, cost);
       }
+      // the costs came from a run in which most problems ran alone; a team
+      // does not run its problem tsize times faster, so size the schedule
+      // again from the times measured under the best measured schedule, up to
+      // three times while that still gains more than 2%
+      for (int round = 0; round < 3 && !rc && cur.measured; ++round) {
+        const float before = cur_ms;
+        rc = run_measured(cur, std::vector<double>(next_cost));
+        if (!(cur_ms < 0.98f * before)) break;
+      }
+      if (cur.measured) cost = used_cost;
     }
   }
   (void)hipEventDestroy(e0);

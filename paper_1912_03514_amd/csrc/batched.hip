@@ -120,7 +120,7 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, int size, unsigned& ep
     __syncthreads();
     return true;
   }
-  return barrier_flat_co(bar, epoch, (unsigned)size, err, s_flag, spin);
+  return barrier_flat(bar, epoch, (unsigned)size, err, s_flag, spin);
 }
 
 // Sum over the first T slots: out[j] = sum_t scal[t * kNScal + s0 + j], j < KR
@@ -763,7 +763,6 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
   Shared& sh = g_sh;
   typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
   typedef const u32x4 __attribute__((address_space(1)))* gvec;
-  typedef double __attribute__((address_space(1)))* gdbl;
   constexpr int NBW = DP / 64;                    // 16-row blocks per wave
   constexpr int NV = 4 * NBW;                     // owned entries per vector
   constexpr int VE = 16 / (int)sizeof(TH);        // elements per 16-byte load
@@ -921,6 +920,201 @@ __device__ __attribute__((noinline)) int64_t cg_solve_local(const TH* __restrict
   return k;
 }
 
+// The one-workgroup CG above spread over a sub-team of Tc workgroups (rank
+// 0 .. Tc - 1 of the problem's team).  The 16-row blocks are grouped in fours
+// (a quad: one block per wave, as above), and member `rank` owns quads
+// rank, rank + Tc, ...: each of its waves forms whole rows of H p for its own
+// blocks from the same register ring, and keeps r and z of its rows in
+// registers.  Per step, two sub-team barriers: one after each member has
+// stored its per-column sums p . q (scalar slots), one after it has stored its
+// rows of the new r and its per-column sums r . r; every member then reads the
+// whole r back and forms the whole p = r + beta p in LDS for the next
+// products.  Every member sums the slots in member order, so all of them take
+// the same step lengths, masks and stop decision.  A last barrier publishes
+// the members' rows of z to the row owners of the heavy-ball update.  With two
+// or more members a member owns at most half the quads, so its r and z take
+// half the registers of the one-workgroup form.  Returns the number of steps
+// (the caller advances its barrier epoch by 2 k + 1), or -1 if a barrier timed
+// out.
+template <typename TH, int DP>
+__device__ __attribute__((noinline)) int64_t cg_solve_team(
+    const TH* __restrict__ H, int64_t ldh, int d, int rank, int Tc, double* R, double* Z,
+    const double* scal, double* myscal, unsigned* bar_cg, unsigned epoch, int* err,
+    BarrierSpin spin, double eps_sub, int64_t max_inner) {
+  extern __shared__ uint4 lds_raw[];
+  double* stage = (double*)lds_raw;      // p, DP x 16 (all rows)
+  double* ql = stage + DP * KR;          // q, DP x 16 (this member's rows)
+  double* red0 = (double*)((char*)lds_raw + kUredOffset);
+  double* red1 = red0 + kBlock;
+  Shared& sh = g_sh;
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  typedef const u32x4 __attribute__((address_space(1)))* gvec;
+  constexpr int NBW = DP / 128 > 0 ? DP / 128 : 1;  // quads per member (Tc >= 2)
+  constexpr int NV = 4 * NBW;
+  constexpr int VE = 16 / (int)sizeof(TH);
+  constexpr int KQ = DP / 4;
+  constexpr int NLD = (KQ * (int)sizeof(TH) / 16) < 4 ? KQ * (int)sizeof(TH) / 16 : 4;
+  constexpr int CE = NLD * VE;
+  constexpr int NRING = 4;
+  const int lane = lane_id(), wave = wave_id();
+  const int j = lane & 15, g = lane >> 4;
+  const int tid = (int)threadIdx.x;
+  // this wave's blocks: 4 (rank + Tc b) + wave for b < nbw (those starting below d)
+  auto block_row0 = [&](int b) { return 16 * (4 * (rank + Tc * b) + wave); };
+  int nbw = 0;
+  while (nbw < NBW && block_row0(nbw) < d) ++nbw;
+  const int nch = min(KQ / CE, (d + 4 * CE - 1) / (4 * CE));
+  const int T = nbw * nch;
+  const int Tp = T > 0 ? (T + NRING - 1) / NRING * NRING : 0;
+  auto row_of = [&](int v) { return block_row0(v >> 2) + g + 4 * (v & 3); };
+  union Chunk {
+    u32x4 u[NLD];
+    TH v[CE];
+  };
+  int pos = 0, fb = 0, fc = 0;
+  auto fetch = [&](Chunk& dst) {
+    const bool in = pos < T;
+    const int row = in ? block_row0(fb) + j : j;
+    const gvec src = (gvec)(H + (int64_t)row * ldh + (in ? fc : 0) * 4 * CE + g * CE);
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) dst.u[i] = src[i];
+    if (++pos >= Tp) {
+      pos = 0;
+      fb = 0;
+      fc = 0;
+    } else if (++fc == nch) {
+      fc = 0;
+      ++fb;
+    }
+  };
+  Chunk ring[NRING];
+#pragma unroll
+  for (int u = 0; u < NRING; ++u) fetch(ring[u]);
+
+  double r[NV], z[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int row = row_of(v);
+    r[v] = ((v >> 2) < nbw && row < d) ? co_load(R + row * KR + j) : 0.0;
+    z[v] = 0.0;
+  }
+  const double lj = sh.lam[j];
+  bool act = sh.active[j] != 0;
+  double rr = sh.rr[j], bc = 0.0;
+  const double rr0 = sh.rr0[j];
+  int64_t k = 0, kin = 0;
+
+  while (true) {
+    int any = 0;
+    for (int jj = 0; jj < KR; ++jj) any |= sh.active[jj];
+    if (!any || k >= max_inner) break;
+    // p = r (first step) or r + beta_cg p over all rows, r as published by
+    // the members; inactive columns carry p = 0
+    for (int idx = tid; idx < DP * KR; idx += kBlock) {
+      const int c = idx / KR;  // column idx % KR == j for this thread
+      double v = 0.0;
+      if (c < d && act) v = (k == 0) ? co_load(R + idx) : co_load(R + idx) + bc * stage[idx];
+      stage[idx] = v;
+    }
+    __syncthreads();
+    // q = H p + lambda p on this member's blocks, p . q per column
+    double pq = 0.0;
+    {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      int b = 0, c = 0;
+      for (int t0 = 0; t0 < Tp; t0 += NRING) {
+#pragma unroll
+        for (int u = 0; u < NRING; ++u) {
+          if (t0 + u < T) {
+            const double* pk = stage + (c * 4 * CE + g * CE) * KR + j;
+#pragma unroll
+            for (int e = 0; e < CE; ++e)
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ring[u].v[e], pk[e * KR], acc,
+                                                         0, 0, 0);
+            if (++c == nch) {
+              const int row0 = block_row0(b) + g;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int o = (row0 + 4 * i) * KR + j;
+                const double pv = stage[o];
+                const double qv = acc[i] + lj * pv;
+                ql[o] = qv;
+                pq += pv * qv;
+              }
+              acc = (f64x4){0.0, 0.0, 0.0, 0.0};
+              c = 0;
+              ++b;
+            }
+          }
+          fetch(ring[u]);
+        }
+      }
+    }
+    red0[tid] = pq;
+    __syncthreads();
+    if (tid < KR) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) s += red0[t * 16 + tid];
+      co_store(myscal + KR + tid, s);
+    }
+    if (!group_sync(bar_cg, Tc, epoch, err, &sh.flag, spin)) return -1;
+    double spq = 0.0;
+    for (int m = 0; m < Tc; ++m) spq += co_load(scal + (int64_t)m * kNScal + KR + j);
+    double al = 0.0;
+    if (act) {
+      al = rr / spq;
+      if (!(spq > 0.0) || !isfinite(al)) {
+        al = 0.0;
+        act = false;  // breakdown in this column: keep the current step
+      }
+    }
+    double rrp = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if ((v >> 2) < nbw) {
+        const int row = row_of(v);
+        const int o = row * KR + j;
+        if (act) {
+          z[v] += al * stage[o];
+          r[v] -= al * ql[o];
+        }
+        if (row < d) co_store(R + o, r[v]);
+      }
+      rrp += r[v] * r[v];
+    }
+    red1[tid] = rrp;
+    __syncthreads();
+    if (tid < KR) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) s += red1[t * 16 + tid];
+      co_store(myscal + tid, s);
+    }
+    if (!group_sync(bar_cg, Tc, epoch, err, &sh.flag, spin)) return -1;
+    double rn = 0.0;
+    for (int m = 0; m < Tc; ++m) rn += co_load(scal + (int64_t)m * kNScal + j);
+    ++k;
+    if (act) {
+      bc = rn / rr;
+      rr = rn;
+      kin = k;
+      if (rn <= eps_sub * eps_sub * rr0) act = false;
+    }
+    if (tid < KR) sh.active[tid] = act ? 1 : 0;
+    __syncthreads();
+  }
+  if (tid < KR) sh.kin[tid] = kin;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int row = row_of(v);
+    if ((v >> 2) < nbw && row < d) co_store(Z + row * KR + j, z[v]);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // the ring's look-ahead loads too
+  if (!group_sync(bar_cg, Tc, epoch, err, &sh.flag, spin)) return -1;
+  return k;
+}
+
 // Lane l's value of v in every lane (l a compile-time constant after
 // unrolling: two v_readlane into scalar registers, no LDS round trip).
 __device__ __forceinline__ double lane_value(double v, int l) {
@@ -1063,6 +1257,8 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
   // a one-workgroup CG keeps p and q in LDS (2 x DP x 16 doubles within the
   // tile region)
   const bool local_cg = Tc == 1 && 2 * (size_t)DP * KR * sizeof(double) <= kUredOffset;
+  // a larger sub-team runs the same form, each member on its share of the rows
+  const bool team_cg = Tc > 1 && 2 * (size_t)DP * KR * sizeof(double) <= kUredOffset;
   // CG members own 16-aligned column ranges of R, Z, Q, XP and X
   const int cpw = ((d + Tc - 1) / Tc + 15) / 16 * 16;
   const int c_lo = cg ? min(d, rank * cpw) : d;
@@ -1170,6 +1366,13 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
                                                 a.max_inner)
                     : cg_solve_local<double, DP>((const double*)e.H, e.ldh, d, R, Z, a.eps_sub,
                                                  a.max_inner);
+      else if (team_cg)
+        k = a.h_f32 ? cg_solve_team<float, DP>((const float*)e.H, e.ldh, d, rank, Tc, R, Z, scal,
+                                               myscal, e.bar_cg, ep_cg, a.err, a.spin, a.eps_sub,
+                                               a.max_inner)
+                    : cg_solve_team<double, DP>((const double*)e.H, e.ldh, d, rank, Tc, R, Z,
+                                                scal, myscal, e.bar_cg, ep_cg, a.err, a.spin,
+                                                a.eps_sub, a.max_inner);
       else
         k = a.h_f32 ? cg_solve<float, DP>((const float*)e.H, e.ldh, d, c_lo, c_hi, R, Z, Q, scal,
                                           myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin, a.eps_sub,
@@ -1178,7 +1381,7 @@ __device__ void run_entry(const BatchArgs& a, const BatchEntry& e, int rank, voi
                                            scal, myscal, Tc, e.bar_cg, ep_cg, a.err, a.spin,
                                            a.eps_sub, a.max_inner);
       alive = k >= 0;
-      if (alive && Tc > 1 && !exact) ep_cg += 2u * (unsigned)k;
+      if (alive && Tc > 1 && !exact) ep_cg += 2u * (unsigned)k + (team_cg ? 1u : 0u);
       if (!alive) break;
       if (threadIdx.x < KR) {
         const int j = threadIdx.x;

@@ -19,7 +19,8 @@
 namespace mihs {
 
 bool block_tuning_valid(const mihs_batched_tuning_t& t) {
-  return (t.cg_cols == 16 || t.cg_cols == 32 || t.cg_cols == 64 || t.cg_cols == 512) &&
+  return (t.cg_cols == 16 || t.cg_cols == 32 || t.cg_cols == 64 || t.cg_cols == 128 ||
+          t.cg_cols == 512) &&
          (t.a_dma == 0 || t.a_dma == 1) && t.inner_weight >= 1.0 && t.inner_weight <= 1e4 &&
          (t.measured == 0 || t.measured == 1) && (t.exact == 0 || t.exact == 1);
 }

@@ -122,8 +122,10 @@ def test_graph_replays_match_the_eager_run(problem_set, cg_cols, exact):
 def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
     """mihs_tune_batched with exact sub-solves allowed times ten candidate
     shapes by coordinate descent, full runs of the best inexact and the best
-    exact shape, and a schedule sized from the faster one's per-problem costs,
-    and keeps the best for this problem set: the plain batched call afterwards
+    exact shape, and a schedule sized from the faster one's per-problem costs
+    (an inexact one also with 64 columns per CG member), then up to three
+    times more from the costs measured under the best of those while that
+    gains, and keeps the best for this problem set: the plain batched call afterwards
     (which looks the shape up) still reaches the closed form, and so does a plan
     that asks for the measured schedule explicitly."""
     mihs = _mihs()
@@ -133,9 +135,9 @@ def test_autotuner_picks_a_candidate_and_the_handle_keeps_it(problem_set):
     announce("batched autotuner")
     res = s.tune(trial_outer=3, allow_exact=True)
     best = res["best"]
-    assert len(res["trial_ms"]) == 13
+    assert 13 <= len(res["trial_ms"]) <= 16
     assert all(t > 0 for t in res["trial_ms"])
-    assert best["cg_cols"] in (16, 32, 64, 512) and best["a_dma"] in (0, 1)
+    assert best["cg_cols"] in (16, 32, 64, 128, 512) and best["a_dma"] in (0, 1)
     assert best["inner_weight"] in (6.25, 25.0, 100.0, 400.0)
     assert best["measured"] in (0, 1) and best["exact"] in (0, 1)
     s.run()
@@ -193,8 +195,11 @@ def test_measured_schedule_with_more_entries_than_workgroups():
     announce("batched 300 problems: tuner with measured schedule")
     res = s.tune(trial_outer=3)
     # inexact shapes only (the default): eight short trials, one full run of
-    # the best, one run of the measured schedule; exact sub-solves never chosen
-    assert len(res["trial_ms"]) == 10
+    # the best, runs of the measured schedule (with the best shape's CG width,
+    # with 64 columns per CG member unless that is the same, and up to three
+    # times re-sized from the costs measured under the best); exact sub-solves
+    # never chosen
+    assert 10 <= len(res["trial_ms"]) <= 14
     assert res["best"]["exact"] == 0
     g = s.capture()
     s.X_all.fill_(float("nan"))

@@ -410,8 +410,8 @@ __device__ __forceinline__ void rowdots(const TH* __restrict__ H, int64_t ldh, i
 // one counter's arrivals queue up (128 workgroups: 2.1 us either way; 256:
 // 3.8 us flat against 2.2 us two-level).
 __device__ __forceinline__ bool cg_sync(const SolveArgs& a, unsigned& epoch, int* s_flag) {
-  return a.cg_hier ? barrier_hier_co(a.bar_cgh, epoch, a.Gc, a.err, s_flag, a.spin_fast)
-                   : barrier_flat_co(a.bar_cg, epoch, a.Gc, a.err, s_flag, a.spin_fast);
+  return a.cg_hier ? barrier_hier(a.bar_cgh, epoch, a.Gc, a.err, s_flag, a.spin_fast)
+                   : barrier_flat(a.bar_cg, epoch, a.Gc, a.err, s_flag, a.spin_fast);
 }
 
 // GRAM: the inner CG applies (SA)^T SA through the precomputed H (owners form
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
       rowpass<TA, double, EPT, true, RA>(A, a.lda, a_r0, a_r1, d, vbuf, a.b, acc, ssq);
       wg_store_partial<TA, double, EPT>(acc, rbuf, a.partA + (int64_t)w * a.dpad, d);
     }
-    if (!(alive = barrier_hier_co(a.bar_all, ep_all, G, a.err, &s_flag, a.spin_fast))) break;
+    if (!(alive = barrier_hier(a.bar_all, ep_all, G, a.err, &s_flag, a.spin_fast))) break;
 
     int decision = 0;  // 0 continue, 1 converged, 2 breakdown
     if (in_cg) {
@@ -869,7 +869,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
         if (w == 0) co_store(a.status, decision);
       }
     }
-    if (!(alive = barrier_hier_co(a.bar_all, ep_all, G, a.err, &s_flag,
+    if (!(alive = barrier_hier(a.bar_all, ep_all, G, a.err, &s_flag,
                                in_cg ? a.spin_fast : a.spin_idle)))
       break;
     decision = __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

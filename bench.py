@@ -45,6 +45,11 @@ def parse():
                     help="relative-step stop tolerance (default: per workload, chosen so "
                          "that the result is within 1e-10 of x*)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="batched workload: skip the after-timing check of all 4096 results "
+                         "against QR closed forms (for profiler runs: its ~2 million library "
+                         "launches end them before they write their output); the line then "
+                         "says the results were not checked")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2^20 x 4096 CountSketch workload of the default line")
     ap.add_argument("--large-steps", type=int, default=1)
@@ -351,16 +356,20 @@ def run_batched(args):
     res["plain"] = configuration("plain FP64, inner CG", "plain", False, short, 1)
     res["exact"] = configuration("mixed, exact sub-solves", "mixed", True, short, 1)
 
-    log("checking all 4096 results of every configuration against QR closed forms")
     worst = {k: 0.0 for k in res}
-    for i, ((A, b), s) in enumerate(zip(probs, specs)):
+    if args.no_check:
+        log("results not checked (--no-check)")
+    else:
+        log("checking all 4096 results of every configuration against QR closed forms")
+    for i, ((A, b), s) in enumerate(zip(probs, specs) if not args.no_check else []):
         ref = ridge_path_qr(A, b, s.lambdas)
         nrm = np.linalg.norm(ref, axis=0)
         for k, r in res.items():
             X = r["xs"][i].cpu().numpy()
             e = float(np.max(np.linalg.norm(X - ref, axis=0) / nrm))
             worst[k] = max(worst[k], e)
-    log(f"  worst relative errors {worst}")
+    if not args.no_check:
+        log(f"  worst relative errors {worst}")
     mx = res["mixed"]
     apass = sum(s.n * s.d * 8 for s in specs)
     # per-problem outer counts: every entry passes over its A once per outer
@@ -388,8 +397,8 @@ def run_batched(args):
         "plain_fp64_ms": round(res["plain"]["ms"], 3),
         "mixed_speedup_vs_plain": round(res["plain"]["ms"] / value, 3),
         "exact_subsolves": clean(res["exact"]),
-        "max_rel_err_all_4096": worst,
-        "accuracy_ok": all(v <= 1e-10 for v in worst.values()),
+        "max_rel_err_all_4096": None if args.no_check else worst,
+        "accuracy_ok": None if args.no_check else all(v <= 1e-10 for v in worst.values()),
         "slowest_entries": [{"problem": int(i), "n": specs[i].n, "d": specs[i].d,
                              "ms": round(float(mx["elapsed_ms"][i]), 2),
                              "outer_max": int(mx["outer"][i].max())} for i in slow],

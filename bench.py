@@ -66,12 +66,15 @@ def parse():
 # runs (FETCH_SIZE, then WRITE_SIZE, each scaled by what the counter reads for a
 # plain 1 GiB device copy: x1.99992 for FETCH_SIZE, x1.000 for WRITE_SIZE); see
 # profiles/solve_kernel_srht_2p18x2048.md.  Valid for the kernel as profiled.
-MEASURED_TRAFFIC = {("srht_2p18x2048", "mixed"): 155456514665}
+MEASURED_TRAFFIC = {}
 
 # Stop-rule tolerance per workload: the relative-step rule estimates the error
 # from the Corollary 4 rate sqrt(beta); where the observed rate is slower (the
-# two-stage sketch of the ill-conditioned FP32 workload) the tolerance is tighter.
-DEFAULT_TOL = {"count_2p20x4096": 2e-12, "batched_lambda_path": 3e-12}
+# two-stage sketch of the ill-conditioned FP32 workload, the batched paths) the
+# tolerance is tighter.  The headline stops at the metric's own 1e-10, the rule
+# its CPU baseline (the oracle) uses too; every workload's final error is
+# checked against 1e-10 after timing.
+DEFAULT_TOL = {"count_2p20x4096": 2e-12, "batched_lambda_path": 3e-12, "srht_2p18x2048": 1e-10}
 
 
 def log(msg):

@@ -847,6 +847,7 @@ def run_ridge(args, wname, steps, warmup, full=True):
                      "algorithmic_bytes_per_launch": solve_bytes,
                      "kernel_ms": round(kernel_ms, 3),
                      "launch_overhead_ms": round(mx["overhead_ms"], 3)},
+        "row_weights": list(mihs.row_weights()),
         "accuracy_ok": max(mx["errs"]) <= 1e-10 and max(pl["errs"]) <= 1e-10,
     }
     if full and not args.no_cpu_baseline:
@@ -864,7 +865,8 @@ def run_ridge(args, wname, steps, warmup, full=True):
 def ridge_summary(r):
     """The keys of a ridge result that another workload's line carries."""
     keep = ("value", "unit", "ms_per_step", "steps", "warmup", "config", "plain_fp64_ms",
-            "mixed_speedup_vs_plain", "mixed", "plain", "roofline", "accuracy_ok")
+            "mixed_speedup_vs_plain", "mixed", "plain", "roofline", "row_weights",
+            "accuracy_ok")
     return {k: r[k] for k in keep if k in r}
 
 

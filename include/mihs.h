@@ -104,6 +104,45 @@ typedef struct {
 int mihs_create(mihs_handle_t* handle, int device);
 int mihs_destroy(mihs_handle_t handle);
 
+/* ------------------------------------------------------------------------
+ * Row shares of the gradient pass (Algorithm 1: g = A^T (b - A x) - lambda x,
+ * one pass over A per outer iteration).
+ *
+ * The calls that run the persistent solve kernel (mihs_solve,
+ * mihs_solve_noalloc, mihs_solve_inner, mihs_solve_dual, mihs_solve_pd,
+ * mihs_solve_pd_dual, mihs_estimate_sd, the per-column solves of
+ * mihs_solve_backward) split the rows of A over their workgroups, which the device dispatches to its 8 XCDs in turn
+ * (workgroup v on XCD v mod 8).  Workgroup v of G takes rows in proportion to
+ * the weight w[v mod 8] of its XCD: rows [bound(v), bound(v + 1)) with
+ * bound(v) = floor(n P(v) / P(G)), P(v) = sum of w[u mod 8] over u < v.  Equal
+ * weights give the even split floor(n v / G).  XCDs need not stream from HBM
+ * at the same rate; with equal shares the pass lasts as long as the slowest.
+ * The weights belong to the handle (equal after mihs_create): every solve on
+ * the handle uses them, so results repeat bit for bit on one handle; other
+ * weights change the grouping of the partial sums, hence the rounding.
+ *
+ * mihs_calibrate_rows   times the gradient pass's row loop on every XCD, with
+ *   one workgroup per CU and equal shares of a 2 GiB zero matrix (2048 FP64
+ *   columns) that the call allocates and frees (2 warm-up and 12 timed
+ *   passes, ~6 ms; synchronous), then sets
+ *   w_k = 4 round(16 (t_min / t_k)^(3/4)) clamped to [32, 64] (t_k: the XCD's
+ *   mean time; the power damps the correction, since slow XCDs speed up once
+ *   fast ones finish; steps of 4 keep the 1-2% drift of the means between
+ *   calibrations from moving the split).  weights (8 entries, may be NULL) receives the result.
+ *   MIHS_ERR_HIP (weights unchanged) when the buffer cannot be allocated or a
+ *   HIP call fails.  The Python binding calls it once per handle.
+ * mihs_set_row_weights  sets the 8 weights, each in [1, 64]; NULL restores
+ *   equal weights.  MIHS_ERR_INVALID for a weight out of range.
+ * mihs_get_row_weights  copies the handle's 8 weights to weights.
+ * mihs_row_split        host only: bounds[0..G] of the split above for n rows
+ *   over G workgroups (bounds[0] = 0, bounds[G] = n); MIHS_ERR_INVALID for
+ *   n < 0, G < 1 or a weight out of [1, 64].
+ * ------------------------------------------------------------------------ */
+int mihs_calibrate_rows(mihs_handle_t handle, int32_t* weights);
+int mihs_set_row_weights(mihs_handle_t handle, const int32_t* weights);
+int mihs_get_row_weights(mihs_handle_t handle, int32_t* weights);
+int mihs_row_split(int64_t n, int32_t G, const int32_t* weights, int64_t* bounds);
+
 /* Human-readable text for a return code or an info status. */
 const char* mihs_status_string(int code);
 

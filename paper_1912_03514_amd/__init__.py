@@ -16,5 +16,5 @@ from ._binding import (  # noqa: F401
     mihs_solve_backward, mihs_solve_batched, mihs_solve_dual, mihs_solve_multi, mihs_solve_pd,
     mihs_solve_pd_dual, mihs_transpose, MIHSRidge, momentum, momentum_thm1, lambda_from_log,
     release_all, mihs_solve_noalloc, NOALLOC_SCRATCH_BYTES, tuning_cache_save,
-    tuning_cache_load,
+    tuning_cache_load, row_weights, set_row_weights, calibrate_rows, row_split,
 )

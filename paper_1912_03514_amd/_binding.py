@@ -11,7 +11,7 @@ import ctypes
 import os
 import threading
 import weakref
-from typing import Dict, Optional, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import torch
 
@@ -77,6 +77,11 @@ _SIGS = {
     "mihs_lambda_from_log": (_int, [_dbl, ctypes.POINTER(_dbl)]),
     "mihs_create": (_int, [ctypes.POINTER(_vp), _int]),
     "mihs_destroy": (_int, [_vp]),
+    "mihs_calibrate_rows": (_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    "mihs_set_row_weights": (_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    "mihs_get_row_weights": (_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    "mihs_row_split": (_int, [_i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(_i64)]),
     "mihs_status_string": (ctypes.c_char_p, [_int]),
     "mihs_sketch_workspace_size": (_int, [_vp, _i64, _i64, _i64, _i64, _int, _int, _int,
                                           ctypes.POINTER(_sz)]),
@@ -198,10 +203,48 @@ def handle(device: Optional[int] = None) -> int:
         lib = load_library()
         hp = _vp()
         _check(lib.mihs_create(ctypes.byref(hp), dev), "mihs_create")
+        # per-XCD row shares of the gradient pass, measured once per handle;
+        # when the measurement cannot run the handle keeps equal shares
+        lib.mihs_calibrate_rows(hp.value, None)
         with _lock:
             _handles[dev] = hp.value
         h = hp.value
     return h
+
+
+_W8 = ctypes.c_int32 * 8
+
+
+def row_weights(device: Optional[int] = None) -> Tuple[int, ...]:
+    """The handle's 8 per-XCD row weights of the gradient pass
+    (mihs_get_row_weights)."""
+    w = _W8()
+    _check(load_library().mihs_get_row_weights(handle(device), w), "mihs_get_row_weights")
+    return tuple(w)
+
+
+def set_row_weights(weights: Optional[Sequence[int]], device: Optional[int] = None) -> None:
+    """Set the 8 per-XCD row weights (each 1..64); None restores equal weights
+    (mihs_set_row_weights)."""
+    w = None if weights is None else _W8(*[int(v) for v in weights])
+    _check(load_library().mihs_set_row_weights(handle(device), w), "mihs_set_row_weights")
+
+
+def calibrate_rows(device: Optional[int] = None) -> Tuple[int, ...]:
+    """Measure the per-XCD streaming rates again and set the weights from them
+    (mihs_calibrate_rows); returns the new weights."""
+    w = _W8()
+    _check(load_library().mihs_calibrate_rows(handle(device), w), "mihs_calibrate_rows")
+    return tuple(w)
+
+
+def row_split(n: int, G: int, weights: Sequence[int]) -> List[int]:
+    """First row of each of G workgroups (and n at the end) for these weights
+    (mihs_row_split, host only)."""
+    out = (_i64 * (int(G) + 1))()
+    _check(load_library().mihs_row_split(int(n), int(G), _W8(*[int(v) for v in weights]), out),
+           "mihs_row_split")
+    return list(out)
 
 
 def _stream(device) -> int:

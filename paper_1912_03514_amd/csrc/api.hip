@@ -48,6 +48,7 @@ int mihs_create(mihs_handle_t* handle, int device) {
   h->num_cu = prop.multiProcessorCount;
   h->wall_khz = wall_khz;
   strncpy(h->arch, prop.gcnArchName, sizeof(h->arch) - 1);
+  for (int k = 0; k < mihs::kXcds; ++k) h->row_weight[k] = mihs::kRowWeightMax;
   // this device's address of the static scratch of mihs_solve_noalloc, taken
   // once here with the device current (the caller's current device is kept)
   int prev = 0;
@@ -62,6 +63,14 @@ int mihs_create(mihs_handle_t* handle, int device) {
   }
   *handle = h;
   return MIHS_OK;
+}
+
+int mihs_calibrate_rows(mihs_handle_t handle, int32_t* weights) {
+  if (!handle) return MIHS_ERR_INVALID;
+  const int rc = mihs::calibrate_rows(handle);
+  if (rc == MIHS_OK && weights)
+    for (int k = 0; k < mihs::kXcds; ++k) weights[k] = handle->row_weight[k];
+  return rc;
 }
 
 int mihs_destroy(mihs_handle_t handle) {

@@ -501,6 +501,30 @@ extern "C" int mihs_tuning_cache_load(mihs_handle_t handle, const char* path, in
 
 extern "C" {
 
+int mihs_set_row_weights(mihs_handle_t handle, const int32_t* weights) {
+  if (!handle) return MIHS_ERR_INVALID;
+  if (weights)
+    for (int k = 0; k < mihs::kXcds; ++k)
+      if (weights[k] < 1 || weights[k] > mihs::kRowWeightMax) return MIHS_ERR_INVALID;
+  for (int k = 0; k < mihs::kXcds; ++k)
+    handle->row_weight[k] = weights ? weights[k] : mihs::kRowWeightMax;
+  return MIHS_OK;
+}
+
+int mihs_get_row_weights(mihs_handle_t handle, int32_t* weights) {
+  if (!handle || !weights) return MIHS_ERR_INVALID;
+  for (int k = 0; k < mihs::kXcds; ++k) weights[k] = handle->row_weight[k];
+  return MIHS_OK;
+}
+
+int mihs_row_split(int64_t n, int32_t G, const int32_t* weights, int64_t* bounds) {
+  if (n < 0 || G < 1 || !weights || !bounds) return MIHS_ERR_INVALID;
+  for (int k = 0; k < mihs::kXcds; ++k)
+    if (weights[k] < 1 || weights[k] > mihs::kRowWeightMax) return MIHS_ERR_INVALID;
+  for (int v = 0; v <= G; ++v) bounds[v] = mihs::row_split_bound(n, G, weights, v);
+  return MIHS_OK;
+}
+
 int mihs_momentum_cor4(double sd, int64_t m, double* alpha, double* beta) {
   if (!alpha || !beta || !isfinite(sd) || m < 1) return MIHS_ERR_INVALID;
   const double b = sd / (double)m;

@@ -24,6 +24,7 @@ struct mihs_handle {
   int num_cu;
   int wall_khz;  // rate of the device's constant wall clock
   char arch[64];
+  int32_t row_weight[8];  // gradient-pass row shares per XCD (mihs_set_row_weights)
   void* noalloc_scratch;  // this device's address of the library's static scratch
   std::mutex tune_mu;
   std::vector<mihs_tuned_set> tuned;
@@ -38,6 +39,33 @@ constexpr size_t kNoAllocScratchBytes = (size_t)MIHS_NOALLOC_SCRATCH_BYTES;
 // This device's address of that scratch (hipGetSymbolAddress; the handle's
 // device must be current).
 int noalloc_scratch_address(void** ptr);
+
+#if defined(__HIPCC__)
+#define MIHS_HOST_DEVICE __host__ __device__
+#else
+#define MIHS_HOST_DEVICE
+#endif
+
+// Rows of the solve kernel's gradient pass: workgroups are dispatched to the
+// XCDs in turn (workgroup v on XCD v mod 8), and workgroup v takes rows in
+// proportion to its XCD's weight w[v mod 8] (1..kRowWeightMax).  Returns the
+// first row of workgroup v of G (v = G gives n).  Equal weights give
+// floor(n v / G), the even split.
+constexpr int kXcds = 8;
+constexpr int32_t kRowWeightMax = 64;
+MIHS_HOST_DEVICE inline int64_t row_split_bound(int64_t n, int G, const int32_t* w, int v) {
+  if (v >= G) return n;
+  int64_t sum = 0;
+  for (int k = 0; k < kXcds; ++k) sum += w[k];
+  int64_t pre = (int64_t)(v / kXcds) * sum, tot = (int64_t)(G / kXcds) * sum;
+  for (int k = 0; k < v % kXcds; ++k) pre += w[k];
+  for (int k = 0; k < G % kXcds; ++k) tot += w[k];
+  return n * pre / tot;
+}
+
+// Measures each XCD's streaming time and sets h->row_weight from it
+// (mihs_calibrate_rows).
+int calibrate_rows(mihs_handle* h);
 
 // Padded vector length used by the row kernels: 64 lanes x elements-per-lane.
 int ept_for(int64_t d);

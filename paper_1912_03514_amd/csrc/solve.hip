@@ -27,6 +27,8 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <algorithm>
+
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -74,6 +76,7 @@ struct SolveArgs {
   const int* skip;    // when set and nonzero the launch returns at once
   int d, dpad, G, Gc, cpw;
   int cg_hier;        // inner-solve group large enough for the two-level barrier
+  int32_t xw[kXcds];  // gradient-pass row weight of each XCD (row_split_bound)
   BarrierSpin spin_fast, spin_idle;
 };
 
@@ -480,7 +483,8 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
     cg1 = tr <= kCg1MaxCond * a.lam;
   }
 
-  const int64_t a_r0 = a.n * w / G, a_r1 = a.n * (w + 1) / G;
+  const int64_t a_r0 = row_split_bound(a.n, G, a.xw, w);
+  const int64_t a_r1 = row_split_bound(a.n, G, a.xw, w + 1);
   const int64_t s_r0 = in_cg ? a.m * w / Gc : 0;
   const int64_t s_r1 = in_cg ? a.m * (w + 1) / Gc : 0;
 
@@ -1244,6 +1248,7 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   a.bar_cg = bar + 9 * 32;
   a.bar_cgh = bar + 12 * 32;
   a.cg_hier = Gc > 128 ? 1 : 0;
+  for (int k = 0; k < kXcds; ++k) a.xw[k] = h->row_weight[k];
   a.err = (int*)(bar + 10 * 32);
   a.status = (int*)(bar + 11 * 32);
   a.d = (int)s.d;
@@ -1278,6 +1283,113 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
   if (hipLaunchCooperativeKernel((const void*)kern, dim3(G), dim3(kBlock), args, shmem, stream) !=
       hipSuccess)
     return MIHS_ERR_HIP;
+  return MIHS_OK;
+}
+
+// ---- per-XCD row weights of the gradient pass --------------------------------
+// The gradient pass streams A once per outer iteration in contiguous row ranges,
+// one workgroup per CU; its length is that of the slowest workgroup.  XCDs do
+// not all stream from HBM at the same rate: on MI355X, with equal shares of an
+// FP64 matrix of 2048 columns, the odd-numbered XCDs took 6-8% longer than the
+// even ones, on every pass (a plain 16-byte stream shows about half of that, so
+// the measurement below runs the gradient pass's own row loop).  The rows are
+// shared out by per-XCD weights measured here.
+
+constexpr int kCalCols = 2048;                      // FP64 columns of the timing matrix
+constexpr int64_t kCalRows = (int64_t)1 << 17;      // 2 GiB (> the Infinity Cache)
+constexpr int kCalWarm = 2;                         // untimed passes
+constexpr int kCalPasses = 12;                      // timed passes
+constexpr long kRowWeightStep = 4;                  // weights are multiples of this
+constexpr size_t kCalLds = 96 * 1024;               // keeps one workgroup per CU
+
+// One workgroup per CU runs the gradient pass's row loop (x = 0) over its equal
+// share of the rows and records its start and end wall clock (clk[2w],
+// clk[2w + 1]).
+__global__ __launch_bounds__(kBlock) void xcd_rowpass_kernel(const double* __restrict__ M,
+                                                             long long* clk, double* sink) {
+  extern __shared__ double v[];  // kCalCols zeros, then padding
+  for (int c = threadIdx.x; c < kCalCols; c += kBlock) v[c] = 0.0;
+  __syncthreads();
+  const int G = gridDim.x, w = blockIdx.x;
+  const long long t0 = wall_clock64();
+  constexpr int EPT = kCalCols / kWave;
+  double acc[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) acc[e] = 0.0;
+  double ssq = 0.0;
+  rowpass<double, double, EPT, true, RowsInFlight<double, EPT>::value>(
+      M, kCalCols, kCalRows * w / G, kCalRows * (w + 1) / G, kCalCols, v, nullptr, acc, ssq);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    clk[2 * w] = t0;
+    clk[2 * w + 1] = wall_clock64();
+  }
+  // keeps the arithmetic (never true: the matrix is zero)
+  double t = ssq;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) t += acc[e];
+  if (t == 1.25e300) sink[w] = t;
+}
+
+int calibrate_rows(mihs_handle* h) {
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(h->device) != hipSuccess)
+    return MIHS_ERR_HIP;
+  const int G = h->num_cu;
+  char* buf = nullptr;
+  const size_t bytes = (size_t)kCalRows * kCalCols * sizeof(double);
+  const size_t clk_off = bytes, sink_off = bytes + (size_t)G * 16;
+  int rc = MIHS_OK;
+  if (G < kXcds || hipMalloc(&buf, sink_off + (size_t)G * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipSetDevice(prev);
+    return MIHS_ERR_HIP;
+  }
+  std::vector<long long> clk((size_t)2 * G);
+  std::vector<double> tsum(kXcds, 0.0);
+  std::vector<int> cnt(kXcds, 0);
+  if (hipMemset(buf, 0, bytes) != hipSuccess ||
+      hipFuncSetAttribute((const void*)xcd_rowpass_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCalLds) != hipSuccess)
+    rc = MIHS_ERR_HIP;
+  for (int pass = 0; pass < kCalWarm + kCalPasses && rc == MIHS_OK; ++pass) {
+    hipLaunchKernelGGL(xcd_rowpass_kernel, dim3(G), dim3(kBlock), kCalLds, 0, (const double*)buf,
+                       (long long*)(buf + clk_off), (double*)(buf + sink_off));
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpy(clk.data(), buf + clk_off, clk.size() * sizeof(long long),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+      rc = MIHS_ERR_HIP;
+      break;
+    }
+    if (pass < kCalWarm) continue;
+    for (int w = 0; w < G; ++w) {
+      tsum[w % kXcds] += (double)(clk[2 * w + 1] - clk[2 * w]);
+      cnt[w % kXcds] += 1;
+    }
+  }
+  (void)hipFree(buf);
+  (void)hipSetDevice(prev);
+  if (rc != MIHS_OK) return rc;
+  // Weight (t_min / t)^(3/4) of the fastest XCD's kRowWeightMax, at most a 2:1
+  // spread, in steps of kRowWeightStep.  With equal shares the slow XCDs also
+  // stream faster once the fast ones are done, so the time ratio overstates the
+  // rate ratio under a balanced load: on the headline solve (odd XCDs 7-9%
+  // slower at equal shares) weights 64/60 by XCD parity gave 25.10-25.26 ms
+  // per solve, 64/56 25.47 ms, equal weights 25.56-25.67 ms.  The steps keep
+  // the 1-2% drift of the means between calibrations from moving the split
+  // (64/60 with one even XCD at 63 measured 25.36 ms).
+  double tmin = 0.0;
+  for (int k = 0; k < kXcds; ++k) {
+    const double t = tsum[k] / (double)cnt[k];
+    if (!(t > 0.0)) return MIHS_ERR_HIP;
+    if (k == 0 || t < tmin) tmin = t;
+  }
+  for (int k = 0; k < kXcds; ++k) {
+    const double t = tsum[k] / (double)cnt[k];
+    const long wk =
+        kRowWeightStep * lround((double)(kRowWeightMax / kRowWeightStep) * pow(tmin / t, 0.75));
+    h->row_weight[k] = (int32_t)std::min<long>(kRowWeightMax, std::max<long>(kRowWeightMax / 2, wk));
+  }
   return MIHS_OK;
 }
 

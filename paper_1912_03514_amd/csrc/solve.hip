@@ -690,9 +690,12 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 nu_p += (double)wc * (double)rc;
               }
               block_sum2(mu_p, nu_p, s_red);
+              // the step's scalar slots alternate like w: one barrier separates
+              // a step's reads of a slot pair from its next write (two steps on)
+              const int sp = 2 + 4 * wb;
               if (threadIdx.x == 0) {
-                co_store(scal_w + 2, mu_p);
-                co_store(scal_w + 3, nu_p);
+                co_store(scal_w + sp, mu_p);
+                co_store(scal_w + sp + 1, nu_p);
               }
               if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
               // fetch w (written by every CG workgroup before the barrier) while
@@ -704,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
                 wpre[i] = (c < d) ? co_load(P[wb] + c) : TV(0);
               }
               double mu_n, nu_n;
-              sum2_slots(a.scal, Gc, 2, 3, s_red, mu_n, nu_n);
+              sum2_slots(a.scal, Gc, sp, sp + 1, s_red, mu_n, nu_n);
               if (mu_n <= stop || k >= a.max_inner) break;
               const double bt = mu_n / mu;
               const double den = nu_n - bt * mu_n / alpha;

@@ -493,10 +493,12 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
   int status = MIHS_MAX_ITER;
   bool alive = true;
 
+  // x in LDS for the first gradient pass; later passes get it at the end of
+  // the previous iteration, fetched together with the stop test's sums
+  for (int c = threadIdx.x; c < a.dpad; c += kBlock) vbuf[c] = (c < d) ? co_load(a.x + c) : 0.0;
+  __syncthreads();
   while (outer < a.max_outer) {
     // ---- A1 (all): partial A^T (b - A x) over this workgroup's rows
-    for (int c = threadIdx.x; c < a.dpad; c += kBlock) vbuf[c] = (c < d) ? co_load(a.x + c) : 0.0;
-    __syncthreads();
     if constexpr (EPT == 64) {
       double acc[16];
 #pragma unroll
@@ -531,6 +533,16 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
       if (threadIdx.x == 0) co_store(scal_w + 0, rr_part);
       if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
 
+      // the single-reduction CG starts from the whole of r = g: its loads are
+      // issued before the slot sum
+      TV rpre[NPT];
+      if (GRAM && cg1) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+          const int c = threadIdx.x + i * kBlock;
+          rpre[i] = (c < d) ? co_load(r + c) : TV(0);
+        }
+      }
       double rr0, unused;
       sum2_slots(a.scal, Gc, 0, 0, s_red, rr0, unused);
       last_gnorm = sqrt(rr0);
@@ -644,7 +656,11 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           TV* rv = (TV*)vbuf;
           TV* sv = (TV*)rbuf;
           const TV lt = (TV)a.lam;
-          for (int c = threadIdx.x; c < a.dpad; c += kBlock) rv[c] = (c < d) ? co_load(r + c) : TV(0);
+#pragma unroll
+          for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + i * kBlock;
+            if (c < a.dpad) rv[c] = rpre[i];
+          }
           __syncthreads();
           int wb = 0;
           double mu = rr0, alpha = 0.0, unused2;
@@ -661,6 +677,11 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
             nu_part = block_sum(nu_part, s_red);
             if (threadIdx.x == 0) co_store(scal_w + 1, nu_part);
             if (!(alive = cg_sync(a, ep_cg, &s_flag))) break;
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+              const int c = threadIdx.x + i * kBlock;
+              rpre[i] = (c < d) ? co_load(P[wb] + c) : TV(0);  // w, for s below
+            }
             double nu;
             sum2_slots(a.scal, Gc, 1, 1, s_red, nu, unused2);
             alpha = mu / nu;
@@ -668,8 +689,11 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
           }
           if (decision == 0) {
             // s = w, p = r
-            for (int c = threadIdx.x; c < a.dpad; c += kBlock)
-              sv[c] = (c < d) ? co_load(P[wb] + c) : TV(0);
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+              const int c = threadIdx.x + i * kBlock;
+              if (c < a.dpad) sv[c] = rpre[i];
+            }
             for (int i = threadIdx.x; i < nown; i += kBlock) own_r[i] = rv[c_lo + i];
             __syncthreads();
             while (true) {
@@ -879,6 +903,14 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
     if (!(alive = barrier_hier(a.bar_all, ep_all, G, a.err, &s_flag,
                                in_cg ? a.spin_fast : a.spin_idle)))
       break;
+    // the updated x (owners stored it before the barrier), the decision and the
+    // step sums: all loads issued before any is used
+    double xpre[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int c = threadIdx.x + i * kBlock;
+      xpre[i] = (c < d) ? co_load(a.x + c) : 0.0;
+    }
     decision = __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (decision == 1) {
       status = MIHS_CONVERGED;
@@ -900,6 +932,12 @@ __global__ __launch_bounds__(kBlock) void solve_kernel(SolveArgs a) {
       status = MIHS_CONVERGED;
       break;
     }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int c = threadIdx.x + i * kBlock;
+      if (c < a.dpad) vbuf[c] = xpre[i];
+    }
+    __syncthreads();
   }
   if (!alive) status = MIHS_BARRIER_TIMEOUT;
   // publish the momentum state (the iterate before x) of the owned columns

@@ -123,10 +123,10 @@ int mihs_destroy(mihs_handle_t handle);
  *
  * mihs_calibrate_rows   times the gradient pass's row loop on every XCD, with
  *   one workgroup per CU and equal shares of a 2 GiB zero matrix (2048 FP64
- *   columns) that the call allocates and frees (2 warm-up and 12 timed
- *   passes, ~6 ms; synchronous), then sets
+ *   columns) that the call allocates and frees (6 warm-up and 15 timed
+ *   passes, ~8 ms; synchronous), then sets
  *   w_k = 4 round(16 (t_min / t_k)^(3/4)) clamped to [32, 64] (t_k: the XCD's
- *   mean time; the power damps the correction, since slow XCDs speed up once
+ *   median over the passes of its workgroups' mean time; the power damps the correction, since slow XCDs speed up once
  *   fast ones finish; steps of 4 keep the 1-2% drift of the means between
  *   calibrations from moving the split).  weights (8 entries, may be NULL) receives the result.
  *   MIHS_ERR_HIP (weights unchanged) when the buffer cannot be allocated or a

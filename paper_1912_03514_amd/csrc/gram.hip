@@ -1,6 +1,8 @@
 // Gram matrices H = M^T M of sketches (M = SA, m x d row-major) on the FP64
 // matrix cores.  The inner CG applies the sub-problem operator (SA)^T SA as
 // H p, one d x d product per step instead of two passes over SA.
+#include <type_traits>
+
 #include "device_util.hpp"
 #include "internal.hpp"
 
@@ -97,18 +99,19 @@ constexpr int kT = 128;       // tile edge
 constexpr int kKC = 16;       // rows of M per chunk
 constexpr int kLdt = kT + 4;  // LDS row stride (doubles)
 
-template <typename TS>
+template <typename TS, int W = 8>
 struct ChunkLoad {
-  // thread t: chunk row t / 16, columns c0 + 8 (t % 16) .. + 8 of one tile
-  static constexpr int kVec = 16 / (int)sizeof(TS);
-  static constexpr int kN = 8 / kVec;  // 16-byte loads per thread per tile
+  // thread t: chunk row t / 16, columns c0 + W (t % 16) .. + W of one tile
+  // (W = 8: a 128-column tile, W = 4: a 64-column tile)
+  static constexpr int kVec = 16 / (int)sizeof(TS) < W ? 16 / (int)sizeof(TS) : W;
+  static constexpr int kN = W / kVec;  // 16-byte (or 8-byte) loads per thread per tile
   typedef TS vec_t __attribute__((ext_vector_type(kVec)));
   static __device__ __forceinline__ void run(const TS* __restrict__ M, int64_t m, int64_t ld,
-                                             int d, int64_t r0, int c0, double (&out)[8]) {
+                                             int d, int64_t r0, int c0, double (&out)[W]) {
     const int t = threadIdx.x;
     const int64_t r = r0 + t / 16;
-    const int c = c0 + 8 * (t % 16);
-    if (r < m && c + 8 <= d) {
+    const int c = c0 + W * (t % 16);
+    if (r < m && c + W <= d) {
       const TS* p = M + r * ld + c;
 #pragma unroll
       for (int i = 0; i < kN; ++i) {
@@ -118,34 +121,41 @@ struct ChunkLoad {
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) out[e] = (r < m && c + e < d) ? (double)M[r * ld + c + e] : 0.0;
+      for (int e = 0; e < W; ++e) out[e] = (r < m && c + e < d) ? (double)M[r * ld + c + e] : 0.0;
     }
   }
 };
 
-template <typename TS, typename TH>
+// Tiles of 128 rows (i) by TN columns (j) of H.  TN = 128: the tiles on and
+// above the diagonal, each written with its mirror (a diagonal tile computes
+// both of its triangles).  TN = 64 (twice as many workgroups, for matrices
+// with fewer 128-tiles than CUs): every tile that holds an entry with i <= j,
+// and it writes those entries and their mirrors only.
+template <typename TS, typename TH, int TN>
 __global__ __launch_bounds__(kBlock) void gram_tile128_kernel(const TS* M, int64_t m, int64_t ld,
                                                               int d, TH* H, int64_t ldh, int hn) {
+  static_assert(TN == 128 || TN == 64, "tile width");
+  constexpr int NB = TN / 32;  // 16-column blocks per wave
+  constexpr int WJ = TN / 16;  // columns of the j tile loaded per thread
   const int bi = blockIdx.y, bj = blockIdx.x;
-  if (bi > bj) return;
+  if (TN == kT ? bi > bj : bi * kT > bj * TN + TN - 1) return;
   __shared__ double tl[2][2][kKC][kLdt];  // [buffer][i or j tile][row][col]
   const int lane = lane_id(), wave = wave_id();
   const int wr = wave >> 1, wc = wave & 1;
-  const int ci0 = bi * kT, cj0 = bj * kT;
-  f64x4 acc[4][4];
+  const int ci0 = bi * kT, cj0 = bj * TN;
+  f64x4 acc[4][NB];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  const int srow = threadIdx.x / 16, scol = 8 * (threadIdx.x % 16);
-  double gi[8], gj[8];
+    for (int b = 0; b < NB; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  const int srow = threadIdx.x / 16, scol = 8 * (threadIdx.x % 16), scolj = WJ * (threadIdx.x % 16);
+  double gi[8], gj[WJ];
   ChunkLoad<TS>::run(M, m, ld, d, 0, ci0, gi);
-  ChunkLoad<TS>::run(M, m, ld, d, 0, cj0, gj);
+  ChunkLoad<TS, WJ>::run(M, m, ld, d, 0, cj0, gj);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    tl[0][0][srow][scol + e] = gi[e];
-    tl[0][1][srow][scol + e] = gj[e];
-  }
+  for (int e = 0; e < 8; ++e) tl[0][0][srow][scol + e] = gi[e];
+#pragma unroll
+  for (int e = 0; e < WJ; ++e) tl[0][1][srow][scolj + e] = gj[e];
   __syncthreads();
   const int64_t nchunks = (m + kKC - 1) / kKC;
   for (int64_t ch = 0; ch < nchunks; ++ch) {
@@ -153,28 +163,27 @@ __global__ __launch_bounds__(kBlock) void gram_tile128_kernel(const TS* M, int64
     const bool more = ch + 1 < nchunks;
     if (more) {
       ChunkLoad<TS>::run(M, m, ld, d, (ch + 1) * kKC, ci0, gi);
-      ChunkLoad<TS>::run(M, m, ld, d, (ch + 1) * kKC, cj0, gj);
+      ChunkLoad<TS, WJ>::run(M, m, ld, d, (ch + 1) * kKC, cj0, gj);
     }
 #pragma unroll
     for (int ks = 0; ks < kKC / 4; ++ks) {
       const int r = 4 * ks + (lane >> 4);
-      double av[4], bv[4];
+      double av[4], bv[NB];
 #pragma unroll
       for (int a = 0; a < 4; ++a) av[a] = tl[cur][0][r][wr * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = tl[cur][1][r][wc * 64 + b * 16 + (lane & 15)];
+      for (int b = 0; b < NB; ++b) bv[b] = tl[cur][1][r][wc * (TN / 2) + b * 16 + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < NB; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     if (more) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        tl[cur ^ 1][0][srow][scol + e] = gi[e];
-        tl[cur ^ 1][1][srow][scol + e] = gj[e];
-      }
+      for (int e = 0; e < 8; ++e) tl[cur ^ 1][0][srow][scol + e] = gi[e];
+#pragma unroll
+      for (int e = 0; e < WJ; ++e) tl[cur ^ 1][1][srow][scolj + e] = gj[e];
     }
     __syncthreads();
   }
@@ -189,19 +198,24 @@ __global__ __launch_bounds__(kBlock) void gram_tile128_kernel(const TS* M, int64
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) asm volatile("" : "+a"(acc[a][b]));
+      for (int b = 0; b < NB; ++b) asm volatile("" : "+a"(acc[a][b]));
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < NB; ++b) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = ci0 + wr * 64 + a * 16 + (lane >> 4) + 4 * r;
-          const int j = cj0 + wc * 64 + b * 16 + (lane & 15);
+          const int j = cj0 + wc * (TN / 2) + b * 16 + (lane & 15);
           if (i < hn && j < hn) {
             const TH v = (TH)acc[a][b][r];
-            H[(int64_t)i * ldh + j] = v;
-            if (bi != bj) H[(int64_t)j * ldh + i] = v;
+            if (TN == kT) {
+              H[(int64_t)i * ldh + j] = v;
+              if (bi != bj) H[(int64_t)j * ldh + i] = v;
+            } else if (i <= j) {
+              H[(int64_t)i * ldh + j] = v;
+              H[(int64_t)j * ldh + i] = v;
+            }
           }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -210,14 +224,20 @@ __global__ __launch_bounds__(kBlock) void gram_tile128_kernel(const TS* M, int64
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = ci0 + wr * 64 + a * 16 + (lane >> 4) + 4 * r;
-          const int j = cj0 + wc * 64 + b * 16 + (lane & 15);
+          const int j = cj0 + wc * (TN / 2) + b * 16 + (lane & 15);
           if (i < hn && j < hn) {
-            H[(int64_t)i * ldh + j] = (TH)acc[a][b][r];
-            if (bi != bj) H[(int64_t)j * ldh + i] = (TH)acc[a][b][r];
+            const TH v = (TH)acc[a][b][r];
+            if (TN == kT) {
+              H[(int64_t)i * ldh + j] = v;
+              if (bi != bj) H[(int64_t)j * ldh + i] = v;
+            } else if (i <= j) {
+              H[(int64_t)i * ldh + j] = v;
+              H[(int64_t)j * ldh + i] = v;
+            }
           }
         }
   }
@@ -240,21 +260,35 @@ int launch_gram(const void* M, int m_f32, int64_t m, int64_t d, int64_t ld, void
   if (ldh < 64 * (int64_t)nb) return MIHS_ERR_INVALID;
   const int hn = 64 * (int)nb;
   if (d > 64) {
-    // 128 x 128 tiles: a quarter of the 64 x 64 form's reloads of M
+    // 128 x 128 tiles: a quarter of the 64 x 64 form's reloads of M; 128 x 64
+    // tiles where the 128 x 128 ones on and above the diagonal would leave
+    // CUs idle (d = 2048: 136 tiles, 272 of 128 x 64)
     const unsigned nt = (unsigned)((d + kT - 1) / kT);
-    const dim3 grid(nt, nt);
-    if (m_f32 && h_f32)
-      gram_tile128_kernel<float, float><<<grid, dim3(kBlock), 0, st>>>(
-          (const float*)M, m, ld, (int)d, (float*)H, ldh, hn);
-    else if (m_f32)
-      gram_tile128_kernel<float, double><<<grid, dim3(kBlock), 0, st>>>(
-          (const float*)M, m, ld, (int)d, (double*)H, ldh, hn);
-    else if (h_f32)
-      gram_tile128_kernel<double, float><<<grid, dim3(kBlock), 0, st>>>(
-          (const double*)M, m, ld, (int)d, (float*)H, ldh, hn);
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return MIHS_ERR_HIP;
+    const bool narrow = (int64_t)nt * (nt + 1) / 2 < ncu;
+    auto go = [&](auto tn) {
+      constexpr int TN = decltype(tn)::value;
+      const dim3 grid((unsigned)((d + TN - 1) / TN), nt);
+      if (m_f32 && h_f32)
+        gram_tile128_kernel<float, float, TN><<<grid, dim3(kBlock), 0, st>>>(
+            (const float*)M, m, ld, (int)d, (float*)H, ldh, hn);
+      else if (m_f32)
+        gram_tile128_kernel<float, double, TN><<<grid, dim3(kBlock), 0, st>>>(
+            (const float*)M, m, ld, (int)d, (double*)H, ldh, hn);
+      else if (h_f32)
+        gram_tile128_kernel<double, float, TN><<<grid, dim3(kBlock), 0, st>>>(
+            (const double*)M, m, ld, (int)d, (float*)H, ldh, hn);
+      else
+        gram_tile128_kernel<double, double, TN><<<grid, dim3(kBlock), 0, st>>>(
+            (const double*)M, m, ld, (int)d, (double*)H, ldh, hn);
+    };
+    if (narrow)
+      go(std::integral_constant<int, 64>());
     else
-      gram_tile128_kernel<double, double><<<grid, dim3(kBlock), 0, st>>>(
-          (const double*)M, m, ld, (int)d, (double*)H, ldh, hn);
+      go(std::integral_constant<int, kT>());
     return hipGetLastError() == hipSuccess ? MIHS_OK : MIHS_ERR_HIP;
   }
   const dim3 grid(nb, nb);

@@ -1338,8 +1338,9 @@ int launch_solve(const mihs_handle* h, const SolveDesc& s, void* ws, size_t ws_b
 
 constexpr int kCalCols = 2048;                      // FP64 columns of the timing matrix
 constexpr int64_t kCalRows = (int64_t)1 << 17;      // 2 GiB (> the Infinity Cache)
-constexpr int kCalWarm = 2;                         // untimed passes
-constexpr int kCalPasses = 12;                      // timed passes
+constexpr int kCalWarm = 6;    // untimed passes (the first calibration of a process,
+                               // with 2, sometimes saw a 14% spread instead of 10%)
+constexpr int kCalPasses = 15;  // timed passes; per XCD the median pass counts
 constexpr long kRowWeightStep = 4;                  // weights are multiples of this
 constexpr size_t kCalLds = 96 * 1024;               // keeps one workgroup per CU
 
@@ -1387,8 +1388,7 @@ int calibrate_rows(mihs_handle* h) {
     return MIHS_ERR_HIP;
   }
   std::vector<long long> clk((size_t)2 * G);
-  std::vector<double> tsum(kXcds, 0.0);
-  std::vector<int> cnt(kXcds, 0);
+  std::vector<double> tpass[kXcds];  // per XCD: mean workgroup time of each pass
   if (hipMemset(buf, 0, bytes) != hipSuccess ||
       hipFuncSetAttribute((const void*)xcd_rowpass_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCalLds) != hipSuccess)
@@ -1403,10 +1403,13 @@ int calibrate_rows(mihs_handle* h) {
       break;
     }
     if (pass < kCalWarm) continue;
+    double sum[kXcds] = {0.0};
+    int cnt[kXcds] = {0};
     for (int w = 0; w < G; ++w) {
-      tsum[w % kXcds] += (double)(clk[2 * w + 1] - clk[2 * w]);
+      sum[w % kXcds] += (double)(clk[2 * w + 1] - clk[2 * w]);
       cnt[w % kXcds] += 1;
     }
+    for (int k = 0; k < kXcds; ++k) tpass[k].push_back(sum[k] / (double)cnt[k]);
   }
   (void)hipFree(buf);
   (void)hipSetDevice(prev);
@@ -1419,14 +1422,16 @@ int calibrate_rows(mihs_handle* h) {
   // per solve, 64/56 25.47 ms, equal weights 25.56-25.67 ms.  The steps keep
   // the 1-2% drift of the means between calibrations from moving the split
   // (64/60 with one even XCD at 63 measured 25.36 ms).
-  double tmin = 0.0;
+  double tk[kXcds], tmin = 0.0;
   for (int k = 0; k < kXcds; ++k) {
-    const double t = tsum[k] / (double)cnt[k];
-    if (!(t > 0.0)) return MIHS_ERR_HIP;
-    if (k == 0 || t < tmin) tmin = t;
+    std::vector<double>& v = tpass[k];
+    std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+    tk[k] = v[v.size() / 2];
+    if (!(tk[k] > 0.0)) return MIHS_ERR_HIP;
+    if (k == 0 || tk[k] < tmin) tmin = tk[k];
   }
   for (int k = 0; k < kXcds; ++k) {
-    const double t = tsum[k] / (double)cnt[k];
+    const double t = tk[k];
     const long wk =
         kRowWeightStep * lround((double)(kRowWeightMax / kRowWeightStep) * pow(tmin / t, 0.75));
     h->row_weight[k] = (int32_t)std::min<long>(kRowWeightMax, std::max<long>(kRowWeightMax / 2, wk));

@@ -67,7 +67,7 @@ def parse():
 # plain 1 GiB device copy: x1.99992 for FETCH_SIZE, x1.000 for WRITE_SIZE); see
 # profiles/solve_kernel_srht_2p18x2048.md.  Valid for the kernel as profiled, on
 # the launch of 35 outer / 342 inner iterations.
-MEASURED_TRAFFIC = {("srht_2p18x2048", "mixed"): 151138983817}
+MEASURED_TRAFFIC = {("srht_2p18x2048", "mixed"): 151142182626}
 
 # Stop-rule tolerance per workload: the relative-step rule estimates the error
 # from the Corollary 4 rate sqrt(beta); where the observed rate is slower (the

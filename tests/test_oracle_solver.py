@@ -370,3 +370,40 @@ def test_pd_planted_mistake_is_caught(monkeypatch):
                           0.0, None)
     zs = np.linalg.solve(SA @ SA.T + P.lam * np.eye(40), SA @ c)
     assert not (np.linalg.norm(z - zs) <= 1e-6 * np.linalg.norm(zs))
+
+
+@pytest.mark.parametrize("beta", [0.04, 0.25, 0.5, 0.81])
+def test_stop_threshold_is_exact_for_geometric_convergence(beta):
+    """The relative-step rule (Corollary 4's rate rho = sqrt(beta)): for an iterate
+    sequence x_k = x* + rho^k v converging at exactly that rate,
+    ||x_{k+1} - x*|| = rho / (1 - rho) ||x_{k+1} - x_k||, so the rule stops at the
+    first k whose true relative error is <= tol, never earlier and never later."""
+    rng = np.random.default_rng(7)
+    xs = rng.standard_normal(50)
+    v = rng.standard_normal(50)
+    rho = math.sqrt(beta)
+    tol = 1e-10
+    thr = O.stop_threshold(tol, beta)
+    stop_k, first_ok = None, None
+    for k in range(1, 400):
+        x = xs + rho ** k * v
+        # the differences in closed form (no cancellation against x*)
+        step = np.linalg.norm(rho ** (k - 1) * (rho - 1.0) * v) / np.linalg.norm(x)
+        err = np.linalg.norm(rho ** k * v) / np.linalg.norm(x)
+        # the identity behind the rule
+        assert math.isclose(err, step * rho / (1.0 - rho), rel_tol=1e-9)
+        if stop_k is None and step <= thr:
+            stop_k = k
+        if first_ok is None and err <= tol * (1.0 + 1e-9):
+            first_ok = k
+        if stop_k is not None and first_ok is not None:
+            break
+    assert stop_k == first_ok, (stop_k, first_ok)
+    # a planted mistake (threshold tol * rho, the rate's place swapped) stops
+    # at another iterate whenever rho / (1 - rho) != 1 / rho
+    wrong = tol * rho
+    if abs(rho / (1.0 - rho) - 1.0 / rho) > 0.05:
+        stop_w = next(k for k in range(1, 400)
+                      if np.linalg.norm(rho ** (k - 1) * (rho - 1.0) * v)
+                      / np.linalg.norm(xs + rho ** k * v) <= wrong)
+        assert stop_w != first_ok

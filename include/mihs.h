@@ -132,7 +132,10 @@ int mihs_destroy(mihs_handle_t handle);
  *   MIHS_ERR_HIP (weights unchanged) when the buffer cannot be allocated or a
  *   HIP call fails.  The Python binding calls it once per handle.
  * mihs_set_row_weights  sets the 8 weights, each in [1, 64]; NULL restores
- *   equal weights.  MIHS_ERR_INVALID for a weight out of range.
+ *   equal weights.  MIHS_ERR_INVALID for a weight out of range.  Solves read the
+ *   weights when they are enqueued; changing them while another thread enqueues
+ *   a solve on the same handle is not synchronised (any mix of old and new
+ *   weights still gives a valid split).
  * mihs_get_row_weights  copies the handle's 8 weights to weights.
  * mihs_row_split        host only: bounds[0..G] of the split above for n rows
  *   over G workgroups (bounds[0] = 0, bounds[G] = n); MIHS_ERR_INVALID for

@@ -269,7 +269,10 @@ __global__ __launch_bounds__(kBlock) void srht_stage2(const TY* __restrict__ Y, 
 // so that after all blocks acc_k = ((H D A)[idx_k]) restricted to the strip.
 // Thread (c, g), c = t % 16, g = t / 16, owns column c of samples
 // g * NACC .. g * NACC + NACC - 1 in registers.  The next block's rows are
-// loaded while the current one is transformed and accumulated.  The partial
+// loaded while the current one is transformed and accumulated.  Each sample's
+// row offset in T and block index k_hi share one 32-bit word in LDS (one read
+// per sample and block; with two, the FP32 form used 236 VGPRs and the FP64
+// form spilled, against 204 and 210 now).  The partial
 // sums of the workgroup's block range go to P[part] (or, with one range per
 // strip, scaled straight to SA).
 // ---------------------------------------------------------------------------
@@ -305,8 +308,9 @@ __global__ __launch_bounds__(kFusedThreads) void srht_fused_kernel(
   static_assert(R == 16 || R == 32, "block shape");
   extern __shared__ unsigned char smem_raw[];
   TY* T = (TY*)smem_raw;                                   // B x kFusedLdt
-  int* s_off = (int*)(T + (size_t)B * kFusedLdt);          // 32 * NACC sample row offsets
-  int* s_khi = s_off + 32 * NACC;                          // 32 * NACC sample k_hi
+  // per sample: its row offset in T (low 16 bits) and k_hi (high 16 bits), one
+  // LDS read per sample and block
+  uint32_t* s_smp = (uint32_t*)(T + (size_t)B * kFusedLdt);  // 32 * NACC
   const int t = threadIdx.x;
   const int c = t % kFusedW, g = t / kFusedW;              // g in [0, 32)
   const int strip = blockIdx.x % (int)((d + kFusedW - 1) / kFusedW);
@@ -317,8 +321,8 @@ __global__ __launch_bounds__(kFusedThreads) void srht_fused_kernel(
 
   for (int k = t; k < 32 * NACC; k += kFusedThreads) {
     const int v = k < m ? idx[k] : 0;
-    s_off[k] = (v & (B - 1)) * kFusedLdt;
-    s_khi[k] = k < m ? (v >> LOGB) : 0;
+    const uint32_t khi = k < m ? (uint32_t)(v >> LOGB) : 0u;
+    s_smp[k] = (uint32_t)((v & (B - 1)) * kFusedLdt) | (khi << 16);
   }
   TY acc[NACC];
 #pragma unroll
@@ -357,11 +361,12 @@ __global__ __launch_bounds__(kFusedThreads) void srht_fused_kernel(
       const bool neg = (sw[i] >> g) & 1u;
       x[i] = neg ? -(TY)xa[i] : (TY)xa[i];
     }
+    // the next block's rows as soon as this block's are in x
+    if (b + 1 < b1) load_block(b + 1);
     fwht_regs<TY, R>(x);
     __syncthreads();  // the previous block's accumulation has read T
 #pragma unroll
     for (int i = 0; i < R; ++i) T[(g + 32 * i) * kFusedLdt + c] = x[i];
-    if (b + 1 < b1) load_block(b + 1);
     __syncthreads();
     // phase 2: the butterflies of row bits 0 .. log2(R)-1 on rows R g + i
     {
@@ -394,8 +399,9 @@ __global__ __launch_bounds__(kFusedThreads) void srht_fused_kernel(
 #pragma unroll
       for (int j = j0; j < j0 + 8; ++j) {
         const int k = g * NACC + j;
-        const TY v = Tc[s_off[k]];
-        const bool neg = (__popc((uint32_t)s_khi[k] & bb) & 1) != 0;
+        const uint32_t smp = s_smp[k];
+        const TY v = Tc[smp & 0xFFFFu];
+        const bool neg = (__popc((smp >> 16) & bb) & 1) != 0;
         acc[j] += neg ? -v : v;
       }
     }
@@ -1011,6 +1017,8 @@ SrhtFusedPlan srht_fused_plan(const mihs_handle* h, int64_t n, int64_t d, int64_
   SrhtFusedPlan F;
   F.logb = ty_bytes == 4 ? 10 : 9;
   if (n < (1LL << F.logb) || (n & (n - 1)) != 0 || m > 2048 || m < 1) return F;
+  // a sample's block index k_hi is kept in 16 bits
+  if ((n >> F.logb) > 65536) return F;
   F.ok = true;
   F.nacc = m <= 512 ? 16 : (m <= 1024 ? 32 : 64);
   F.nblk = n >> F.logb;
@@ -1022,7 +1030,7 @@ SrhtFusedPlan srht_fused_plan(const mihs_handle* h, int64_t n, int64_t d, int64_
   F.idx_bytes = align_up((size_t)m * 4, 256);
   F.sign_bytes = align_up((size_t)(n / 32) * 4, 256);
   F.part_bytes = F.nparts > 1 ? align_up((size_t)F.nparts * m * d * ty_bytes, 256) : 0;
-  F.lds = (size_t)(1 << F.logb) * kFusedLdt * ty_bytes + 2 * 32 * (size_t)F.nacc * 4;
+  F.lds = (size_t)(1 << F.logb) * kFusedLdt * ty_bytes + 32 * (size_t)F.nacc * 4;
   return F;
 }
 

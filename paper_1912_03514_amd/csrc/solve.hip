@@ -393,11 +393,14 @@ __device__ __forceinline__ void rowdots_r(const TH* __restrict__ H, int64_t ldh,
 }
 
 // Rows per wave: up to 512 bytes per lane in flight (at most 4 rows), halved
-// when the workgroup owns too few rows to give every wave a full set.
+// when the workgroup owns too few rows to give every wave a full set.  Rows of
+// 4096 entries keep one row in flight: a second FP32 row spilled the solve
+// kernel's registers to scratch (89 VGPRs), which cost more than the extra
+// round trip saves.
 template <typename TH, typename TV, int EPT>
 __device__ __forceinline__ void rowdots(const TH* __restrict__ H, int64_t ldh, int r0, int r1,
                                         int d, const TV* __restrict__ v, double* out) {
-  constexpr int RB = 512 / (EPT * (int)sizeof(TH));
+  constexpr int RB = (EPT >= 64 ? 256 : 512) / (EPT * (int)sizeof(TH));
   constexpr int R = RB < 1 ? 1 : (RB > 4 ? 4 : RB);
   if constexpr (R > 1) {
     if (r1 - r0 <= kWavesPerBlock * (R / 2)) {

@@ -71,6 +71,24 @@ def test_srht_full_size_whole_rows(prec):
         assert np.all(err <= 4 * math.log2(n) * u * colsum), (k, float(err.max()))
 
 
+@pytest.mark.parametrize("prec", ["plain", "mixed"])
+def test_srht_two_stage_above_2048_samples(prec):
+    """More than 2048 sampled rows (ragged m = 3000) take the two-stage form: the
+    blocked transform H D A over 512-row blocks written out, then the sampled
+    rows combined across blocks.  Every entry is within a few rounding errors of
+    the oracle's transform (log2(n) levels, in FP64 or FP32)."""
+    mihs = _mihs()
+    n, d, m = 1 << 14, 40, 3000
+    A = _rand(n, d, 19)
+    ref = sketches.srht_sketch(A, m, 23)
+    announce(f"srht two-stage n={n} d={d} m={m} ({prec})")
+    SA = mihs.mihs_sketch(to_dev(A), "srht", m, 23, precision=prec).double().cpu().numpy()
+    assert SA.shape == (m, d)
+    u = 2.0 ** -52 if prec == "plain" else 2.0 ** -23
+    bound = 4 * math.log2(n) * u * np.abs(A).sum(axis=0).max() / math.sqrt(m)
+    assert np.max(np.abs(SA - ref)) <= bound
+
+
 @pytest.mark.parametrize("adt", [np.float64, np.float32])
 def test_srht_mixed(adt):
     mihs = _mihs()

@@ -76,25 +76,27 @@ def test_shapes_plain(n, d):
     assert rel(x.cpu().numpy(), xs) <= 1e-10
 
 
-def test_gram_path_with_rows_wider_than_2048():
-    """d in (2048, 4096] with m >= d: the gradient pass splits rows into quarters
-    and the inner CG applies the Gram matrix with 64 entries of a row per lane
-    (FP64 H, or FP32 H in mixed precision); ragged d, 12 rows of H per CG
-    workgroup.  Both precisions reach the closed form to 1e-10."""
+def test_operator_paths_with_rows_wider_than_2048():
+    """d in (2048, 4096]: the gradient pass splits rows into quarters and the inner
+    CG works on 64 entries of a row per lane, through the Gram matrix (m >= d:
+    FP64 H, or FP32 H in mixed precision; 12 rows of H per CG workgroup) or by
+    streaming SA (m < d, FP64 or FP32 rows); ragged d.  Every form reaches the
+    closed form to 1e-10."""
     mihs = _mihs()
-    n, d, m = 8000, 3001, 3200
+    n, d = 8000, 3001
     sd = d / 5
     P = _problem(n, d, sd, seed=77)
-    SA = sketches.countsketch(P.A, m, 5)
-    a, b = O.momentum_cor4(sd, m)
     xs = O.ridge_lstsq(P.A, P.b, P.lam)
-    for prec, sa, eps in (("plain", SA, 1e-3), ("mixed", SA.astype(np.float32), 1e-2)):
-        announce(f"gram path n={n} d={d} m={m} {prec}")
-        x, info = mihs.mihs_solve(to_dev(P.A), to_dev(P.b), P.lam, to_dev(sa), a, b,
-                                  eps_sub=eps, tol=1e-11, max_outer=400, max_inner=4000,
-                                  precision=prec)
-        assert info["status"] == 0, (prec, info)
-        assert rel(x.cpu().numpy(), xs) <= 1e-10, prec
+    for m in (3200, 2400):
+        SA = sketches.countsketch(P.A, m, 5)
+        a, b = O.momentum_cor4(sd, m)
+        for prec, sa, eps in (("plain", SA, 1e-3), ("mixed", SA.astype(np.float32), 1e-2)):
+            announce(f"wide rows n={n} d={d} m={m} {prec}")
+            x, info = mihs.mihs_solve(to_dev(P.A), to_dev(P.b), P.lam, to_dev(sa), a, b,
+                                      eps_sub=eps, tol=1e-11, max_outer=400, max_inner=4000,
+                                      precision=prec)
+            assert info["status"] == 0, (m, prec, info)
+            assert rel(x.cpu().numpy(), xs) <= 1e-10, (m, prec)
 
 
 def test_fp32_matrix_and_mixed_inner():

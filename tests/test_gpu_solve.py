@@ -80,8 +80,8 @@ def test_operator_paths_with_rows_wider_than_2048():
     """d in (2048, 4096]: the gradient pass splits rows into quarters and the inner
     CG works on 64 entries of a row per lane, through the Gram matrix (m >= d:
     FP64 H, or FP32 H in mixed precision; 12 rows of H per CG workgroup) or by
-    streaming SA (m < d, FP64 or FP32 rows); ragged d.  Every form reaches the
-    closed form to 1e-10."""
+    streaming SA (m < d, FP64 or FP32 rows, and AAb_Solver); ragged d.  Every
+    form reaches the closed form to 1e-10."""
     mihs = _mihs()
     n, d = 8000, 3001
     sd = d / 5
@@ -97,6 +97,12 @@ def test_operator_paths_with_rows_wider_than_2048():
                                       precision=prec)
             assert info["status"] == 0, (m, prec, info)
             assert rel(x.cpu().numpy(), xs) <= 1e-10, (m, prec)
+    # AAb_Solver as the inner solver on the same rows (the paper's eps_sub = 0.1)
+    announce(f"wide rows n={n} d={d} m=2400 aab")
+    x, info = mihs.mihs_solve(to_dev(P.A), to_dev(P.b), P.lam, to_dev(SA), a, b, eps_sub=0.1,
+                              tol=1e-11, max_outer=400, max_inner=4000, inner="aab")
+    assert info["status"] == 0, info
+    assert rel(x.cpu().numpy(), xs) <= 1e-10
 
 
 def test_fp32_matrix_and_mixed_inner():
